@@ -1,0 +1,174 @@
+"""Python access to the FP64 CPU oracle (liborc.so, built from orc.c).
+
+TEST INFRASTRUCTURE.  Only tests, the smoke check and the CPU-baseline leg
+of the benchmark import this package; the library package never does.
+
+All arrays are NumPy complex128 in the canonical layout:
+  links (4, V, 3, 3) [mu][lex][row][col], vectors (V/2, 3) [eo][colour],
+  full-lattice vectors (V, 3) [lex][colour].
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liborc.so")
+SOURCES = ("orc.c", "orc_net.c")
+
+_c = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+
+
+def compile_sources(srcs, out_path):
+    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", out_path]
+    subprocess.run(cmd + list(srcs) + ["-lm"], check=True)
+    return out_path
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle sources into liborc.so with gcc + OpenMP."""
+    srcs = [os.path.join(_HERE, f) for f in SOURCES if os.path.exists(os.path.join(_HERE, f))]
+    if force or not os.path.exists(_LIB_PATH):
+        compile_sources(srcs, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _bind(L):
+    L.orc_dhop_full.argtypes = [_c, _i, _c, _c, _c]
+    L.orc_dslash_eo.argtypes = [_c, _i, _c, _i, _c, _c]
+    L.orc_normal_op.argtypes = [_c, _i, _c, _d, _d, _c, _c]
+    L.orc_tables.argtypes = [_c, _i, _c, _c, _c]
+    L.orc_true_residual.argtypes = [_c, _i, _c, _d, _d, _c, _c]
+    L.orc_true_residual.restype = _d
+    L.orc_cg.argtypes = [_c, _i, _c, _d, _d, _c, _c, _d, _i, _c, _c, _c]
+    L.orc_multishift_cg.argtypes = [_c, _i, _c, _d, _i, _c, _c, _c, _d, _i,
+                                    _c, _c, _c, _c]
+    for f in (L.orc_dhop_full, L.orc_dslash_eo, L.orc_normal_op, L.orc_tables,
+              L.orc_cg, L.orc_multishift_cg):
+        f.restype = _i
+    return L
+
+
+def _dims(dims):
+    return (ctypes.c_int * 4)(*[int(d) for d in dims])
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _cplx(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise ValueError(f"{what}: oracle returned {rc}")
+    return rc
+
+
+class Oracle:
+    """The oracle's entry points bound to one build of the library."""
+
+    def __init__(self, L):
+        self.L = L
+
+    def dhop_full(self, dims, links, vec, antiperiodic_t=True):
+        links, vec = _cplx(links), _cplx(vec)
+        out = np.empty_like(vec)
+        _check(self.L.orc_dhop_full(_dims(dims), int(antiperiodic_t), _p(links), _p(vec),
+                                    _p(out)), "dhop_full")
+        return out
+
+    def dslash_eo(self, dims, links, out_parity, vec, antiperiodic_t=True):
+        links, vec = _cplx(links), _cplx(vec)
+        out = np.empty_like(vec)
+        _check(self.L.orc_dslash_eo(_dims(dims), int(antiperiodic_t), _p(links),
+                                    int(out_parity), _p(vec), _p(out)), "dslash_eo")
+        return out
+
+    def normal_op(self, dims, links, mass, shift, vec, antiperiodic_t=True):
+        links, vec = _cplx(links), _cplx(vec)
+        out = np.empty_like(vec)
+        _check(self.L.orc_normal_op(_dims(dims), int(antiperiodic_t), _p(links), float(mass),
+                                    float(shift), _p(vec), _p(out)), "normal_op")
+        return out
+
+    def tables(self, dims, antiperiodic_t=True):
+        """(nbr [2,8,V/2], coord [2,V/2,4], sign [2,8,V/2]) as int32."""
+        vh = int(np.prod(dims)) // 2
+        nbr = np.zeros((2, 8, vh), np.int32)
+        coord = np.zeros((2, vh, 4), np.int32)
+        sign = np.zeros((2, 8, vh), np.int32)
+        _check(self.L.orc_tables(_dims(dims), int(antiperiodic_t), _p(nbr), _p(coord),
+                                 _p(sign)), "tables")
+        return nbr, coord, sign
+
+    def true_residual(self, dims, links, mass, shift, b, x, antiperiodic_t=True):
+        links, b, x = _cplx(links), _cplx(b), _cplx(x)
+        return self.L.orc_true_residual(_dims(dims), int(antiperiodic_t), _p(links),
+                                        float(mass), float(shift), _p(b), _p(x))
+
+    def cg(self, dims, links, mass, shift, b, x0=None, tol=1e-10, max_iter=10000,
+           antiperiodic_t=True):
+        """Single-shift CG from x0 (zero if None). Returns (x, status, info)."""
+        links, b = _cplx(links), _cplx(b)
+        x = np.zeros_like(b) if x0 is None else _cplx(x0).copy()
+        it = ctypes.c_int(0)
+        ri, rt = ctypes.c_double(0), ctypes.c_double(0)
+        rc = _check(self.L.orc_cg(_dims(dims), int(antiperiodic_t), _p(links), float(mass),
+                                  float(shift), _p(b), _p(x), float(tol), int(max_iter),
+                                  ctypes.byref(it), ctypes.byref(ri), ctypes.byref(rt)), "cg")
+        return x, rc, dict(iters=it.value, resid_iter=ri.value, resid_true=rt.value)
+
+    def multishift_cg(self, dims, links, mass, shifts, b, tol=1e-10, max_iter=100000,
+                      antiperiodic_t=True):
+        """Returns (x [n, V/2, 3], status, info)."""
+        links, b = _cplx(links), _cplx(b)
+        shifts = np.ascontiguousarray(shifts, dtype=np.float64)
+        n = shifts.size
+        x = np.zeros((n,) + b.shape, np.complex128)
+        it = ctypes.c_int(0)
+        its = np.zeros(n, np.int32)
+        ri = np.zeros(n)
+        rt = np.zeros(n)
+        rc = _check(self.L.orc_multishift_cg(_dims(dims), int(antiperiodic_t), _p(links),
+                                             float(mass), n, _p(shifts), _p(b), _p(x),
+                                             float(tol), int(max_iter), ctypes.byref(it),
+                                             _p(its), _p(ri), _p(rt)), "multishift_cg")
+        return x, rc, dict(iters=it.value, iters_shift=its, resid_iter=ri, resid_true=rt)
+
+
+_default = None
+
+
+def default() -> Oracle:
+    global _default
+    if _default is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        _default = Oracle(_bind(ctypes.CDLL(_LIB_PATH)))
+    return _default
+
+
+def lib():
+    return default().L
+
+
+def load(path) -> Oracle:
+    """An Oracle bound to the library at `path` (used to test the pins
+    against deliberately broken builds of the oracle source)."""
+    return Oracle(_bind(ctypes.CDLL(path)))
+
+
+def __getattr__(name):
+    # module-level access (oracle.dslash_eo(...)) goes to the default build
+    if name in ("dhop_full", "dslash_eo", "normal_op", "tables", "true_residual", "cg",
+                "multishift_cg"):
+        return getattr(default(), name)
+    raise AttributeError(name)
