@@ -1,0 +1,179 @@
+/*
+ * stag.h -- C ABI of the MI355X (gfx950) even/odd staggered solver library.
+ *
+ * The library solves the problem the paper states (Bonati, Cossu, D'Elia,
+ * Di Giacomo, "Staggered fermions simulations on GPUs", Lattice 2010):
+ * unimproved staggered fermions with even/odd preconditioning (Section 2),
+ * inverted with CG and with the Krylov solver for shifted systems whose
+ * start vector must be zero (Section 6), in double precision for the
+ * Metropolis inversions and single precision elsewhere (Section 4).
+ *
+ * Operator (textbook Kogut-Susskind form; the paper prints no formula):
+ *   (D psi)(x) = 1/2 sum_mu eta_mu(x) [ s_mu(x) U_mu(x) psi(x+mu)
+ *                                      - s_mu(x-mu) U_mu(x-mu)^dag psi(x-mu) ]
+ *   eta_mu(x) = (-1)^(x0+...+x_{mu-1}); s_mu(x) = -1 on the time links from
+ *   x3 = L3-1 to x3 = 0 when the time direction is antiperiodic, else +1.
+ *   D_eo = D from odd to even sites, D_oe from even to odd sites.
+ *   M = m^2 - D_eo D_oe on even sites (Hermitian positive definite).
+ *
+ * Geometry: dims = (L0,L1,L2,L3) = (x,y,z,t), every L_mu even and >= 2.
+ *   lex(x) = x0 + L0*(x1 + L1*(x2 + L2*x3)), parity = (x0+x1+x2+x3) mod 2,
+ *   eo(x) = lex(x) >> 1 indexes the V/2 sites of one parity.
+ *
+ * Layouts.
+ *   Canonical links : complex128 (4, V, 3, 3) [mu][lex][row][col].
+ *   Canonical vector: complex128 (V/2, 3) [eo][colour].
+ *   Library vector  : structure of arrays [colour][eo] of complex numbers,
+ *                     i.e. 3 planes of V/2 {re,im} pairs; double2 planes for
+ *                     STAG_F64 (48*V/2 bytes), float2 planes for STAG_F32
+ *                     (24*V/2 bytes).  stag_vec_pack/unpack convert.
+ *   Packed links live inside the lattice handle (see stag_links_set).
+ *
+ * Pointers: every field pointer is a DEVICE pointer unless marked host.
+ * The caller owns every buffer it passes; the library owns only the lattice
+ * handle and the work buffers it allocates inside it.
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls
+ * are ordered on that stream; stag_dslash_eo, stag_normal_op, stag_vec_*,
+ * stag_tables and stag_links_set are asynchronous, the solvers return after
+ * the stream has finished their work.  One handle must not be used from two
+ * streams (or host threads) at once.
+ * Errors: no C++ exception crosses this boundary.  Every call returns a
+ * stag_status; stag_last_error() gives a message for the calling thread.
+ */
+#ifndef STAG_H
+#define STAG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    STAG_OK = 0,
+    STAG_ENOCONV = 1,     /* max_iter reached; best iterate and stats returned */
+    STAG_EBREAKDOWN = 2,  /* non-positive or non-finite curvature <p, A p> */
+    STAG_EINVAL = -1,     /* invalid argument (see each call) */
+    STAG_ENOMEM = -2,     /* device allocation failed */
+    STAG_EHIP = -3        /* a HIP runtime call failed */
+} stag_status;
+
+typedef enum {
+    STAG_F64 = 0,    /* double precision vectors and links */
+    STAG_F32 = 1,    /* single precision vectors and links, double reductions */
+    STAG_MIXED = 2   /* solvers only: single precision iterations with double
+                        precision reliable updates and per-shift refinement */
+} stag_prec;
+
+typedef enum {
+    STAG_LINK18 = 0, /* all 9 complex entries of each link */
+    STAG_LINK12 = 1  /* first two rows; third rebuilt as conj(row0 x row1)
+                        (Section 5, 12-real representation); needs SU(3) links */
+} stag_link_fmt;
+
+#define STAG_MAX_SHIFTS 64
+
+typedef struct stag_lattice stag_lattice;
+
+/* Solver statistics (host struct). */
+typedef struct {
+    int iters;                              /* Krylov iterations (multi-shift or CG) */
+    int n_reliable;                         /* double precision reliable updates */
+    int refine_iters;                       /* iterations of the per-shift refinement */
+    int fallback_used;                      /* learned preconditioner abandoned */
+    int iters_shift[STAG_MAX_SHIFTS];       /* iteration at which shift i froze */
+    double resid_iter[STAG_MAX_SHIFTS];     /* iterated |zeta_i| ||r|| / ||b|| at freeze */
+    double resid_true[STAG_MAX_SHIFTS];     /* FP64 ||b - (M+sigma_i) x_i|| / ||b|| at exit */
+    double resid_unrefined[STAG_MAX_SHIFTS];/* STAG_MIXED: FP64 true residual before refinement */
+    double seconds;                         /* wall time of the call */
+} stag_cg_stats;
+
+/* Create a lattice handle for dims[4] (host array).  antiperiodic_t != 0
+ * selects the antiperiodic fermion boundary in time.  Every L_mu must be
+ * even, >= 2, and V/2 < 2^30.  STAG_EINVAL otherwise.  Uses the current
+ * HIP device; the handle is tied to it. */
+stag_status stag_lattice_create(const int dims[4], int antiperiodic_t, stag_lattice **out);
+
+/* Free the handle and every device buffer it owns.  NULL is allowed. */
+stag_status stag_lattice_destroy(stag_lattice *lat);
+
+/* Number of sites of one parity, V/2 (0 for a NULL handle). */
+int64_t stag_half_volume(const stag_lattice *lat);
+
+/* Pack a gauge field into the handle.  links: device, canonical complex128
+ * (4,V,3,3).  Both a double and a single precision copy are stored in the
+ * even/odd structure-of-arrays layout (element-major, site index fastest;
+ * Section 5 and its Figure 2), keeping all 9 entries or the first two rows
+ * (fmt).  Links must be SU(3) for STAG_LINK12.  Replaces earlier links. */
+stag_status stag_links_set(stag_lattice *lat, const void *links, stag_link_fmt fmt, void *stream);
+
+/* Test hook: write the geometry tables computed by the same device index
+ * functions the operator kernels use.  All int32 device arrays:
+ *   nbr  [2][8][V/2]: eo index of neighbour d of site (parity, eo);
+ *                     d = 0..3 forward x+mu, d = 4..7 backward x-mu.
+ *   coord[2][V/2][4]: coordinates.
+ *   sign [2][8][V/2]: eta_mu(x) s_mu(x) (forward) / eta_mu(x) s_mu(x-mu)
+ *                     (backward), excluding the 1/2 and the backward minus.
+ * Any of the three may be NULL. */
+stag_status stag_tables(const stag_lattice *lat, int32_t *nbr, int32_t *coord, int32_t *sign,
+                        void *stream);
+
+/* Canonical complex128 (V/2,3) vector <-> library vector of precision prec
+ * (STAG_F64 or STAG_F32; F32 rounds to nearest). */
+stag_status stag_vec_pack(const stag_lattice *lat, const void *canonical, void *vec, stag_prec prec,
+                          void *stream);
+stag_status stag_vec_unpack(const stag_lattice *lat, const void *vec, void *canonical, stag_prec prec,
+                            void *stream);
+
+/* Half hopping term.  out_parity = 0: out = D_eo in (odd -> even);
+ * out_parity = 1: out = D_oe in (even -> odd).  in and out are library
+ * vectors of precision prec (STAG_F64 or STAG_F32, using the matching link
+ * copy); they must not overlap.  Asynchronous. */
+stag_status stag_dslash_eo(const stag_lattice *lat, int out_parity, const void *in, void *out,
+                           stag_prec prec, void *stream);
+
+/* out = (m^2 + shift) in - D_eo D_oe in on even sites; library vectors of
+ * precision prec, no overlap.  Uses a work vector inside the handle.
+ * mass > 0, shift >= 0.  Asynchronous. */
+stag_status stag_normal_op(stag_lattice *lat, double mass, double shift, const void *in, void *out,
+                           stag_prec prec, void *stream);
+
+/* Multi-shift CG (Section 6; Jegerlehner's method): solve
+ *   (M + shifts[i]) x_i = src,  i = 0..n_shifts-1,
+ * from x_i = 0 (the shifted solver needs the zero start: sols are outputs
+ * only).  src and every sols[i] are STAG_F64 library vectors; shifts and
+ * sols are HOST arrays (sols holds device pointers).  Shift i stops when
+ * its iterated residual |zeta_i| ||r|| <= tol ||src||; the FP64 true
+ * residual of every shift is computed at the end.
+ *   prec = STAG_F64   : all double precision.
+ *   prec = STAG_F32   : single precision vectors and links with double
+ *                       reductions and recursion (reaches only the single
+ *                       precision floor, Section 6).
+ *   prec = STAG_MIXED : single precision iterations, double precision
+ *                       reliable updates of the base residual every 100
+ *                       iterations, then a mixed CG refinement of every shift
+ *                       whose true residual exceeds tol.
+ * Requires mass > 0, shifts >= 0, tol > 0, 1 <= n_shifts <= 64, links set.
+ * ||src|| = 0 gives zero solutions and 0 iterations.  Returns STAG_ENOCONV
+ * after max_iter iterations (stats filled), STAG_EBREAKDOWN on a
+ * non-positive curvature.  stats may be NULL. */
+stag_status stag_multishift_cg(stag_lattice *lat, double mass, const double *shifts, int n_shifts,
+                               const void *src, void *const *sols, double tol, int max_iter,
+                               stag_prec prec, stag_cg_stats *stats, void *stream);
+
+/* Single-shift CG for (M + shift) x = src starting from the x passed in
+ * (STAG_F64 library vectors; x is read and overwritten).  Stops when the
+ * FP64 true residual is <= tol ||src||.  prec = STAG_F64, or STAG_MIXED for
+ * single precision iterations with double precision reliable updates. */
+stag_status stag_cg(stag_lattice *lat, double mass, double shift, const void *src, void *x,
+                    double tol, int max_iter, stag_prec prec, stag_cg_stats *stats, void *stream);
+
+/* Message of a status code, and the last error message of this thread. */
+const char *stag_status_string(stag_status s);
+const char *stag_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STAG_H */

@@ -1,0 +1,153 @@
+"""Python binding of libstag.so, the MI355X even/odd staggered solver library.
+
+A thin ctypes layer over the C ABI in include/stag.h: it passes device
+pointers from torch tensors and the current HIP stream, and converts status
+codes.  Every step of the computation runs in the library's HIP kernels;
+there is no Python or CPU fallback -- importing fails loudly when the built
+library is missing.
+
+Library vectors are torch tensors of shape (3, V/2, 2) (colour plane, site,
+re/im), float64 for STAG_F64 and float32 for STAG_F32.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+from ._abi import (F32, F64, MIXED, LINK12, LINK18, CgStats, StagError, load_library,
+                   status_name)
+
+__all__ = ["Lattice", "CgStats", "StagError", "F64", "F32", "MIXED", "LINK18", "LINK12",
+           "library_path", "vec_empty"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libstag.so")
+
+
+_L = load_library(library_path())
+
+_PREC = {"f64": F64, "f32": F32, "mixed": MIXED, F64: F64, F32: F32, MIXED: MIXED}
+_FMT = {"18": LINK18, "12": LINK12, 18: LINK18, 12: LINK12, LINK18: LINK18, LINK12: LINK12}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(rc: int, what: str):
+    if rc < 0:
+        raise StagError(rc, f"{what}: {status_name(rc)}: {_L.stag_last_error().decode()}")
+    return rc
+
+
+def vec_empty(vh: int, prec="f64", device="cuda") -> torch.Tensor:
+    dt = torch.float64 if _PREC[prec] == F64 else torch.float32
+    return torch.empty((3, vh, 2), dtype=dt, device=device)
+
+
+class Lattice:
+    """A lattice handle: geometry, packed links and solver work buffers."""
+
+    def __init__(self, dims, antiperiodic_t: bool = True):
+        self.dims = tuple(int(d) for d in dims)
+        self.V = 1
+        for d in self.dims:
+            self.V *= d
+        self.Vh = self.V // 2
+        h = ctypes.c_void_p()
+        _check(_L.stag_lattice_create((ctypes.c_int * 4)(*self.dims), int(antiperiodic_t),
+                                      ctypes.byref(h)), "stag_lattice_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _L.stag_lattice_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- set-up
+    def set_links(self, links: torch.Tensor, fmt="18"):
+        """links: complex128 device tensor (4, V, 3, 3), canonical layout."""
+        if links.dtype != torch.complex128 or tuple(links.shape) != (4, self.V, 3, 3):
+            raise ValueError("links must be complex128 of shape (4, V, 3, 3)")
+        _check(_L.stag_links_set(self._h, _ptr(links), _FMT[fmt], _stream()), "stag_links_set")
+
+    def tables(self):
+        nbr = torch.empty((2, 8, self.Vh), dtype=torch.int32, device="cuda")
+        coord = torch.empty((2, self.Vh, 4), dtype=torch.int32, device="cuda")
+        sign = torch.empty((2, 8, self.Vh), dtype=torch.int32, device="cuda")
+        _check(_L.stag_tables(self._h, _ptr(nbr), _ptr(coord), _ptr(sign), _stream()), "stag_tables")
+        return nbr, coord, sign
+
+    def pack(self, canonical: torch.Tensor, prec="f64", out=None) -> torch.Tensor:
+        """complex128 (V/2, 3) device tensor -> library vector."""
+        if canonical.dtype != torch.complex128 or tuple(canonical.shape) != (self.Vh, 3):
+            raise ValueError("canonical vector must be complex128 of shape (V/2, 3)")
+        out = vec_empty(self.Vh, prec) if out is None else out
+        _check(_L.stag_vec_pack(self._h, _ptr(canonical), _ptr(out), _PREC[prec], _stream()),
+               "stag_vec_pack")
+        return out
+
+    def unpack(self, vec: torch.Tensor, prec=None) -> torch.Tensor:
+        prec = prec if prec is not None else ("f64" if vec.dtype == torch.float64 else "f32")
+        out = torch.empty((self.Vh, 3), dtype=torch.complex128, device="cuda")
+        _check(_L.stag_vec_unpack(self._h, _ptr(vec), _ptr(out), _PREC[prec], _stream()),
+               "stag_vec_unpack")
+        return out
+
+    # ---------------------------------------------------------------- operator
+    def dslash_eo(self, out_parity: int, vec: torch.Tensor, out=None) -> torch.Tensor:
+        prec = "f64" if vec.dtype == torch.float64 else "f32"
+        out = torch.empty_like(vec) if out is None else out
+        _check(_L.stag_dslash_eo(self._h, int(out_parity), _ptr(vec), _ptr(out), _PREC[prec],
+                                 _stream()), "stag_dslash_eo")
+        return out
+
+    def normal_op(self, mass: float, shift: float, vec: torch.Tensor, out=None) -> torch.Tensor:
+        prec = "f64" if vec.dtype == torch.float64 else "f32"
+        out = torch.empty_like(vec) if out is None else out
+        _check(_L.stag_normal_op(self._h, float(mass), float(shift), _ptr(vec), _ptr(out),
+                                 _PREC[prec], _stream()), "stag_normal_op")
+        return out
+
+    # ---------------------------------------------------------------- solvers
+    def multishift_cg(self, mass, shifts, src: torch.Tensor, sols=None, tol=1e-10,
+                      max_iter=100000, prec="f64"):
+        """Solve (M + shifts[i]) x_i = src.  Returns (sols, status, stats)."""
+        shifts = [float(s) for s in shifts]
+        n = len(shifts)
+        if sols is None:
+            sols = [torch.empty_like(src) for _ in range(n)]
+        arr = (ctypes.c_double * n)(*shifts)
+        ptrs = (ctypes.c_void_p * n)(*[_ptr(x).value for x in sols])
+        st = CgStats()
+        rc = _check(_L.stag_multishift_cg(self._h, float(mass), arr, n, _ptr(src), ptrs, float(tol),
+                                          int(max_iter), _PREC[prec], ctypes.byref(st), _stream()),
+                    "stag_multishift_cg")
+        return sols, rc, st.to_dict(n)
+
+    def cg(self, mass, shift, src: torch.Tensor, x: torch.Tensor, tol=1e-10, max_iter=100000,
+           prec="f64"):
+        """Single-shift CG for (M + shift) x = src from the given x (overwritten)."""
+        st = CgStats()
+        rc = _check(_L.stag_cg(self._h, float(mass), float(shift), _ptr(src), _ptr(x), float(tol),
+                               int(max_iter), _PREC[prec], ctypes.byref(st), _stream()), "stag_cg")
+        return x, rc, st.to_dict(1)

@@ -1,0 +1,80 @@
+"""ctypes declarations of the C ABI (include/stag.h).  Importable without a
+GPU: loading the shared library and resolving its symbols needs no device."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+STAG_OK, STAG_ENOCONV, STAG_EBREAKDOWN = 0, 1, 2
+STAG_EINVAL, STAG_ENOMEM, STAG_EHIP = -1, -2, -3
+F64, F32, MIXED = 0, 1, 2
+LINK18, LINK12 = 0, 1
+MAX_SHIFTS = 64
+
+_NAMES = {0: "STAG_OK", 1: "STAG_ENOCONV", 2: "STAG_EBREAKDOWN", -1: "STAG_EINVAL",
+          -2: "STAG_ENOMEM", -3: "STAG_EHIP"}
+
+
+def status_name(rc: int) -> str:
+    return _NAMES.get(rc, f"status {rc}")
+
+
+class StagError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class CgStats(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int),
+        ("n_reliable", ctypes.c_int),
+        ("refine_iters", ctypes.c_int),
+        ("fallback_used", ctypes.c_int),
+        ("iters_shift", ctypes.c_int * MAX_SHIFTS),
+        ("resid_iter", ctypes.c_double * MAX_SHIFTS),
+        ("resid_true", ctypes.c_double * MAX_SHIFTS),
+        ("resid_unrefined", ctypes.c_double * MAX_SHIFTS),
+        ("seconds", ctypes.c_double),
+    ]
+
+    def to_dict(self, n: int) -> dict:
+        return dict(iters=self.iters, n_reliable=self.n_reliable, refine_iters=self.refine_iters,
+                    fallback_used=self.fallback_used,
+                    iters_shift=list(self.iters_shift[:n]), resid_iter=list(self.resid_iter[:n]),
+                    resid_true=list(self.resid_true[:n]),
+                    resid_unrefined=list(self.resid_unrefined[:n]), seconds=self.seconds)
+
+
+_v, _i, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+
+# name -> (restype, argtypes); the full set of entry points of include/stag.h
+SIGNATURES = {
+    "stag_lattice_create": (_i, [ctypes.POINTER(ctypes.c_int), _i, ctypes.POINTER(_v)]),
+    "stag_lattice_destroy": (_i, [_v]),
+    "stag_half_volume": (ctypes.c_int64, [_v]),
+    "stag_links_set": (_i, [_v, _v, _i, _v]),
+    "stag_tables": (_i, [_v, _v, _v, _v, _v]),
+    "stag_vec_pack": (_i, [_v, _v, _v, _i, _v]),
+    "stag_vec_unpack": (_i, [_v, _v, _v, _i, _v]),
+    "stag_dslash_eo": (_i, [_v, _i, _v, _v, _i, _v]),
+    "stag_normal_op": (_i, [_v, _d, _d, _v, _v, _i, _v]),
+    "stag_multishift_cg": (_i, [_v, _d, ctypes.POINTER(_d), _i, _v, ctypes.POINTER(_v), _d, _i, _i,
+                                ctypes.POINTER(CgStats), _v]),
+    "stag_cg": (_i, [_v, _d, _d, _v, _v, _d, _i, _i, ctypes.POINTER(CgStats), _v]),
+    "stag_status_string": (ctypes.c_char_p, [_i]),
+    "stag_last_error": (ctypes.c_char_p, []),
+}
+
+
+def load_library(path: str):
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build the HIP library first "
+            "(python -c 'import __graft_entry__ as g; g.build()' or python -m paper_1010_5433_amd.build)")
+    L = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L

@@ -1,0 +1,258 @@
+// The C ABI (include/stag.h): argument validation, handle and work-buffer
+// management, and dispatch to the kernels and solver drivers.  No C++
+// exception crosses this boundary.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+#include "links.h"
+#include "solver.h"
+
+namespace stag {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+const char *last_error() { return g_last_error.c_str(); }
+
+stag_status ws_get(stag_lattice *lat, int slot, size_t bytes, void **out) {
+    if (bytes == 0) bytes = 16;
+    if (lat->ws_bytes[slot] < bytes) {
+        if (lat->ws[slot]) {
+            // the buffer may still be in use by queued work
+            STAG_HIP(hipDeviceSynchronize());
+            STAG_HIP(hipFree(lat->ws[slot]));
+            lat->ws[slot] = nullptr;
+            lat->ws_bytes[slot] = 0;
+        }
+        STAG_HIP(hipMalloc(&lat->ws[slot], bytes));
+        lat->ws_bytes[slot] = bytes;
+    }
+    *out = lat->ws[slot];
+    return STAG_OK;
+}
+
+stag_status multishift_cg(stag_lattice *lat, double mass, const double *shifts, int n, const void *src,
+                          void *const *sols, double tol, int max_iter, stag_prec prec, stag_cg_stats *stats,
+                          hipStream_t s);
+stag_status single_cg(stag_lattice *lat, double mass, double shift, const void *src, void *x, double tol,
+                      int max_iter, stag_prec prec, stag_cg_stats *stats, hipStream_t s);
+
+static stag_status use_device(const stag_lattice *lat) {
+    int dev = -1;
+    STAG_HIP(hipGetDevice(&dev));
+    if (dev != lat->device) STAG_HIP(hipSetDevice(lat->device));
+    return STAG_OK;
+}
+
+static stag_status check_lattice(const stag_lattice *lat, bool need_links) {
+    if (!lat) return invalid("null lattice handle");
+    if (need_links && !lat->nrow) return invalid("links not set (call stag_links_set first)");
+    return use_device(lat);
+}
+
+static bool prec_ok(stag_prec p) { return p == STAG_F64 || p == STAG_F32; }
+
+}  // namespace stag
+
+using namespace stag;
+
+extern "C" {
+
+stag_status stag_lattice_create(const int dims[4], int antiperiodic_t, stag_lattice **out) {
+    try {
+        if (!dims || !out) return invalid("null argument");
+        *out = nullptr;
+        int64_t v = 1;
+        for (int mu = 0; mu < 4; ++mu) {
+            if (dims[mu] < 2 || (dims[mu] & 1))
+                return invalid("every lattice extent must be even and >= 2 (dim " + std::to_string(mu) + " = " +
+                               std::to_string(dims[mu]) + ")");
+            v *= dims[mu];
+        }
+        if (v / 2 >= (int64_t(1) << 30)) return invalid("lattice too large (V/2 must be < 2^30)");
+        stag_lattice *lat = new stag_lattice;
+        std::memset(lat, 0, sizeof(*lat));
+        for (int mu = 0; mu < 4; ++mu) lat->dims[mu] = dims[mu];
+        lat->antiperiodic = antiperiodic_t ? 1 : 0;
+        lat->V = v;
+        lat->Vh = v / 2;
+        lat->g = make_geom(dims, lat->antiperiodic);
+        hipError_t e = hipGetDevice(&lat->device);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&lat->host_flags, 4 * sizeof(int), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            set_error(std::string("device set-up failed: ") + hipGetErrorString(e));
+            delete lat;
+            return STAG_EHIP;
+        }
+        *out = lat;
+        return STAG_OK;
+    } catch (...) {
+        set_error("allocation failed");
+        return STAG_ENOMEM;
+    }
+}
+
+stag_status stag_lattice_destroy(stag_lattice *lat) {
+    if (!lat) return STAG_OK;
+    hipSetDevice(lat->device);
+    hipDeviceSynchronize();
+    hipFree(lat->links64);
+    hipFree(lat->links32);
+    for (int k = 0; k < WS_NSLOTS; ++k) hipFree(lat->ws[k]);
+    hipHostFree(lat->host_flags);
+    delete lat;
+    return STAG_OK;
+}
+
+int64_t stag_half_volume(const stag_lattice *lat) { return lat ? lat->Vh : 0; }
+
+stag_status stag_links_set(stag_lattice *lat, const void *links, stag_link_fmt fmt, void *stream) {
+    STAG_TRY(check_lattice(lat, false));
+    if (!links) return invalid("null links");
+    if (fmt != STAG_LINK18 && fmt != STAG_LINK12) return invalid("unknown link format");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nrow = fmt == STAG_LINK12 ? 2 : 3;
+    STAG_HIP(hipStreamSynchronize(s));
+    if (lat->links64) STAG_HIP(hipFree(lat->links64));
+    if (lat->links32) STAG_HIP(hipFree(lat->links32));
+    lat->links64 = lat->links32 = nullptr;
+    lat->nrow = 0;
+    STAG_HIP(hipMalloc(&lat->links64, link_field_bytes(true, nrow, lat->Vh)));
+    STAG_HIP(hipMalloc(&lat->links32, link_field_bytes(false, nrow, lat->Vh)));
+    STAG_HIP(launch_pack_links(lat->g, links, lat->links64, true, nrow, s));
+    STAG_HIP(launch_pack_links(lat->g, links, lat->links32, false, nrow, s));
+    lat->nrow = nrow;
+    return STAG_OK;
+}
+
+stag_status stag_tables(const stag_lattice *lat, int32_t *nbr, int32_t *coord, int32_t *sign, void *stream) {
+    STAG_TRY(check_lattice(lat, false));
+    STAG_HIP(launch_tables(lat->g, nbr, coord, sign, static_cast<hipStream_t>(stream)));
+    return STAG_OK;
+}
+
+stag_status stag_vec_pack(const stag_lattice *lat, const void *canonical, void *vec, stag_prec prec, void *stream) {
+    STAG_TRY(check_lattice(lat, false));
+    if (!canonical || !vec) return invalid("null vector");
+    if (!prec_ok(prec)) return invalid("vector precision must be STAG_F64 or STAG_F32");
+    STAG_HIP(launch_pack_vec(lat->g, canonical, vec, prec == STAG_F64, static_cast<hipStream_t>(stream)));
+    return STAG_OK;
+}
+
+stag_status stag_vec_unpack(const stag_lattice *lat, const void *vec, void *canonical, stag_prec prec, void *stream) {
+    STAG_TRY(check_lattice(lat, false));
+    if (!canonical || !vec) return invalid("null vector");
+    if (!prec_ok(prec)) return invalid("vector precision must be STAG_F64 or STAG_F32");
+    STAG_HIP(launch_unpack_vec(lat->g, vec, canonical, prec == STAG_F64, static_cast<hipStream_t>(stream)));
+    return STAG_OK;
+}
+
+stag_status stag_dslash_eo(const stag_lattice *lat, int out_parity, const void *in, void *out, stag_prec prec,
+                           void *stream) {
+    STAG_TRY(check_lattice(lat, true));
+    if (!in || !out) return invalid("null vector");
+    if (in == out) return invalid("in and out must not overlap");
+    if (out_parity != 0 && out_parity != 1) return invalid("out_parity must be 0 or 1");
+    if (!prec_ok(prec)) return invalid("precision must be STAG_F64 or STAG_F32");
+    const bool dbl = prec == STAG_F64;
+    DslashArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = lat->g;
+    a.out_parity = out_parity;
+    a.links = dbl ? lat->links64 : lat->links32;
+    a.in = in;
+    a.out = out;
+    STAG_HIP(launch_dslash(dbl, lat->nrow, DS_PLAIN, a, static_cast<hipStream_t>(stream)));
+    return STAG_OK;
+}
+
+stag_status stag_normal_op(stag_lattice *lat, double mass, double shift, const void *in, void *out, stag_prec prec,
+                           void *stream) {
+    STAG_TRY(check_lattice(lat, true));
+    if (!in || !out) return invalid("null vector");
+    if (in == out) return invalid("in and out must not overlap");
+    if (!(mass > 0) || !std::isfinite(mass)) return invalid("mass must be > 0");
+    if (!(shift >= 0) || !std::isfinite(shift)) return invalid("shift must be >= 0");
+    if (!prec_ok(prec)) return invalid("precision must be STAG_F64 or STAG_F32");
+    const bool dbl = prec == STAG_F64;
+    void *t = nullptr;
+    STAG_TRY(ws_get(lat, WS_E, (size_t)vec_bytes(lat, dbl), &t));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DslashArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = lat->g;
+    a.links = dbl ? lat->links64 : lat->links32;
+    a.out_parity = 1;
+    a.in = in;
+    a.out = t;
+    STAG_HIP(launch_dslash(dbl, lat->nrow, DS_PLAIN, a, s));
+    a.out_parity = 0;
+    a.in = t;
+    a.out = out;
+    a.aux = in;
+    a.c = mass * mass + shift;
+    STAG_HIP(launch_dslash(dbl, lat->nrow, DS_NORMAL, a, s));
+    return STAG_OK;
+}
+
+static stag_status check_solver_args(double mass, double tol, int max_iter, stag_prec prec) {
+    if (!(mass > 0) || !std::isfinite(mass)) return invalid("mass must be > 0");
+    if (!(tol > 0) || !std::isfinite(tol)) return invalid("tol must be > 0");
+    if (max_iter < 1) return invalid("max_iter must be >= 1");
+    if (prec != STAG_F64 && prec != STAG_F32 && prec != STAG_MIXED) return invalid("unknown precision");
+    return STAG_OK;
+}
+
+stag_status stag_multishift_cg(stag_lattice *lat, double mass, const double *shifts, int n_shifts, const void *src,
+                               void *const *sols, double tol, int max_iter, stag_prec prec, stag_cg_stats *stats,
+                               void *stream) {
+    try {
+        STAG_TRY(check_lattice(lat, true));
+        STAG_TRY(check_solver_args(mass, tol, max_iter, prec));
+        if (!shifts || !src || !sols) return invalid("null argument");
+        if (n_shifts < 1 || n_shifts > STAG_MAX_SHIFTS) return invalid("n_shifts must be in [1, 64]");
+        for (int i = 0; i < n_shifts; ++i) {
+            if (!(shifts[i] >= 0) || !std::isfinite(shifts[i])) return invalid("shifts must be >= 0 and finite");
+            if (!sols[i]) return invalid("null solution pointer");
+            if (sols[i] == src) return invalid("a solution aliases the source");
+        }
+        return multishift_cg(lat, mass, shifts, n_shifts, src, sols, tol, max_iter, prec, stats,
+                             static_cast<hipStream_t>(stream));
+    } catch (...) {
+        set_error("host allocation failed");
+        return STAG_ENOMEM;
+    }
+}
+
+stag_status stag_cg(stag_lattice *lat, double mass, double shift, const void *src, void *x, double tol, int max_iter,
+                    stag_prec prec, stag_cg_stats *stats, void *stream) {
+    try {
+        STAG_TRY(check_lattice(lat, true));
+        STAG_TRY(check_solver_args(mass, tol, max_iter, prec));
+        if (prec == STAG_F32) return invalid("stag_cg takes STAG_F64 or STAG_MIXED");
+        if (!(shift >= 0) || !std::isfinite(shift)) return invalid("shift must be >= 0");
+        if (!src || !x) return invalid("null vector");
+        if (src == x) return invalid("x aliases the source");
+        return single_cg(lat, mass, shift, src, x, tol, max_iter, prec, stats, static_cast<hipStream_t>(stream));
+    } catch (...) {
+        set_error("host allocation failed");
+        return STAG_ENOMEM;
+    }
+}
+
+const char *stag_status_string(stag_status s) {
+    switch (s) {
+        case STAG_OK: return "ok";
+        case STAG_ENOCONV: return "not converged within max_iter";
+        case STAG_EBREAKDOWN: return "breakdown: non-positive or non-finite curvature";
+        case STAG_EINVAL: return "invalid argument";
+        case STAG_ENOMEM: return "out of memory";
+        case STAG_EHIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char *stag_last_error(void) { return stag::last_error(); }
+
+}  // extern "C"

@@ -1,0 +1,380 @@
+// Solver kernels: FP64 reductions, the shifted-CG scalar recursion on the
+// device, and the fused vector updates.
+//
+// Scalar recursion (Jegerlehner's multi-shift CG, the Krylov solver for
+// shifted systems cited in Section 6), base shift sigma_0 = min sigma_i,
+// s_i = sigma_i - sigma_0, alpha_{-1} = 1, beta_{-1} = 0, zeta^{-1} = zeta^0 = 1:
+//   alpha_k = rho_k / Re<p, A p>
+//   zeta_i^{k+1} = zeta_i^k zeta_i^{k-1} alpha_{k-1} /
+//        [alpha_k beta_{k-1} (zeta_i^{k-1} - zeta_i^k) + zeta_i^{k-1} alpha_{k-1} (1 + s_i alpha_k)]
+//   beta_k = rho_{k+1} / rho_k
+//   alpha_k^i = alpha_k zeta_i^{k+1} / zeta_i^k,  beta_k^i = beta_k (zeta_i^{k+1} / zeta_i^k)^2
+// Shift i freezes once |zeta_i^{k+1}| sqrt(rho_{k+1}) <= tol ||b||.
+//
+// All sums run in a fixed order (per-block partials, then one wave that
+// reads them in a fixed stride and finishes with a DPP reduction), so a
+// solve is bitwise reproducible from run to run.
+#include <math.h>
+
+#include "common.h"
+#include "solver.h"
+
+namespace stag {
+
+int blas_grid(int64_t n) {
+    int64_t g = (n + kBlasBlock - 1) / kBlasBlock;
+    if (g > kMaxBlasGrid) g = kMaxBlasGrid;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+// Sum of nparts partials by one wave (blockDim.x == 64), fixed order.
+__device__ __forceinline__ double sum_partials(const double *part, int nparts) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += kWave) s += part[k];
+    return wave_sum(s);
+}
+
+template <typename R> using T2 = typename vtype<R>::t2;
+
+template <typename R> __device__ __forceinline__ double abs2(T2<R> v) {
+    return double(v.x) * double(v.x) + double(v.y) * double(v.y);
+}
+
+// ---------------------------------------------------------------- vectors
+
+template <typename R>
+__global__ void __launch_bounds__(kBlasBlock) k_norm2(const T2<R> *v, int64_t n, double *partial) {
+    __shared__ double red[kBlasBlock / kWave];
+    double part = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock)
+        part += abs2<R>(v[j]);
+    const double s = block_sum(part, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlasBlock) k_ms_start(const double2 *b, T2<R> *r, ShiftPtrs ptrs, int n_shift,
+                                                      int zero_x, int64_t n) {
+    for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
+        const double2 bj = b[j];
+        T2<R> v;
+        v.x = R(bj.x);
+        v.y = R(bj.y);
+        r[j] = v;
+        for (int i = 0; i < n_shift; ++i) {
+            static_cast<T2<R> *>(ptrs.p[i])[j] = v;
+            if (zero_x) {
+                T2<R> z;
+                z.x = R(0);
+                z.y = R(0);
+                static_cast<T2<R> *>(ptrs.x[i])[j] = z;
+            }
+        }
+    }
+}
+
+// r -= alpha A p, and the partial of ||r||^2.
+template <typename R>
+__global__ void __launch_bounds__(kBlasBlock) k_r_update(const MsState *st, T2<R> *r, const T2<R> *ap, int64_t n,
+                                                      double *partial) {
+    if (st->done) return;
+    __shared__ double red[kBlasBlock / kWave];
+    const R alpha = R(st->alpha);
+    double part = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
+        T2<R> rv = r[j];
+        const T2<R> q = ap[j];
+        rv.x -= alpha * q.x;
+        rv.y -= alpha * q.y;
+        r[j] = rv;
+        part += abs2<R>(rv);
+    }
+    const double s = block_sum(part, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// For every shift updated this iteration: x_i += alpha_i p_i and
+// p_i = zeta_i r + beta_i p_i, reading r once for all shifts.  A frozen base
+// system still advances its direction p = r + beta p while other shifts run.
+template <typename R>
+__global__ void __launch_bounds__(kBlasBlock) k_shift_update(const MsState *st, const T2<R> *r, ShiftPtrs ptrs,
+                                                          int n_shift, int64_t n) {
+    if (!st->upd_valid) return;
+    const int base = st->base;
+    const int upd_p = st->upd_p;
+    const R beta = R(st->beta);
+    for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
+        const T2<R> rv = r[j];
+        for (int i = 0; i < n_shift; ++i) {
+            T2<R> *pi = static_cast<T2<R> *>(ptrs.p[i]);
+            if (st->upd[i]) {
+                T2<R> *xi = static_cast<T2<R> *>(ptrs.x[i]);
+                const R ai = R(st->a[i]), bi = R(st->b[i]), zi = R(st->zeta[i]);
+                const T2<R> pv = pi[j];
+                T2<R> xv = xi[j];
+                xv.x += ai * pv.x;
+                xv.y += ai * pv.y;
+                xi[j] = xv;
+                T2<R> np;
+                np.x = zi * rv.x + bi * pv.x;
+                np.y = zi * rv.y + bi * pv.y;
+                pi[j] = np;
+            } else if (i == base && upd_p) {
+                const T2<R> pv = pi[j];
+                T2<R> np;
+                np.x = rv.x + beta * pv.x;
+                np.y = rv.y + beta * pv.y;
+                pi[j] = np;
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlasBlock) k_x_flush(const MsState *st, ShiftPtrs hi, ShiftPtrs lo, int n_shift,
+                                                     int64_t n, int skip_on_done) {
+    if (skip_on_done && st->done) return;
+    for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
+        for (int i = 0; i < n_shift; ++i) {
+            double2 *h = static_cast<double2 *>(hi.x[i]);
+            float2 *l = static_cast<float2 *>(lo.x[i]);
+            const float2 lv = l[j];
+            double2 hv = h[j];
+            hv.x += double(lv.x);
+            hv.y += double(lv.y);
+            h[j] = hv;
+            l[j] = make_float2(0.f, 0.f);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlasBlock) k_demote(const MsState *st, const double2 *src, float2 *dst, int64_t n) {
+    if (st->done) return;
+    for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
+        const double2 v = src[j];
+        dst[j] = make_float2(float(v.x), float(v.y));
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlasBlock) k_restart(const double2 *rhi, T2<R> *r, T2<R> *p, int64_t n) {
+    for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
+        const double2 v = rhi[j];
+        T2<R> w;
+        w.x = R(v.x);
+        w.y = R(v.y);
+        r[j] = w;
+        p[j] = w;
+    }
+}
+
+// ---------------------------------------------------------------- scalars (one wave)
+
+// rho from partial_r; ||b||^2 from partial_b, or equal to rho when
+// partial_b is null (zero start: r = b).
+__global__ void __launch_bounds__(kWave) k_scalar_init(MsState *st, const double *partial_r, int nparts_r,
+                                                    const double *partial_b, int nparts_b) {
+    const double rho = sum_partials(partial_r, nparts_r);
+    const double b2 = partial_b ? sum_partials(partial_b, nparts_b) : rho;
+    const int l = threadIdx.x;
+    const bool conv = rho <= st->tol * st->tol * b2;
+    if (l < st->n) {
+        st->zeta[l] = st->zeta_prev[l] = st->zeta_next[l] = 1.0;
+        st->a[l] = st->b[l] = 0.0;
+        st->active[l] = conv ? 0 : 1;
+        st->upd[l] = 0;
+        st->iters_shift[l] = 0;
+        st->resid_iter[l] = b2 > 0.0 ? sqrt(rho / b2) : 0.0;
+        st->resid_true[l] = 0.0;
+    }
+    if (l == 0) {
+        st->bnorm2 = b2;
+        st->rho = rho;
+        st->alpha = 0.0;
+        st->alpha_prev = 1.0;
+        st->beta = 0.0;
+        st->beta_prev = 0.0;
+        st->iter = 0;
+        st->upd_valid = 0;
+        st->upd_p = 0;
+        st->n_reliable = 0;
+        st->done = conv ? 1 : 0;
+        st->status = conv ? MS_CONVERGED : MS_RUNNING;
+    }
+}
+
+__global__ void __launch_bounds__(kWave) k_scalar_alpha(MsState *st, const double *partial, int nparts) {
+    const int l = threadIdx.x;
+    if (st->done) {
+        if (l == 0) st->upd_valid = 0;
+        return;
+    }
+    const double pap = sum_partials(partial, nparts);
+    if (!(pap > 0.0) || !isfinite(pap)) {
+        if (l == 0) {
+            st->status = MS_BREAKDOWN;
+            st->done = 1;
+            st->upd_valid = 0;
+        }
+        return;
+    }
+    const double alpha = st->rho / pap;
+    if (l < st->n && st->active[l]) {
+        if (l == st->base) {
+            st->zeta_next[l] = 1.0;
+        } else {
+            const double z = st->zeta[l], zp = st->zeta_prev[l];
+            const double den = alpha * st->beta_prev * (zp - z) + zp * st->alpha_prev * (1.0 + st->shift_rel[l] * alpha);
+            st->zeta_next[l] = z * zp * st->alpha_prev / den;
+        }
+    }
+    if (l == 0) st->alpha = alpha;
+}
+
+__global__ void __launch_bounds__(kWave) k_scalar_beta(MsState *st, const double *partial, int nparts) {
+    if (st->done) return;
+    const int l = threadIdx.x;
+    const double rho_new = sum_partials(partial, nparts);
+    const double beta = rho_new / st->rho;
+    const double alpha = st->alpha;
+    const int it = st->iter + 1;
+    bool act = false;
+    if (l < st->n) {
+        const bool was = st->active[l] != 0;
+        st->upd[l] = was ? 1 : 0;
+        if (was) {
+            const double zn = st->zeta_next[l];
+            const double ratio = zn / st->zeta[l];
+            st->a[l] = alpha * ratio;
+            st->b[l] = beta * ratio * ratio;
+            const double res = fabs(zn) * sqrt(rho_new / st->bnorm2);
+            st->resid_iter[l] = res;
+            if (res <= st->tol) {
+                st->active[l] = 0;
+                st->iters_shift[l] = it;
+            } else {
+                act = true;
+            }
+            st->zeta_prev[l] = st->zeta[l];
+            st->zeta[l] = zn;
+        }
+    }
+    const unsigned long long any = __ballot(act);
+    const int upd_base = __shfl(l < st->n ? st->upd[l] : 0, st->base);
+    if (l == 0) {
+        st->upd_p = (upd_base || any) ? 1 : 0;
+        st->beta = beta;
+        st->beta_prev = beta;
+        st->alpha_prev = alpha;
+        st->rho = rho_new;
+        st->iter = it;
+        st->upd_valid = 1;
+        if (!any) {
+            st->done = 1;
+            st->status = MS_CONVERGED;
+        } else if (it >= st->max_iter) {
+            st->done = 1;
+            st->status = MS_NOCONV;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kWave) k_scalar_reliable(MsState *st, const double *partial, int nparts) {
+    if (st->done) return;
+    const double rho = sum_partials(partial, nparts);
+    if (threadIdx.x == 0) {
+        st->rho = rho;
+        st->n_reliable += 1;
+    }
+}
+
+__global__ void __launch_bounds__(kWave) k_reduce_to(MsState *st, int slot, const double *partial, int nparts) {
+    const double s = sum_partials(partial, nparts);
+    if (threadIdx.x == 0) st->scratch[slot] = s;
+}
+
+__global__ void __launch_bounds__(kWave) k_store_true_resid(MsState *st, int i, const double *partial, int nparts) {
+    const double s = sum_partials(partial, nparts);
+    if (threadIdx.x == 0) st->resid_true[i] = st->bnorm2 > 0.0 ? sqrt(s / st->bnorm2) : sqrt(s);
+}
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_norm2(bool dbl, const void *v, int64_t n, double *partial, int grid, hipStream_t s) {
+    if (dbl) hipLaunchKernelGGL(k_norm2<double>, dim3(grid), dim3(kBlasBlock), 0, s, static_cast<const double2 *>(v), n, partial);
+    else hipLaunchKernelGGL(k_norm2<float>, dim3(grid), dim3(kBlasBlock), 0, s, static_cast<const float2 *>(v), n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_start(bool dbl, const double2 *b, void *r, ShiftPtrs ptrs, int n_shift, bool zero_x, int64_t n,
+                           hipStream_t s) {
+    const int grid = blas_grid(n);
+    if (dbl) hipLaunchKernelGGL(k_ms_start<double>, dim3(grid), dim3(kBlasBlock), 0, s, b, static_cast<double2 *>(r), ptrs, n_shift, zero_x ? 1 : 0, n);
+    else hipLaunchKernelGGL(k_ms_start<float>, dim3(grid), dim3(kBlasBlock), 0, s, b, static_cast<float2 *>(r), ptrs, n_shift, zero_x ? 1 : 0, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scalar_init(MsState *st, const double *partial_r, int nparts_r, const double *partial_b,
+                              int nparts_b, hipStream_t s) {
+    hipLaunchKernelGGL(k_scalar_init, dim3(1), dim3(kWave), 0, s, st, partial_r, nparts_r, partial_b, nparts_b);
+    return hipGetLastError();
+}
+
+hipError_t launch_scalar_alpha(MsState *st, const double *partial, int nparts, hipStream_t s) {
+    hipLaunchKernelGGL(k_scalar_alpha, dim3(1), dim3(kWave), 0, s, st, partial, nparts);
+    return hipGetLastError();
+}
+
+hipError_t launch_r_update(bool dbl, MsState *st, void *r, const void *ap, int64_t n, double *partial, int grid,
+                           hipStream_t s) {
+    if (dbl) hipLaunchKernelGGL(k_r_update<double>, dim3(grid), dim3(kBlasBlock), 0, s, st, static_cast<double2 *>(r), static_cast<const double2 *>(ap), n, partial);
+    else hipLaunchKernelGGL(k_r_update<float>, dim3(grid), dim3(kBlasBlock), 0, s, st, static_cast<float2 *>(r), static_cast<const float2 *>(ap), n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_scalar_beta(MsState *st, const double *partial, int nparts, hipStream_t s) {
+    hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kWave), 0, s, st, partial, nparts);
+    return hipGetLastError();
+}
+
+hipError_t launch_shift_update(bool dbl, MsState *st, const void *r, ShiftPtrs ptrs, int n_shift, int64_t n, int grid,
+                               hipStream_t s) {
+    if (dbl) hipLaunchKernelGGL(k_shift_update<double>, dim3(grid), dim3(kBlasBlock), 0, s, st, static_cast<const double2 *>(r), ptrs, n_shift, n);
+    else hipLaunchKernelGGL(k_shift_update<float>, dim3(grid), dim3(kBlasBlock), 0, s, st, static_cast<const float2 *>(r), ptrs, n_shift, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_x_flush(MsState *st, ShiftPtrs hi, ShiftPtrs lo, int n_shift, int64_t n, bool skip_on_done,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_x_flush, dim3(blas_grid(n)), dim3(kBlasBlock), 0, s, st, hi, lo, n_shift, n, skip_on_done ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_demote(MsState *st, const double2 *src, float2 *dst, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_demote, dim3(blas_grid(n)), dim3(kBlasBlock), 0, s, st, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scalar_reliable(MsState *st, const double *partial, int nparts, hipStream_t s) {
+    hipLaunchKernelGGL(k_scalar_reliable, dim3(1), dim3(kWave), 0, s, st, partial, nparts);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_to(MsState *st, int slot, const double *partial, int nparts, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(kWave), 0, s, st, slot, partial, nparts);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_true_resid(MsState *st, int i, const double *partial, int nparts, hipStream_t s) {
+    hipLaunchKernelGGL(k_store_true_resid, dim3(1), dim3(kWave), 0, s, st, i, partial, nparts);
+    return hipGetLastError();
+}
+
+hipError_t launch_restart(bool dbl, const double2 *rhi, void *r, void *p, int64_t n, hipStream_t s) {
+    const int grid = blas_grid(n);
+    if (dbl) hipLaunchKernelGGL(k_restart<double>, dim3(grid), dim3(kBlasBlock), 0, s, rhi, static_cast<double2 *>(r), static_cast<double2 *>(p), n);
+    else hipLaunchKernelGGL(k_restart<float>, dim3(grid), dim3(kBlasBlock), 0, s, rhi, static_cast<float2 *>(r), static_cast<float2 *>(p), n);
+    return hipGetLastError();
+}
+
+}  // namespace stag

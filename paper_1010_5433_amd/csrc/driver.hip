@@ -1,0 +1,341 @@
+// Host driver of the shifted CG family.
+//
+// One routine runs the multi-shift CG (zero start, Section 6: the shifted
+// solver must start from the null vector) and the single-shift CG from a
+// given x (used to refine single precision results).  The iteration is
+// enqueued in chunks; all scalars stay on the device and the host only
+// reads a 4-byte "done" flag per chunk, one chunk behind, so the GPU queue
+// never drains while the host checks convergence.  Kernels enqueued after
+// the solve ended see the flag and return at once.
+//
+// Precision policy (Section 4 and Section 6): STAG_F64 runs everything in
+// double; STAG_F32 and STAG_MIXED run the operator and the vectors in
+// single precision with double reductions and recursion, accumulating
+// solutions in single precision and flushing them into the double
+// solutions.  STAG_MIXED adds reliable updates: every `reliable_every`
+// iterations the base residual is recomputed as b - A x in double
+// precision (the residual-replacement idea the paper discusses, applied to
+// the base system of the shifted family) and the single precision residual
+// is replaced by it.
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "solver.h"
+
+namespace stag {
+
+struct ShiftedSolve {
+    double mass;
+    int n;
+    const double *shifts;     // host
+    const void *src;          // double library vector
+    void *const *x_hi;        // double library vectors (outputs)
+    bool x_init;              // start from x_hi (n == 1) instead of zero
+    double tol;
+    int max_iter;
+    bool dbl_iter;            // double precision iterations
+    int reliable_every;       // 0: no reliable updates
+};
+
+struct ShiftedResult {
+    int status;               // MsStatus
+    int iters;
+    int n_reliable;
+    int iters_shift[kMaxShifts];
+    double resid_iter[kMaxShifts];
+    double resid_true[kMaxShifts];
+};
+
+static constexpr int kChunk = 8;   // iterations enqueued between flag reads
+
+stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult *res, hipStream_t s) {
+    const int n = sp.n;
+    const bool dbl = sp.dbl_iter;
+    const int64_t ne = 3 * lat->Vh;  // complex entries per vector
+    const size_t vb = (size_t)vec_bytes(lat, dbl);
+    const size_t vb64 = (size_t)vec_bytes(lat, true);
+    const void *links_it = dbl ? lat->links64 : lat->links32;
+
+    int base = 0;
+    for (int i = 1; i < n; ++i)
+        if (sp.shifts[i] < sp.shifts[base]) base = i;
+    const double sigma0 = sp.shifts[base];
+
+    void *T, *T64, *R, *AP, *P, *XLO = nullptr, *RHI, *PART, *STATE;
+    const int ds_grid = dslash_grid(lat->g, kDslashBlock);
+    const int bl_grid = blas_grid(ne);
+    const int nparts_max = ds_grid > kMaxBlasGrid ? ds_grid : kMaxBlasGrid;
+    STAG_TRY(ws_get(lat, WS_T, vb, &T));
+    STAG_TRY(ws_get(lat, WS_T2, vb64, &T64));
+    STAG_TRY(ws_get(lat, WS_R, vb, &R));
+    STAG_TRY(ws_get(lat, WS_AP, vb, &AP));
+    STAG_TRY(ws_get(lat, WS_P, vb * n, &P));
+    if (!dbl) STAG_TRY(ws_get(lat, WS_XLO, (size_t)vec_bytes(lat, false) * n, &XLO));
+    STAG_TRY(ws_get(lat, WS_RHI, vb64, &RHI));
+    STAG_TRY(ws_get(lat, WS_PART, sizeof(double) * 2 * nparts_max, &PART));
+    STAG_TRY(ws_get(lat, WS_STATE, sizeof(MsState), &STATE));
+    double *part0 = static_cast<double *>(PART), *part1 = part0 + nparts_max;
+    MsState *st = static_cast<MsState *>(STATE);
+
+    ShiftPtrs it_ptrs, hi_ptrs, lo_ptrs;
+    std::memset(&it_ptrs, 0, sizeof(it_ptrs));
+    std::memset(&hi_ptrs, 0, sizeof(hi_ptrs));
+    std::memset(&lo_ptrs, 0, sizeof(lo_ptrs));
+    for (int i = 0; i < n; ++i) {
+        it_ptrs.p[i] = static_cast<char *>(P) + vb * i;
+        hi_ptrs.x[i] = sp.x_hi[i];
+        if (!dbl) lo_ptrs.x[i] = static_cast<char *>(XLO) + (size_t)vec_bytes(lat, false) * i;
+        it_ptrs.x[i] = dbl ? sp.x_hi[i] : lo_ptrs.x[i];
+    }
+    void *pbase = it_ptrs.p[base];
+
+    // static part of the state
+    MsState hs;
+    std::memset(&hs, 0, sizeof(hs));
+    hs.n = n;
+    hs.base = base;
+    hs.tol = sp.tol;
+    hs.max_iter = sp.max_iter;
+    for (int i = 0; i < n; ++i) hs.shift_rel[i] = sp.shifts[i] - sigma0;
+    STAG_HIP(hipMemcpyAsync(st, &hs, sizeof(hs), hipMemcpyHostToDevice, s));
+
+    const double m2 = sp.mass * sp.mass;
+    DslashArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = lat->g;
+
+    // r = b - A x_hi in double precision into RHI, partial |r|^2 into part0
+    auto true_residual = [&](void *x, double shift, void *rout, double *partial, const int *skip) -> hipError_t {
+        DslashArgs d = a;
+        d.links = lat->links64;
+        d.skip = skip;
+        d.out_parity = 1;
+        d.in = x;
+        d.out = T64;
+        hipError_t e = launch_dslash(true, lat->nrow, DS_PLAIN, d, s);
+        if (e != hipSuccess) return e;
+        d.out_parity = 0;
+        d.in = T64;
+        d.out = rout;
+        d.aux = x;
+        d.rhs = sp.src;
+        d.c = m2 + shift;
+        d.partial = partial;
+        return launch_dslash(true, lat->nrow, DS_RESID, d, s);
+    };
+
+    // ---------------------------------------------------------------- start
+    if (!sp.x_init) {
+        STAG_HIP(launch_ms_start(dbl, static_cast<const double2 *>(sp.src), R, it_ptrs, n, true, ne, s));
+        if (!dbl)
+            for (int i = 0; i < n; ++i) STAG_HIP(hipMemsetAsync(sp.x_hi[i], 0, vb64, s));
+        STAG_HIP(launch_norm2(true, sp.src, ne, part0, bl_grid, s));
+        STAG_HIP(launch_scalar_init(st, part0, bl_grid, nullptr, 0, s));
+    } else {
+        STAG_HIP(true_residual(sp.x_hi[0], sp.shifts[0], RHI, part0, nullptr));
+        STAG_HIP(launch_restart(dbl, static_cast<const double2 *>(RHI), R, pbase, ne, s));
+        if (!dbl) STAG_HIP(hipMemsetAsync(lo_ptrs.x[0], 0, (size_t)vec_bytes(lat, false), s));
+        STAG_HIP(launch_norm2(true, sp.src, ne, part1, bl_grid, s));
+        STAG_HIP(launch_scalar_init(st, part0, ds_grid, part1, bl_grid, s));
+    }
+
+    // ---------------------------------------------------------------- iterate
+    a.links = links_it;
+    a.skip = &st->done;
+    auto iteration = [&](int k) -> stag_status {
+        DslashArgs d = a;
+        d.out_parity = 1;
+        d.in = pbase;
+        d.out = T;
+        STAG_HIP(launch_dslash(dbl, lat->nrow, DS_PLAIN, d, s));
+        d.out_parity = 0;
+        d.in = T;
+        d.out = AP;
+        d.aux = pbase;
+        d.c = m2 + sigma0;
+        d.partial = part0;
+        STAG_HIP(launch_dslash(dbl, lat->nrow, DS_NORMAL_DOT, d, s));
+        STAG_HIP(launch_scalar_alpha(st, part0, ds_grid, s));
+        STAG_HIP(launch_r_update(dbl, st, R, AP, ne, part1, bl_grid, s));
+        STAG_HIP(launch_scalar_beta(st, part1, bl_grid, s));
+        STAG_HIP(launch_shift_update(dbl, st, R, it_ptrs, n, ne, bl_grid, s));
+        if (sp.reliable_every > 0 && (k + 1) % sp.reliable_every == 0) {
+            STAG_HIP(launch_x_flush(st, hi_ptrs, lo_ptrs, n, ne, true, s));
+            STAG_HIP(true_residual(sp.x_hi[base], sigma0, RHI, part0, &st->done));
+            STAG_HIP(launch_demote(st, static_cast<const double2 *>(RHI), static_cast<float2 *>(R), ne, s));
+            STAG_HIP(launch_scalar_reliable(st, part0, ds_grid, s));
+        }
+        return STAG_OK;
+    };
+
+    hipEvent_t ev[2];
+    STAG_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    STAG_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    volatile int *flags = lat->host_flags;
+    flags[0] = flags[1] = 0;
+    stag_status rc = STAG_OK;
+    int chunk = 0;
+    bool finished = false;
+    for (int k0 = 0; k0 < sp.max_iter + kChunk && !finished; k0 += kChunk, ++chunk) {
+        for (int k = k0; k < k0 + kChunk; ++k) {
+            rc = iteration(k);
+            if (rc != STAG_OK) break;
+        }
+        if (rc != STAG_OK) break;
+        const int slot = chunk & 1;
+        if (hipMemcpyAsync(const_cast<int *>(flags + slot), &st->done, sizeof(int), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipEventRecord(ev[slot], s) != hipSuccess) {
+            set_error("flag copy failed");
+            rc = STAG_EHIP;
+            break;
+        }
+        if (chunk > 0) {
+            if (hipEventSynchronize(ev[slot ^ 1]) != hipSuccess) {
+                set_error("event synchronize failed");
+                rc = STAG_EHIP;
+                break;
+            }
+            if (flags[slot ^ 1]) finished = true;
+        }
+    }
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    if (rc != STAG_OK) return rc;
+
+    // ---------------------------------------------------------------- finish
+    if (!dbl) STAG_HIP(launch_x_flush(st, hi_ptrs, lo_ptrs, n, ne, false, s));
+    for (int i = 0; i < n; ++i) {
+        STAG_HIP(true_residual(sp.x_hi[i], sp.shifts[i], nullptr, part0, nullptr));
+        STAG_HIP(launch_store_true_resid(st, i, part0, ds_grid, s));
+    }
+    STAG_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    STAG_HIP(hipStreamSynchronize(s));
+    res->status = hs.status;
+    res->iters = hs.iter;
+    res->n_reliable = hs.n_reliable;
+    for (int i = 0; i < n; ++i) {
+        res->iters_shift[i] = hs.active[i] ? hs.iter : hs.iters_shift[i];
+        res->resid_iter[i] = hs.resid_iter[i];
+        res->resid_true[i] = hs.resid_true[i];
+    }
+    return STAG_OK;
+}
+
+static stag_status status_of(int ms) {
+    switch (ms) {
+        case MS_CONVERGED: return STAG_OK;
+        case MS_BREAKDOWN: set_error("non-positive or non-finite curvature <p, A p>"); return STAG_EBREAKDOWN;
+        default: set_error("maximum number of iterations reached"); return STAG_ENOCONV;
+    }
+}
+
+// Single-shift CG from x: repeat passes until the double precision true
+// residual meets tol (one pass in double precision normally suffices; the
+// mixed pass may need a second one when the iterated and true residuals
+// drift apart near convergence).
+static stag_status cg_refine(stag_lattice *lat, double mass, double shift, const void *src, void *x, double tol,
+                             int max_iter, bool mixed, int *iters, int *n_rel, double *resid, hipStream_t s) {
+    ShiftedSolve sp;
+    void *xs[1] = {x};
+    sp.mass = mass;
+    sp.n = 1;
+    sp.shifts = &shift;
+    sp.src = src;
+    sp.x_hi = xs;
+    sp.x_init = true;
+    sp.tol = tol;
+    sp.dbl_iter = !mixed;
+    sp.reliable_every = mixed ? 100 : 0;
+    *iters = 0;
+    *n_rel = 0;
+    ShiftedResult r;
+    int ms = MS_NOCONV;
+    for (int pass = 0; pass < 6; ++pass) {
+        sp.max_iter = max_iter - *iters;
+        if (sp.max_iter <= 0) break;
+        STAG_TRY(run_shifted(lat, sp, &r, s));
+        *iters += r.iters;
+        *n_rel += r.n_reliable;
+        *resid = r.resid_true[0];
+        ms = r.status;
+        if (ms == MS_BREAKDOWN) break;
+        if (r.resid_true[0] <= tol) {
+            ms = MS_CONVERGED;
+            break;
+        }
+        ms = MS_NOCONV;
+    }
+    return status_of(ms);
+}
+
+stag_status multishift_cg(stag_lattice *lat, double mass, const double *shifts, int n, const void *src,
+                          void *const *sols, double tol, int max_iter, stag_prec prec, stag_cg_stats *stats,
+                          hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    ShiftedSolve sp;
+    sp.mass = mass;
+    sp.n = n;
+    sp.shifts = shifts;
+    sp.src = src;
+    sp.x_hi = sols;
+    sp.x_init = false;
+    sp.tol = tol;
+    sp.max_iter = max_iter;
+    sp.dbl_iter = prec == STAG_F64;
+    sp.reliable_every = prec == STAG_MIXED ? 100 : 0;
+    ShiftedResult r;
+    STAG_TRY(run_shifted(lat, sp, &r, s));
+    stag_status rc = status_of(r.status);
+    stag_cg_stats st;
+    std::memset(&st, 0, sizeof(st));
+    st.iters = r.iters;
+    st.n_reliable = r.n_reliable;
+    for (int i = 0; i < n; ++i) {
+        st.iters_shift[i] = r.iters_shift[i];
+        st.resid_iter[i] = r.resid_iter[i];
+        st.resid_true[i] = r.resid_true[i];
+        st.resid_unrefined[i] = r.resid_true[i];
+    }
+    if (prec == STAG_MIXED && rc != STAG_EBREAKDOWN) {
+        stag_status worst = STAG_OK;
+        for (int i = 0; i < n; ++i) {
+            if (st.resid_true[i] <= tol) continue;
+            int it = 0, nrel = 0;
+            double resid = st.resid_true[i];
+            stag_status ri = cg_refine(lat, mass, shifts[i], src, sols[i], tol, max_iter, true, &it, &nrel, &resid, s);
+            if (ri < 0) return ri;
+            st.refine_iters += it;
+            st.n_reliable += nrel;
+            st.resid_true[i] = resid;
+            if (ri != STAG_OK) worst = ri;
+        }
+        rc = worst;
+        if (rc != STAG_OK) status_of(rc == STAG_EBREAKDOWN ? MS_BREAKDOWN : MS_NOCONV);
+    }
+    st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = st;
+    return rc;
+}
+
+stag_status single_cg(stag_lattice *lat, double mass, double shift, const void *src, void *x, double tol,
+                      int max_iter, stag_prec prec, stag_cg_stats *stats, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    int it = 0, nrel = 0;
+    double resid = 0.0;
+    stag_status rc = cg_refine(lat, mass, shift, src, x, tol, max_iter, prec == STAG_MIXED, &it, &nrel, &resid, s);
+    if (rc < 0) return rc;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->iters = it;
+        stats->n_reliable = nrel;
+        stats->iters_shift[0] = it;
+        stats->resid_true[0] = resid;
+        stats->resid_unrefined[0] = resid;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return rc;
+}
+
+}  // namespace stag

@@ -1,0 +1,107 @@
+// Host-side internals shared by the library's translation units: the
+// lattice handle, work buffers, error reporting and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/stag.h"
+#include "geom.h"
+
+namespace stag {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+const char *last_error();
+
+#define STAG_HIP(call)                                                                       \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            ::stag::set_error(std::string(#call) + ": " + hipGetErrorString(e_));            \
+            return e_ == hipErrorOutOfMemory ? STAG_ENOMEM : STAG_EHIP;                       \
+        }                                                                                    \
+    } while (0)
+
+#define STAG_TRY(call)                                                                       \
+    do {                                                                                     \
+        stag_status s_ = (call);                                                             \
+        if (s_ != STAG_OK) return s_;                                                        \
+    } while (0)
+
+inline stag_status invalid(const std::string &msg) {
+    set_error(msg);
+    return STAG_EINVAL;
+}
+
+// ---------------------------------------------------------------- kernels
+enum DslashMode {
+    DS_PLAIN = 0,       // out = D in
+    DS_NORMAL = 1,      // out = c aux - D in
+    DS_NORMAL_DOT = 2,  // out = c aux - D in, partial[block] = sum Re<aux, out>
+    DS_RESID = 3        // r = rhs - (c aux - D in), partial[block] = sum |r|^2, out = r if non-null
+};
+
+struct DslashArgs {
+    Geom g;
+    int out_parity;
+    const void *links;   // packed links matching the precision
+    const void *in;      // opposite-parity vector
+    void *out;           // output-parity vector
+    const void *aux;     // output-parity vector (p for DS_NORMAL*, x for DS_RESID)
+    const void *rhs;     // DS_RESID: right-hand side (double)
+    double c;            // m^2 + shift
+    double *partial;     // per-block partial sums (dot modes)
+    const int *skip;     // if non-null and *skip != 0 the launch does nothing
+};
+
+constexpr int kDslashBlock = 256;
+int dslash_grid(const Geom &g, int block);
+hipError_t launch_dslash(bool dbl, int nrow, int mode, const DslashArgs &a, hipStream_t s);
+
+hipError_t launch_pack_links(const Geom &g, const void *canon, void *dst, bool dbl, int nrow, hipStream_t s);
+hipError_t launch_pack_vec(const Geom &g, const void *canon, void *dst, bool dbl, hipStream_t s);
+hipError_t launch_unpack_vec(const Geom &g, const void *src, void *canon, bool dbl, hipStream_t s);
+hipError_t launch_tables(const Geom &g, int32_t *nbr, int32_t *coord, int32_t *sign, hipStream_t s);
+
+}  // namespace stag
+
+// ---------------------------------------------------------------- handle
+enum WsSlot {
+    WS_T = 0,      // odd-parity temporary (double or float)
+    WS_T2,         // second odd temporary
+    WS_R,          // residual
+    WS_AP,         // A p
+    WS_P,          // search directions of every shift
+    WS_XLO,        // single precision solution accumulators (mixed)
+    WS_RHI,        // double precision residual (reliable updates)
+    WS_E,          // even temporary
+    WS_E2,         // second even temporary
+    WS_PART,       // reduction partials
+    WS_STATE,      // solver scalar state
+    WS_NSLOTS
+};
+
+struct stag_lattice {
+    int dims[4];
+    int antiperiodic;
+    int64_t V, Vh;
+    stag::Geom g;
+    int device;
+    int nrow;            // rows stored per link (3 or 2), 0 before stag_links_set
+    void *links64;
+    void *links32;
+    void *ws[WS_NSLOTS];
+    size_t ws_bytes[WS_NSLOTS];
+    int *host_flags;     // pinned host mirror of solver flags
+};
+
+namespace stag {
+
+// Work buffer of at least `bytes` bytes in slot `slot` (grown on demand).
+stag_status ws_get(stag_lattice *lat, int slot, size_t bytes, void **out);
+
+inline int64_t vec_bytes(const stag_lattice *lat, bool dbl) { return (dbl ? 48 : 24) * lat->Vh; }
+
+}  // namespace stag

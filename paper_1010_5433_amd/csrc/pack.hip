@@ -1,0 +1,110 @@
+// Layout conversion (set-up, not in the solver loop) and the geometry-table
+// export used to check the device index functions.
+#include "internal.h"
+#include "links.h"
+
+namespace stag {
+
+constexpr int kPackBlock = 256;
+
+// Canonical complex128 (4,V,3,3) [mu][lex][row][col] -> packed even/odd SoA.
+template <typename R, int NROW>
+__global__ void __launch_bounds__(kPackBlock) k_pack_links(Geom g, const double2 *canon, void *dst) {
+    const int64_t vol = 2 * (int64_t)g.Vh;
+    const int64_t k = (int64_t)blockIdx.x * kPackBlock + threadIdx.x;
+    if (k >= 4 * vol) return;
+    const int mu = (int)(k / vol);
+    const int64_t lex = k - mu * vol;
+    int64_t r = lex;
+    int x[4];
+    for (int nu = 0; nu < 4; ++nu) {
+        x[nu] = (int)(r % g.L[nu]);
+        r /= g.L[nu];
+    }
+    const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+    su3<R> u;
+    const double2 *src = canon + k * 9;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        const double2 v = src[e];
+        u.e[e / 3][e % 3] = {R(v.x), R(v.y)};
+    }
+    LinkLayout<R, NROW>::store(dst, g.Vh, p * 4 + mu, lex >> 1, u);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kPackBlock) k_pack_vec(int vh, const double2 *canon, void *dst) {
+    const int i = blockIdx.x * kPackBlock + threadIdx.x;
+    if (i >= vh) return;
+    vec3<R> v;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double2 z = canon[(int64_t)i * 3 + c];
+        v.c[c] = {R(z.x), R(z.y)};
+    }
+    store_vec<R>(dst, vh, i, v);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kPackBlock) k_unpack_vec(int vh, const void *src, double2 *canon) {
+    const int i = blockIdx.x * kPackBlock + threadIdx.x;
+    if (i >= vh) return;
+    const vec3<R> v = load_vec<R>(src, vh, i);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) canon[(int64_t)i * 3 + c] = make_double2(double(v.c[c].re), double(v.c[c].im));
+}
+
+__global__ void __launch_bounds__(kPackBlock) k_tables(Geom g, int32_t *nbr, int32_t *coord, int32_t *sign) {
+    const int k = blockIdx.x * kPackBlock + threadIdx.x;
+    if (k >= 2 * g.Vh) return;
+    const int p = k / g.Vh, i = k - p * g.Vh;
+    int x[4];
+    site_coords(g, p, i, x);
+    for (int mu = 0; mu < 4; ++mu) {
+        if (nbr) {
+            nbr[(int64_t)(p * 8 + mu) * g.Vh + i] = site_nbr(g, i, x, mu, +1);
+            nbr[(int64_t)(p * 8 + 4 + mu) * g.Vh + i] = site_nbr(g, i, x, mu, -1);
+        }
+        if (sign) {
+            sign[(int64_t)(p * 8 + mu) * g.Vh + i] = fwd_sign(g, x, mu);
+            sign[(int64_t)(p * 8 + 4 + mu) * g.Vh + i] = bwd_sign(g, x, mu);
+        }
+        if (coord) coord[((int64_t)p * g.Vh + i) * 4 + mu] = x[mu];
+    }
+}
+
+static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kPackBlock - 1) / kPackBlock); }
+
+hipError_t launch_pack_links(const Geom &g, const void *canon, void *dst, bool dbl, int nrow, hipStream_t s) {
+    const int64_t n = 8 * (int64_t)g.Vh;
+    const double2 *c = static_cast<const double2 *>(canon);
+    if (dbl) {
+        if (nrow == 2) hipLaunchKernelGGL((k_pack_links<double, 2>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
+        else hipLaunchKernelGGL((k_pack_links<double, 3>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
+    } else {
+        if (nrow == 2) hipLaunchKernelGGL((k_pack_links<float, 2>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
+        else hipLaunchKernelGGL((k_pack_links<float, 3>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_vec(const Geom &g, const void *canon, void *dst, bool dbl, hipStream_t s) {
+    const double2 *c = static_cast<const double2 *>(canon);
+    if (dbl) hipLaunchKernelGGL((k_pack_vec<double>), dim3(blocks_for(g.Vh)), dim3(kPackBlock), 0, s, g.Vh, c, dst);
+    else hipLaunchKernelGGL((k_pack_vec<float>), dim3(blocks_for(g.Vh)), dim3(kPackBlock), 0, s, g.Vh, c, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_vec(const Geom &g, const void *src, void *canon, bool dbl, hipStream_t s) {
+    double2 *c = static_cast<double2 *>(canon);
+    if (dbl) hipLaunchKernelGGL((k_unpack_vec<double>), dim3(blocks_for(g.Vh)), dim3(kPackBlock), 0, s, g.Vh, src, c);
+    else hipLaunchKernelGGL((k_unpack_vec<float>), dim3(blocks_for(g.Vh)), dim3(kPackBlock), 0, s, g.Vh, src, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_tables(const Geom &g, int32_t *nbr, int32_t *coord, int32_t *sign, hipStream_t s) {
+    hipLaunchKernelGGL(k_tables, dim3(blocks_for(2 * (int64_t)g.Vh)), dim3(kPackBlock), 0, s, g, nbr, coord, sign);
+    return hipGetLastError();
+}
+
+}  // namespace stag

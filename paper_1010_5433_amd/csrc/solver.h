@@ -1,0 +1,76 @@
+// Device-resident state of the shifted CG and the launchers of the solver
+// kernels.  All scalars of the recursion live in device memory and are
+// updated by single-wave kernels, so an iteration needs no host round trip.
+#pragma once
+
+#include "internal.h"
+
+namespace stag {
+
+constexpr int kMaxShifts = STAG_MAX_SHIFTS;
+constexpr int kBlasBlock = 256;
+constexpr int kMaxBlasGrid = 8192;
+constexpr int kMaxPartials = 16384;
+
+enum MsStatus { MS_RUNNING = 0, MS_NOCONV = 1, MS_BREAKDOWN = 2, MS_CONVERGED = 3 };
+
+struct MsState {
+    double rho;          // <r, r>
+    double alpha, alpha_prev, beta, beta_prev;
+    double bnorm2;       // ||b||^2 of the reference right-hand side
+    double tol;          // relative tolerance
+    double scratch[4];   // reduced values handed to the host
+    int n, base;
+    int iter, max_iter;
+    int done;            // set once the solve ended: later kernels are no-ops
+    int status;          // MsStatus
+    int upd_valid;       // the shift-update kernel applies this iteration
+    int upd_p;           // the base direction is updated this iteration
+    int n_reliable;
+    int pad[3];
+    double shift_rel[kMaxShifts];   // s_i = sigma_i - sigma_base
+    double zeta[kMaxShifts], zeta_prev[kMaxShifts], zeta_next[kMaxShifts];
+    double a[kMaxShifts], b[kMaxShifts];
+    double resid_iter[kMaxShifts];
+    double resid_true[kMaxShifts];
+    int active[kMaxShifts];
+    int upd[kMaxShifts];
+    int iters_shift[kMaxShifts];
+};
+
+// Pointers to the per-shift vectors, passed by value.
+struct ShiftPtrs {
+    void *x[kMaxShifts];
+    void *p[kMaxShifts];
+};
+
+int blas_grid(int64_t n_elems);
+
+// ||v||^2 partials of a library vector (n_elems complex entries).
+hipError_t launch_norm2(bool dbl, const void *v, int64_t n, double *partial, int grid, hipStream_t s);
+// dst[k] = src[k] (+ dst zero for every x) : multi-shift start x_i = 0, p_i = b, r = b
+hipError_t launch_ms_start(bool dbl, const double2 *b, void *r, ShiftPtrs ptrs, int n_shift, bool zero_x,
+                           int64_t n, hipStream_t s);
+hipError_t launch_scalar_init(MsState *st, const double *partial_r, int nparts_r, const double *partial_b,
+                              int nparts_b, hipStream_t s);
+hipError_t launch_scalar_alpha(MsState *st, const double *partial, int nparts, hipStream_t s);
+hipError_t launch_r_update(bool dbl, MsState *st, void *r, const void *ap, int64_t n, double *partial, int grid,
+                           hipStream_t s);
+hipError_t launch_scalar_beta(MsState *st, const double *partial, int nparts, hipStream_t s);
+hipError_t launch_shift_update(bool dbl, MsState *st, const void *r, ShiftPtrs ptrs, int n_shift, int64_t n,
+                               int grid, hipStream_t s);
+// x_hi += x_lo; x_lo = 0 for every shift (single precision accumulators).
+hipError_t launch_x_flush(MsState *st, ShiftPtrs hi, ShiftPtrs lo, int n_shift, int64_t n, bool skip_on_done,
+                          hipStream_t s);
+// dst (float) = src (double), skipped when the solve is done.
+hipError_t launch_demote(MsState *st, const double2 *src, float2 *dst, int64_t n, hipStream_t s);
+// After a reliable update: rho = sum(partial), count it.
+hipError_t launch_scalar_reliable(MsState *st, const double *partial, int nparts, hipStream_t s);
+// st->scratch[slot] = sum(partial)
+hipError_t launch_reduce_to(MsState *st, int slot, const double *partial, int nparts, hipStream_t s);
+// st->resid_true[i] = sqrt(sum(partial) / bnorm2)
+hipError_t launch_store_true_resid(MsState *st, int i, const double *partial, int nparts, hipStream_t s);
+// r = b - Ax computed elsewhere in double; copy r into a float/double residual and set directions p = r
+hipError_t launch_restart(bool dbl, const double2 *rhi, void *r, void *p, int64_t n, hipStream_t s);
+
+}  // namespace stag

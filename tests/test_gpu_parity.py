@@ -1,0 +1,290 @@
+"""Parity of the HIP path (called through the C ABI) with the FP64 oracle.
+
+Tolerances (derived from the arithmetic; the problem fixes 1e-10 for the
+solver):
+  * tables: bit-exact.
+  * FP64 half Dslash: each output is a sum of 8 products of unit-norm
+    links with the input; with a different summation order and FMA
+    contraction the rounding differs by a few ulp of the inputs, so
+    ||gpu - orc|| / ||orc|| <= 1e-14.
+  * FP32 half Dslash vs the FP64 oracle: inputs and links rounded to single
+    (2^-24 relative each) plus ~8 rounded terms: <= 3e-7 norm-relative.
+  * solvers: the FP64 true relative residual of every shift, computed by the
+    ORACLE's operator on the GPU's solution, <= 1e-10 (the requested tol);
+    solutions agree with the oracle's within kappa_i * 2e-10.
+"""
+import numpy as np
+import pytest
+
+import stag_synth as syn
+from tests import lattice_np as ln
+from tests.gpu_common import lattice_with_links, links_np, log, pack, rel, to_dev, unpack
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [(2, 2, 2, 2), (4, 4, 4, 4), (4, 2, 2, 4), (6, 4, 2, 8), (2, 6, 4, 2)]
+FULL = [(32, 32, 32, 8), (32, 32, 32, 32)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1010_5433_amd  # noqa: F401  (fails loudly if the library is missing)
+
+
+@pytest.mark.parametrize("dims", SMALL + FULL)
+@pytest.mark.parametrize("antiperiodic", [True, False])
+def test_tables_bit_exact(orc, dims, antiperiodic):
+    import paper_1010_5433_amd as stag
+    log(f"tables {dims} ap={antiperiodic}")
+    lat = stag.Lattice(dims, antiperiodic)
+    nbr, coord, sign = lat.tables()
+    onbr, ocoord, osign = orc.tables(dims, antiperiodic)
+    assert np.array_equal(nbr.cpu().numpy(), onbr)
+    assert np.array_equal(coord.cpu().numpy(), ocoord)
+    assert np.array_equal(sign.cpu().numpy(), osign)
+
+
+@pytest.mark.parametrize("dims", SMALL + FULL)
+@pytest.mark.parametrize("fmt", ["18", "12"])
+def test_dslash_f64(orc, dims, fmt):
+    log(f"dslash f64 {dims} fmt={fmt}")
+    U = links_np(dims, "haar" if np.prod(dims) < 4096 else "smooth", 0.5, 11)
+    lat = lattice_with_links(dims, U, fmt)
+    rng = np.random.default_rng(5)
+    vh = int(np.prod(dims)) // 2
+    for out_parity in (0, 1):
+        v = rng.standard_normal((vh, 3)) + 1j * rng.standard_normal((vh, 3))
+        got = unpack(lat, lat.dslash_eo(out_parity, pack(lat, v)))
+        want = orc.dslash_eo(dims, U, out_parity, v)
+        assert rel(got, want) <= 1e-14, (out_parity, rel(got, want))
+
+
+@pytest.mark.parametrize("dims", SMALL + FULL)
+@pytest.mark.parametrize("fmt", ["18", "12"])
+def test_dslash_f32(orc, dims, fmt):
+    log(f"dslash f32 {dims} fmt={fmt}")
+    U = links_np(dims, "haar" if np.prod(dims) < 4096 else "smooth", 0.5, 11)
+    lat = lattice_with_links(dims, U, fmt)
+    rng = np.random.default_rng(6)
+    vh = int(np.prod(dims)) // 2
+    for out_parity in (0, 1):
+        v = rng.standard_normal((vh, 3)) + 1j * rng.standard_normal((vh, 3))
+        got = unpack(lat, lat.dslash_eo(out_parity, pack(lat, v, "f32")))
+        want = orc.dslash_eo(dims, U, out_parity, v)
+        assert rel(got, want) <= 3e-7, (out_parity, rel(got, want))
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 8), (32, 32, 32, 32)])
+def test_free_field_plane_wave_on_gpu(dims):
+    """M psi = (m^2 + sum sin^2 p) psi for plane waves: a closed form that
+    holds at any size, checked at the full 32^4 shape."""
+    log(f"free field {dims}")
+    U = ln.free_links(dims)
+    lat = lattice_with_links(dims, U, "12")
+    rng = np.random.default_rng(2)
+    m = 0.01
+    for _ in range(3):
+        n = [int(rng.integers(0, d)) for d in dims]
+        colour = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+        full, p = ln.plane_wave(dims, n, colour)
+        psi = ln.restrict(dims, 0, full)
+        lam = m * m + np.sum(np.sin(p) ** 2)
+        got = unpack(lat, lat.normal_op(m, 0.0, pack(lat, psi)))
+        assert rel(got, lam * psi) <= 1e-14
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 8), (32, 32, 32, 8)])
+@pytest.mark.parametrize("fmt", ["18", "12"])
+def test_normal_op(orc, dims, fmt):
+    log(f"normal op {dims} fmt={fmt}")
+    U = links_np(dims, "smooth", 0.5, 3)
+    lat = lattice_with_links(dims, U, fmt)
+    v = syn.gaussian_source(dims, 4)
+    got = unpack(lat, lat.normal_op(0.02, 0.3, pack(lat, v)))
+    want = orc.normal_op(dims, U, 0.02, 0.3, v)
+    assert rel(got, want) <= 1e-14
+
+
+def test_vec_pack_roundtrip():
+    import torch
+    log("pack roundtrip")
+    dims = (4, 2, 6, 2)
+    lat = lattice_with_links(dims, ln.free_links(dims))
+    v = syn.gaussian_source(dims, 1)
+    back = unpack(lat, pack(lat, v))
+    assert np.array_equal(back, v)
+    back32 = unpack(lat, pack(lat, v, "f32"))
+    assert np.array_equal(back32, v.real.astype(np.float32) + 1j * v.imag.astype(np.float32))
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------- solvers
+
+def _solve(lat, mass, shifts, b, prec="f64", tol=1e-10, max_iter=100000):
+    import torch
+    src = pack(lat, b)
+    sols, rc, st = lat.multishift_cg(mass, shifts, src, tol=tol, max_iter=max_iter, prec=prec)
+    torch.cuda.synchronize()
+    return [unpack(lat, x) for x in sols], rc, st
+
+
+def test_multishift_config1_vs_oracle(orc):
+    """4^4 Haar, m = 0.1, 8 shifts log-spaced in [1e-4, 1], tol 1e-10, FP64."""
+    c = syn.config("c1_4x4x4x4_haar")
+    log("multishift config 1")
+    U = syn.make_links(c["links"], c["dims"])
+    b = syn.gaussian_source(c["dims"], c["source_seed"])
+    shifts = syn.logspace_shifts(*c["shifts"])
+    xo, rco, io = orc.multishift_cg(c["dims"], U, c["mass"], shifts, b, tol=c["tol"])
+    for fmt in ("18", "12"):
+        lat = lattice_with_links(c["dims"], U, fmt)
+        xs, rc, st = _solve(lat, c["mass"], shifts, b)
+        assert rc == 0
+        assert abs(st["iters"] - io["iters"]) <= 1
+        for i, s in enumerate(shifts):
+            r_orc = orc.true_residual(c["dims"], U, c["mass"], s, b, xs[i])
+            assert r_orc <= 1e-10, (i, r_orc)
+            assert abs(st["resid_true"][i] - r_orc) <= 1e-3 * r_orc + 1e-16
+            assert abs(st["iters_shift"][i] - io["iters_shift"][i]) <= 1
+            assert rel(xs[i], xo[i]) <= 2e-8  # kappa <= ~1e3 here
+
+
+@pytest.mark.parametrize("dims,seed", [((2, 2, 2, 2), 1), ((6, 4, 2, 8), 9)])
+def test_multishift_small_vs_oracle_and_dense(orc, dims, seed):
+    log(f"multishift small {dims}")
+    U = syn.haar_links(dims, seed)
+    b = syn.gaussian_source(dims, seed + 1)
+    shifts = np.array([0.5, 0.0, 1e-3, 0.5, 7.0])   # unsorted, duplicate, zero
+    lat = lattice_with_links(dims, U)
+    xs, rc, st = _solve(lat, 0.1, shifts, b)
+    assert rc == 0
+    vh = int(np.prod(dims)) // 2
+    M = ln.dense_normal_matrix(lambda v: orc.normal_op(dims, U, 0.1, 0.0, v), 3 * vh)
+    for i, s in enumerate(shifts):
+        A = M + s * np.eye(3 * vh)
+        xd = np.linalg.solve(A, b.ravel())
+        r = np.linalg.norm(b.ravel() - A @ xs[i].ravel()) / np.linalg.norm(b)
+        assert r <= 1e-10
+        ev = np.linalg.eigvalsh(A)
+        assert rel(xs[i].ravel(), xd) <= 2 * (ev[-1] / ev[0]) * 1e-10
+
+
+def test_multishift_config2_full_size(orc):
+    """32^3x8 smoothed links, m = 0.02, 12 shifts in [1e-5, 2]: every shift's
+    FP64 true residual, computed by the oracle's operator, <= 1e-10."""
+    c = syn.config("c2_32x32x32x8_smooth")
+    log("multishift config 2 (32^3x8)")
+    U = syn.make_links(c["links"], c["dims"])
+    b = syn.gaussian_source(c["dims"], c["source_seed"])
+    shifts = syn.logspace_shifts(*c["shifts"])
+    lat = lattice_with_links(c["dims"], U)
+    xs, rc, st = _solve(lat, c["mass"], shifts, b)
+    log(f"  iters {st['iters']} seconds {st['seconds']:.3f}")
+    assert rc == 0
+    for i, s in enumerate(shifts):
+        r = orc.true_residual(c["dims"], U, c["mass"], s, b, xs[i])
+        assert r <= 1e-10, (i, s, r)
+        assert abs(st["resid_true"][i] - r) <= 1e-3 * r + 1e-16
+    # iterations are monotone in the shift: larger shifts freeze earlier
+    its = np.array(st["iters_shift"])
+    assert np.all(np.diff(its) <= 0)
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_multishift_config3_full_size(orc, prec):
+    """32^4 smoothed links, m = 0.01, 16 shifts in [1e-6, 4]."""
+    c = syn.config("c3_32x32x32x32_smooth")
+    log(f"multishift config 3 (32^4) prec={prec}")
+    U = links_np(c["dims"], "smooth", c["links"][1], c["links"][2])
+    b = syn.gaussian_source(c["dims"], c["source_seed"])
+    shifts = syn.logspace_shifts(*c["shifts"])
+    lat = lattice_with_links(c["dims"], U)
+    xs, rc, st = _solve(lat, c["mass"], shifts, b, prec=prec)
+    log(f"  iters {st['iters']} refine {st['refine_iters']} reliable {st['n_reliable']} "
+        f"seconds {st['seconds']:.3f}")
+    log(f"  unrefined {np.array(st['resid_unrefined'])}")
+    assert rc == 0
+    for i in (0, 5, 10, 15):
+        r = orc.true_residual(c["dims"], U, c["mass"], shifts[i], b, xs[i])
+        assert r <= 1e-10, (i, r)
+    assert max(st["resid_true"]) <= 1e-10
+
+
+def test_multishift_deterministic():
+    import torch
+    log("determinism")
+    dims = (8, 8, 8, 8)
+    U = links_np(dims, "smooth", 0.5, 7)
+    lat = lattice_with_links(dims, U)
+    src = pack(lat, syn.gaussian_source(dims, 8))
+    shifts = [0.0, 0.01, 0.1]
+    a, _, sa = lat.multishift_cg(0.05, shifts, src)
+    b, _, sb = lat.multishift_cg(0.05, shifts, src)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    assert sa["resid_true"] == sb["resid_true"]
+
+
+def test_multishift_f32_floor_and_mixed_refinement(orc):
+    """Single precision alone stalls far above 1e-10 (Section 6 quotes a
+    10^-2..10^-3 floor for its ensembles); reliable updates plus refinement
+    reach the FP64 target."""
+    log("f32 floor vs mixed")
+    dims = (16, 16, 16, 16)
+    U = links_np(dims, "smooth", 0.5, 21)
+    b = syn.gaussian_source(dims, 22)
+    shifts = [0.0, 1e-3, 0.1]
+    lat = lattice_with_links(dims, U)
+    xs, rc32, st32 = _solve(lat, 0.02, shifts, b, prec="f32", max_iter=4000)
+    assert min(st32["resid_true"]) > 1e-8
+    xs, rcm, stm = _solve(lat, 0.02, shifts, b, prec="mixed")
+    assert rcm == 0
+    for i, s in enumerate(shifts):
+        assert orc.true_residual(dims, U, 0.02, s, b, xs[i]) <= 1e-10
+
+
+def test_single_cg_from_guess(orc):
+    import torch
+    log("single cg")
+    dims = (8, 8, 8, 4)
+    U = links_np(dims, "smooth", 0.5, 31)
+    b = syn.gaussian_source(dims, 32)
+    lat = lattice_with_links(dims, U)
+    src = pack(lat, b)
+    for prec in ("f64", "mixed"):
+        x = pack(lat, 0.1 * syn.gaussian_source(dims, 33))
+        x, rc, st = lat.cg(0.05, 0.02, src, x, prec=prec)
+        torch.cuda.synchronize()
+        assert rc == 0
+        assert orc.true_residual(dims, U, 0.05, 0.02, b, unpack(lat, x)) <= 1e-10
+
+
+def test_solver_edge_cases():
+    import torch
+    import paper_1010_5433_amd as stag
+    log("edge cases")
+    dims = (4, 4, 4, 4)
+    lat = lattice_with_links(dims, syn.haar_links(dims, 1))
+    zero = pack(lat, np.zeros((128, 3), np.complex128))
+    sols, rc, st = lat.multishift_cg(0.1, [0.0, 0.5], zero)
+    torch.cuda.synchronize()
+    assert rc == 0 and st["iters"] == 0
+    assert all(float(x.abs().max()) == 0.0 for x in sols)
+    src = pack(lat, syn.gaussian_source(dims, 2))
+    sols, rc, st = lat.multishift_cg(0.1, [0.0], src, max_iter=3)
+    assert rc == stag._abi.STAG_ENOCONV and st["iters"] == 3
+    with pytest.raises(stag.StagError):
+        lat.multishift_cg(-0.1, [0.0], src)
+    with pytest.raises(stag.StagError):
+        lat.multishift_cg(0.1, [-1.0], src)
+    with pytest.raises(stag.StagError):
+        lat.multishift_cg(0.1, [0.0] * 65, src)
+    with pytest.raises(stag.StagError):
+        lat.dslash_eo(0, src, src)
+    bad = pack(lat, np.full((128, 3), np.nan + 0j))
+    sols, rc, st = lat.multishift_cg(0.1, [0.0], bad)
+    assert rc == stag._abi.STAG_EBREAKDOWN
