@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Benchmark: multi-shift CG time-to-solution at 1e-10 relative residual
+on the 32^4 lattice (smoothed links, m = 0.01, 16 shifts in [1e-6, 4]),
+plus the HBM roofline of the dominant kernel and the FP64 CPU oracle timed
+on the host beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec mixed|f64|f32]
+
+One step = one full multi-shift solve (all shifts to FP64 true relative
+residual <= 1e-10, including the final true-residual check), with the gauge
+field and the source already resident in HBM.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ["paper_1010_5433_amd/csrc/dslash.hip", "paper_1010_5433_amd/csrc/common.h",
+                  "paper_1010_5433_amd/csrc/links.h", "paper_1010_5433_amd/csrc/geom.h",
+                  "paper_1010_5433_amd/csrc/blas.hip"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def dslash_bytes_per_site(dbl: bool, nrow: int, mode: str = "plain") -> int:
+    """Minimum unique HBM traffic of one half-Dslash per output site: all 8
+    links once, the input vector once (neighbours re-read from cache), the
+    output once; the normal-operator epilogue also reads p."""
+    bl = (16 if dbl else 8) * 3 * nrow
+    bv = 48 if dbl else 24
+    return 8 * bl + (3 if mode == "epilogue" else 2) * bv
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(PROFILES, "dslash_traffic_32x32x32x32.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    key = f"traffic_bytes_per_launch[{kernel}]"
+    return float(vals[key]) if key in vals else None
+
+
+def time_dslash(lat, prec, n_warm=5, n_time=50):
+    """Average duration of one half-Dslash launch, HIP events on the stream
+    the library launches on (torch's current stream)."""
+    import torch
+    vh = lat.Vh
+    dt = torch.float64 if prec == "f64" else torch.float32
+    x = torch.randn((3, vh, 2), dtype=dt, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(n_warm):
+        lat.dslash_eo(0, x, y)
+        lat.dslash_eo(1, y, x)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for k in range(n_time):
+        if k & 1:
+            lat.dslash_eo(1, y, x)
+        else:
+            lat.dslash_eo(0, x, y)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / n_time * 1e-3
+
+
+def cpu_baseline(dims, U, b, mass, shifts, gpu_iters, sample_iters):
+    """The FP64 oracle as it stands, on the host cores: the first
+    `sample_iters` iterations of the same solve, scaled to the GPU's
+    iteration count (every shift is still active in the sample, so the
+    extrapolation is an upper bound of the oracle's time to solution)."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    os.environ.setdefault("OMP_NUM_THREADS", str(cores))
+    threads = int(os.environ["OMP_NUM_THREADS"])
+    oracle.default()
+    t0 = time.perf_counter()
+    oracle.multishift_cg(dims, U, mass, shifts, b, tol=1e-10, max_iter=sample_iters)
+    dt = time.perf_counter() - t0
+    per_iter = dt / sample_iters
+    return dict(value=round(per_iter * gpu_iters, 3), unit="s", cores=threads, kind="oracle",
+                sample=f"first {sample_iters} multi-shift iterations of the same 32^4 solve "
+                       f"({dt:.1f} s incl. 16 final true residuals), scaled by the GPU's "
+                       f"{gpu_iters} iterations; {per_iter * 1e3:.1f} ms per iteration")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="mixed", choices=["mixed", "f64", "f32"])
+    ap.add_argument("--fmt", default="18", choices=["18", "12"])
+    ap.add_argument("--cpu-sample-iters", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f64-reference", action="store_true")
+    ap.add_argument("--only-dslash", type=int, default=0,
+                    help="profiling aid: run N half-Dslash launches of the bench's precision and exit")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU decomposition is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1010_5433_amd as stag
+    import stag_synth as syn
+
+    c = syn.config("c3_32x32x32x32_smooth")
+    dims, mass, tol = c["dims"], c["mass"], c["tol"]
+    shifts = syn.logspace_shifts(*c["shifts"])
+    log(f"generating 32^4 smoothed links (seed {c['links'][2]})")
+    U = syn.make_links(c["links"], dims)
+    b = syn.gaussian_source(dims, c["source_seed"])
+    torch.cuda.set_device(0)
+    lat = stag.Lattice(dims)
+    lat.set_links(torch.from_numpy(U).cuda(), args.fmt)
+    src = lat.pack(torch.from_numpy(b).cuda())
+    sols = [torch.empty_like(src) for _ in shifts]
+    torch.cuda.synchronize()
+
+    it_prec = "f64" if args.prec == "f64" else "f32"
+    if args.only_dslash:
+        log(f"profiling aid: {args.only_dslash} half-Dslash launches ({it_prec}, {args.fmt}-real)")
+        time_dslash(lat, it_prec, n_warm=2, n_time=args.only_dslash)
+        x = torch.empty(256 << 20, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)  # 2 GiB read + 2 GiB write: calibrates the byte counters
+        torch.cuda.synchronize()
+        log("done")
+        return
+
+    def solve(prec):
+        out, rc, st = lat.multishift_cg(mass, shifts, src, sols=sols, tol=tol, prec=prec)
+        if rc != 0 or max(st["resid_true"]) > tol:
+            raise RuntimeError(f"solve failed: rc={rc} resid={max(st['resid_true']):.3e}")
+        return st
+
+    for w in range(args.warmup):
+        st = solve(args.prec)
+        log(f"warmup {w}: {st['iters']} iters + {st['refine_iters']} refine, {st['seconds']:.3f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(args.steps):
+        stats.append(solve(args.prec))
+        log(f"step {k}: {stats[-1]['iters']} iters + {stats[-1]['refine_iters']} refine, "
+            f"{stats[-1]['seconds']:.3f} s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tts = elapsed / args.steps
+    st = stats[-1]
+
+    extra = {}
+    if args.prec != "f64" and not args.no_f64_reference:
+        st64 = solve("f64")
+        log(f"f64 reference: {st64['iters']} iters, {st64['seconds']:.3f} s")
+        extra["f64_tts_s"] = round(st64["seconds"], 4)
+        extra["f64_iters"] = st64["iters"]
+
+    # ---- roofline of the dominant kernel: the half-Dslash in the step's precision
+    dbl = it_prec == "f64"
+    nrow = 3 if args.fmt == "18" else 2
+    sec = time_dslash(lat, it_prec)
+    algo = dslash_bytes_per_site(dbl, nrow) * lat.Vh
+    achieved = algo / sec / 1e9
+    kname = f"k_dslash<{'double' if dbl else 'float'},{nrow},PLAIN>"
+    traffic = read_traffic(kname)
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                kernel=kname, bytes_per_launch=algo, avg_launch_us=round(sec * 1e6, 2))
+    # the other precision/format pairs, for the record
+    dsl = {}
+    for p in ("f64", "f32"):
+        d = p == "f64"
+        s = time_dslash(lat, p)
+        gbs = dslash_bytes_per_site(d, nrow) * lat.Vh / s / 1e9
+        dsl[f"{p}_{args.fmt}"] = dict(us=round(s * 1e6, 2), GBs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+    log(f"dslash: {dsl}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle, first {args.cpu_sample_iters} iterations")
+        cpu = cpu_baseline(dims, U, b, mass, shifts, st["iters"] + st["refine_iters"], args.cpu_sample_iters)
+
+    out = {
+        "metric": "multi-shift CG time-to-solution @1e-10 rel resid; Dslash HBM GB/s (% of peak)",
+        "value": round(tts, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(tts * 1e3, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"mixed": "f32+f64", "f64": "f64", "f32": "f32"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": "32^4 smoothed SU(3) links (eps 0.5, seed 301), m=0.01, "
+                               "16 shifts logspace[1e-6,4], 1 Gaussian source (seed 302), tol 1e-10",
+                   "lattice": list(dims), "mass": mass, "n_shifts": len(shifts), "tol": tol,
+                   "precision": args.prec, "links": f"{args.fmt}-real", "parallelism": "single GPU"},
+        "iters": st["iters"],
+        "refine_iters": st["refine_iters"],
+        "n_reliable": st["n_reliable"],
+        "max_resid_true": max(st["resid_true"]),
+        "max_resid_unrefined": max(st["resid_unrefined"]),
+        "resid_unrefined": [float(f"{v:.3g}") for v in st["resid_unrefined"]],
+        "refine_iters_shift": st["refine_iters_shift"],
+        "iters_shift": st["iters_shift"],
+        "roofline": roof,
+        "dslash": dsl,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -85,6 +85,7 @@ typedef struct {
     double resid_iter[STAG_MAX_SHIFTS];     /* iterated |zeta_i| ||r|| / ||b|| at freeze */
     double resid_true[STAG_MAX_SHIFTS];     /* FP64 ||b - (M+sigma_i) x_i|| / ||b|| at exit */
     double resid_unrefined[STAG_MAX_SHIFTS];/* STAG_MIXED: FP64 true residual before refinement */
+    int refine_iters_shift[STAG_MAX_SHIFTS];/* STAG_MIXED: refinement iterations of shift i */
     double seconds;                         /* wall time of the call */
 } stag_cg_stats;
 

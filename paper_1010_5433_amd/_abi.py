@@ -35,6 +35,7 @@ class CgStats(ctypes.Structure):
         ("resid_iter", ctypes.c_double * MAX_SHIFTS),
         ("resid_true", ctypes.c_double * MAX_SHIFTS),
         ("resid_unrefined", ctypes.c_double * MAX_SHIFTS),
+        ("refine_iters_shift", ctypes.c_int * MAX_SHIFTS),
         ("seconds", ctypes.c_double),
     ]
 
@@ -43,7 +44,8 @@ class CgStats(ctypes.Structure):
                     fallback_used=self.fallback_used,
                     iters_shift=list(self.iters_shift[:n]), resid_iter=list(self.resid_iter[:n]),
                     resid_true=list(self.resid_true[:n]),
-                    resid_unrefined=list(self.resid_unrefined[:n]), seconds=self.seconds)
+                    resid_unrefined=list(self.resid_unrefined[:n]),
+                    refine_iters_shift=list(self.refine_iters_shift[:n]), seconds=self.seconds)
 
 
 _v, _i, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double

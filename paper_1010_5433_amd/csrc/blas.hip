@@ -17,6 +17,7 @@
 #include <math.h>
 
 #include "common.h"
+#include "ms_device.h"
 #include "solver.h"
 
 namespace stag {
@@ -203,102 +204,46 @@ __global__ void __launch_bounds__(kWave) k_scalar_init(MsState *st, const double
     }
 }
 
-__global__ void __launch_bounds__(kWave) k_scalar_alpha(MsState *st, const double *partial, int nparts) {
-    const int l = threadIdx.x;
-    if (st->done) {
-        if (l == 0) st->upd_valid = 0;
-        return;
-    }
-    const double pap = sum_partials(partial, nparts);
-    if (!(pap > 0.0) || !isfinite(pap)) {
-        if (l == 0) {
-            st->status = MS_BREAKDOWN;
-            st->done = 1;
-            st->upd_valid = 0;
-        }
-        return;
-    }
-    const double alpha = st->rho / pap;
-    if (l < st->n && st->active[l]) {
-        if (l == st->base) {
-            st->zeta_next[l] = 1.0;
-        } else {
-            const double z = st->zeta[l], zp = st->zeta_prev[l];
-            const double den = alpha * st->beta_prev * (zp - z) + zp * st->alpha_prev * (1.0 + st->shift_rel[l] * alpha);
-            st->zeta_next[l] = z * zp * st->alpha_prev / den;
-        }
-    }
-    if (l == 0) st->alpha = alpha;
-}
-
-__global__ void __launch_bounds__(kWave) k_scalar_beta(MsState *st, const double *partial, int nparts) {
-    if (st->done) return;
-    const int l = threadIdx.x;
-    const double rho_new = sum_partials(partial, nparts);
-    const double beta = rho_new / st->rho;
-    const double alpha = st->alpha;
-    const int it = st->iter + 1;
-    bool act = false;
-    if (l < st->n) {
-        const bool was = st->active[l] != 0;
-        st->upd[l] = was ? 1 : 0;
-        if (was) {
-            const double zn = st->zeta_next[l];
-            const double ratio = zn / st->zeta[l];
-            st->a[l] = alpha * ratio;
-            st->b[l] = beta * ratio * ratio;
-            const double res = fabs(zn) * sqrt(rho_new / st->bnorm2);
-            st->resid_iter[l] = res;
-            if (res <= st->tol) {
-                st->active[l] = 0;
-                st->iters_shift[l] = it;
-            } else {
-                act = true;
-            }
-            st->zeta_prev[l] = st->zeta[l];
-            st->zeta[l] = zn;
-        }
-    }
-    const unsigned long long any = __ballot(act);
-    const int upd_base = __shfl(l < st->n ? st->upd[l] : 0, st->base);
-    if (l == 0) {
-        st->upd_p = (upd_base || any) ? 1 : 0;
-        st->beta = beta;
-        st->beta_prev = beta;
-        st->alpha_prev = alpha;
-        st->rho = rho_new;
-        st->iter = it;
-        st->upd_valid = 1;
-        if (!any) {
-            st->done = 1;
-            st->status = MS_CONVERGED;
-        } else if (it >= st->max_iter) {
-            st->done = 1;
-            st->status = MS_NOCONV;
-        }
-    }
-}
-
-__global__ void __launch_bounds__(kWave) k_scalar_reliable(MsState *st, const double *partial, int nparts) {
-    if (st->done) return;
-    const double rho = sum_partials(partial, nparts);
-    if (threadIdx.x == 0) {
-        st->rho = rho;
-        st->n_reliable += 1;
-    }
-}
-
 __global__ void __launch_bounds__(kWave) k_reduce_to(MsState *st, int slot, const double *partial, int nparts) {
     const double s = sum_partials(partial, nparts);
     if (threadIdx.x == 0) st->scratch[slot] = s;
 }
 
-__global__ void __launch_bounds__(kWave) k_store_true_resid(MsState *st, int i, const double *partial, int nparts) {
-    const double s = sum_partials(partial, nparts);
-    if (threadIdx.x == 0) st->resid_true[i] = st->bnorm2 > 0.0 ? sqrt(s / st->bnorm2) : sqrt(s);
+// One workgroup: sum the partials in a fixed order, then apply the step.
+constexpr int kTailBlock = 256;
+__global__ void __launch_bounds__(kTailBlock) k_reduce_tail(MsState *st, const double *partial, int nparts, int kind,
+                                                         int idx) {
+    __shared__ double red[kTailBlock / kWave];
+    if (kind == TAIL_ALPHA && st->done) {
+        // the solve ended: retire the last update so later launches skip it
+        if (threadIdx.x == 0) st->upd_valid = 0;
+        return;
+    }
+    if ((kind == TAIL_BETA || kind == TAIL_RELIABLE) && st->done) return;
+    double t = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += kTailBlock) t += partial[k];
+    const double total = block_sum(t, red);
+    if (kind == TAIL_ALPHA) {
+        if (threadIdx.x == 0) st->upd_valid = 0;
+        ms_alpha_step(st, total);
+    } else if (kind == TAIL_BETA) {
+        ms_beta_step(st, total);
+    } else if (kind == TAIL_RELIABLE) {
+        if (threadIdx.x == 0) {
+            st->rho = total;
+            st->n_reliable += 1;
+        }
+    } else if (kind == TAIL_TRUE_RESID) {
+        if (threadIdx.x == 0) st->resid_true[idx] = st->bnorm2 > 0.0 ? sqrt(total / st->bnorm2) : sqrt(total);
+    }
 }
 
 // ---------------------------------------------------------------- launchers
+
+hipError_t launch_reduce_tail(MsState *st, const double *partial, int nparts, int kind, int idx, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_tail, dim3(1), dim3(kTailBlock), 0, s, st, partial, nparts, kind, idx);
+    return hipGetLastError();
+}
 
 hipError_t launch_norm2(bool dbl, const void *v, int64_t n, double *partial, int grid, hipStream_t s) {
     if (dbl) hipLaunchKernelGGL(k_norm2<double>, dim3(grid), dim3(kBlasBlock), 0, s, static_cast<const double2 *>(v), n, partial);
@@ -320,20 +265,10 @@ hipError_t launch_scalar_init(MsState *st, const double *partial_r, int nparts_r
     return hipGetLastError();
 }
 
-hipError_t launch_scalar_alpha(MsState *st, const double *partial, int nparts, hipStream_t s) {
-    hipLaunchKernelGGL(k_scalar_alpha, dim3(1), dim3(kWave), 0, s, st, partial, nparts);
-    return hipGetLastError();
-}
-
 hipError_t launch_r_update(bool dbl, MsState *st, void *r, const void *ap, int64_t n, double *partial, int grid,
                            hipStream_t s) {
     if (dbl) hipLaunchKernelGGL(k_r_update<double>, dim3(grid), dim3(kBlasBlock), 0, s, st, static_cast<double2 *>(r), static_cast<const double2 *>(ap), n, partial);
     else hipLaunchKernelGGL(k_r_update<float>, dim3(grid), dim3(kBlasBlock), 0, s, st, static_cast<float2 *>(r), static_cast<const float2 *>(ap), n, partial);
-    return hipGetLastError();
-}
-
-hipError_t launch_scalar_beta(MsState *st, const double *partial, int nparts, hipStream_t s) {
-    hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kWave), 0, s, st, partial, nparts);
     return hipGetLastError();
 }
 
@@ -355,18 +290,8 @@ hipError_t launch_demote(MsState *st, const double2 *src, float2 *dst, int64_t n
     return hipGetLastError();
 }
 
-hipError_t launch_scalar_reliable(MsState *st, const double *partial, int nparts, hipStream_t s) {
-    hipLaunchKernelGGL(k_scalar_reliable, dim3(1), dim3(kWave), 0, s, st, partial, nparts);
-    return hipGetLastError();
-}
-
 hipError_t launch_reduce_to(MsState *st, int slot, const double *partial, int nparts, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(kWave), 0, s, st, slot, partial, nparts);
-    return hipGetLastError();
-}
-
-hipError_t launch_store_true_resid(MsState *st, int i, const double *partial, int nparts, hipStream_t s) {
-    hipLaunchKernelGGL(k_store_true_resid, dim3(1), dim3(kWave), 0, s, st, i, partial, nparts);
     return hipGetLastError();
 }
 

@@ -57,6 +57,31 @@ template <typename R> __device__ __forceinline__ void acc_mul_dag(vec3<R> &acc, 
     }
 }
 
+// ---------------------------------------------------------------- streaming loads
+// Nontemporal loads: data that is read once (the gauge links) should not
+// push reusable data (neighbour colour vectors) out of the XCD's L2.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_nt(const double2 *p) {
+    const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float4 ld_nt(const float4 *p) {
+    const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 ld_nt(const float2 *p) {
+    const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(p));
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st_nt(double2 *p, double2 v) {
+    __builtin_nontemporal_store(d2v{v.x, v.y}, reinterpret_cast<d2v *>(p));
+}
+__device__ __forceinline__ void st_nt(float2 *p, float2 v) {
+    __builtin_nontemporal_store(f2v{v.x, v.y}, reinterpret_cast<f2v *>(p));
+}
+
 // ---------------------------------------------------------------- storage types
 // Library vectors: [colour][site] planes of {re,im}.
 template <typename R> struct vtype;

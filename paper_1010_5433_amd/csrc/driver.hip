@@ -21,6 +21,7 @@
 #include <cstring>
 #include <vector>
 
+#include "ms_device.h"
 #include "solver.h"
 
 namespace stag {
@@ -105,7 +106,8 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
     std::memset(&a, 0, sizeof(a));
     a.g = lat->g;
 
-    // r = b - A x_hi in double precision into RHI, partial |r|^2 into part0
+    // r = b - A x in double precision (into rout if non-null), partials of
+    // |r|^2 in `partial` (ds_grid of them)
     auto true_residual = [&](void *x, double shift, void *rout, double *partial, const int *skip) -> hipError_t {
         DslashArgs d = a;
         d.links = lat->links64;
@@ -156,15 +158,15 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
         d.c = m2 + sigma0;
         d.partial = part0;
         STAG_HIP(launch_dslash(dbl, lat->nrow, DS_NORMAL_DOT, d, s));
-        STAG_HIP(launch_scalar_alpha(st, part0, ds_grid, s));
+        STAG_HIP(launch_reduce_tail(st, part0, ds_grid, TAIL_ALPHA, 0, s));
         STAG_HIP(launch_r_update(dbl, st, R, AP, ne, part1, bl_grid, s));
-        STAG_HIP(launch_scalar_beta(st, part1, bl_grid, s));
+        STAG_HIP(launch_reduce_tail(st, part1, bl_grid, TAIL_BETA, 0, s));
         STAG_HIP(launch_shift_update(dbl, st, R, it_ptrs, n, ne, bl_grid, s));
         if (sp.reliable_every > 0 && (k + 1) % sp.reliable_every == 0) {
             STAG_HIP(launch_x_flush(st, hi_ptrs, lo_ptrs, n, ne, true, s));
             STAG_HIP(true_residual(sp.x_hi[base], sigma0, RHI, part0, &st->done));
+            STAG_HIP(launch_reduce_tail(st, part0, ds_grid, TAIL_RELIABLE, 0, s));
             STAG_HIP(launch_demote(st, static_cast<const double2 *>(RHI), static_cast<float2 *>(R), ne, s));
-            STAG_HIP(launch_scalar_reliable(st, part0, ds_grid, s));
         }
         return STAG_OK;
     };
@@ -208,7 +210,7 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
     if (!dbl) STAG_HIP(launch_x_flush(st, hi_ptrs, lo_ptrs, n, ne, false, s));
     for (int i = 0; i < n; ++i) {
         STAG_HIP(true_residual(sp.x_hi[i], sp.shifts[i], nullptr, part0, nullptr));
-        STAG_HIP(launch_store_true_resid(st, i, part0, ds_grid, s));
+        STAG_HIP(launch_reduce_tail(st, part0, ds_grid, TAIL_TRUE_RESID, i, s));
     }
     STAG_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
     STAG_HIP(hipStreamSynchronize(s));
@@ -307,6 +309,7 @@ stag_status multishift_cg(stag_lattice *lat, double mass, const double *shifts, 
             stag_status ri = cg_refine(lat, mass, shifts[i], src, sols[i], tol, max_iter, true, &it, &nrel, &resid, s);
             if (ri < 0) return ri;
             st.refine_iters += it;
+            st.refine_iters_shift[i] = it;
             st.n_reliable += nrel;
             st.resid_true[i] = resid;
             if (ri != STAG_OK) worst = ri;

@@ -6,7 +6,7 @@
 
 #include <string>
 
-#include "../../include/stag.h"
+#include "stag.h"
 #include "geom.h"
 
 namespace stag {

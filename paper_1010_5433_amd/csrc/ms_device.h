@@ -1,0 +1,99 @@
+// Device-side scalar steps of the shifted CG, shared by the single-system
+// and the batched solvers.  They run in a one-workgroup kernel that first
+// sums the per-workgroup partials of a reduction in a fixed order.
+// (Folding them into the reduction kernels -- the last workgroup to finish
+// completes the sum -- was measured slower on gfx950: the agent-scope
+// release each workgroup then needs writes back its XCD's L2, which costs
+// more than the launch it saves.)
+#pragma once
+
+#include <math.h>
+
+#include "common.h"
+#include "solver.h"
+
+namespace stag {
+
+// alpha_k = rho_k / <p, A p> and zeta_i^{k+1} for every active shift.
+// Threads 0..63 cover the shifts.
+__device__ __forceinline__ void ms_alpha_step(MsState *st, double pap) {
+    const int l = threadIdx.x;
+    if (!(pap > 0.0) || !isfinite(pap)) {
+        if (l == 0) {
+            st->status = MS_BREAKDOWN;
+            st->done = 1;
+        }
+        return;
+    }
+    const double alpha = st->rho / pap;
+    if (l < st->n && st->active[l]) {
+        if (l == st->base) {
+            st->zeta_next[l] = 1.0;
+        } else {
+            const double z = st->zeta[l], zp = st->zeta_prev[l];
+            const double den = alpha * st->beta_prev * (zp - z) + zp * st->alpha_prev * (1.0 + st->shift_rel[l] * alpha);
+            st->zeta_next[l] = z * zp * st->alpha_prev / den;
+        }
+    }
+    if (l == 0) st->alpha = alpha;
+}
+
+// beta_k, alpha_k^i, beta_k^i, the freeze test of every shift, and the
+// histories; flags the shift update of this iteration as valid.
+// Run by the first wave of one workgroup (threads 0..63).
+__device__ __forceinline__ void ms_beta_step(MsState *st, double rho_new) {
+    const int l = threadIdx.x;
+    if (l >= kWave) return;
+    const double beta = rho_new / st->rho;
+    const double alpha = st->alpha;
+    const int it = st->iter + 1;
+    bool act = false;
+    if (l < st->n) {
+        const bool was = st->active[l] != 0;
+        st->upd[l] = was ? 1 : 0;
+        if (was) {
+            const double zn = st->zeta_next[l];
+            const double ratio = zn / st->zeta[l];
+            st->a[l] = alpha * ratio;
+            st->b[l] = beta * ratio * ratio;
+            const double res = fabs(zn) * sqrt(rho_new / st->bnorm2);
+            st->resid_iter[l] = res;
+            if (res <= st->tol) {
+                st->active[l] = 0;
+                st->iters_shift[l] = it;
+            } else {
+                act = true;
+            }
+            st->zeta_prev[l] = st->zeta[l];
+            st->zeta[l] = zn;
+        }
+    }
+    const unsigned long long any = __ballot(act);
+    const int upd_base = __shfl(l < st->n ? st->upd[l] : 0, st->base);
+    if (l == 0) {
+        st->upd_p = (upd_base || any) ? 1 : 0;
+        st->beta = beta;
+        st->beta_prev = beta;
+        st->alpha_prev = alpha;
+        st->rho = rho_new;
+        st->iter = it;
+        st->upd_valid = 1;
+        if (!any) {
+            st->done = 1;
+            st->status = MS_CONVERGED;
+        } else if (it >= st->max_iter) {
+            st->done = 1;
+            st->status = MS_NOCONV;
+        }
+    }
+}
+
+// What the one-workgroup reduction kernel does with the reduced sum.
+enum TailKind {
+    TAIL_ALPHA = 1,      // total = <p, A p>: alpha and zeta; retires the update flag once done
+    TAIL_BETA = 2,       // total = |r|^2: beta, shift coefficients, freeze tests
+    TAIL_RELIABLE = 3,   // total = ||b - A x||^2 after a reliable update
+    TAIL_TRUE_RESID = 4  // total = ||b - (M + sigma_i) x_i||^2 of shift idx
+};
+
+}  // namespace stag

@@ -9,7 +9,7 @@ namespace stag {
 
 constexpr int kMaxShifts = STAG_MAX_SHIFTS;
 constexpr int kBlasBlock = 256;
-constexpr int kMaxBlasGrid = 8192;
+constexpr int kMaxBlasGrid = 2048;
 constexpr int kMaxPartials = 16384;
 
 enum MsStatus { MS_RUNNING = 0, MS_NOCONV = 1, MS_BREAKDOWN = 2, MS_CONVERGED = 3 };
@@ -53,23 +53,17 @@ hipError_t launch_ms_start(bool dbl, const double2 *b, void *r, ShiftPtrs ptrs, 
                            int64_t n, hipStream_t s);
 hipError_t launch_scalar_init(MsState *st, const double *partial_r, int nparts_r, const double *partial_b,
                               int nparts_b, hipStream_t s);
-hipError_t launch_scalar_alpha(MsState *st, const double *partial, int nparts, hipStream_t s);
 hipError_t launch_r_update(bool dbl, MsState *st, void *r, const void *ap, int64_t n, double *partial, int grid,
                            hipStream_t s);
-hipError_t launch_scalar_beta(MsState *st, const double *partial, int nparts, hipStream_t s);
-hipError_t launch_shift_update(bool dbl, MsState *st, const void *r, ShiftPtrs ptrs, int n_shift, int64_t n,
-                               int grid, hipStream_t s);
+hipError_t launch_shift_update(bool dbl, MsState *st, const void *r, ShiftPtrs ptrs, int n_shift, int64_t n, int grid,
+                               hipStream_t s);
+// One workgroup sums nparts partials (fixed order) and applies a TailKind step.
+hipError_t launch_reduce_tail(MsState *st, const double *partial, int nparts, int kind, int idx, hipStream_t s);
 // x_hi += x_lo; x_lo = 0 for every shift (single precision accumulators).
 hipError_t launch_x_flush(MsState *st, ShiftPtrs hi, ShiftPtrs lo, int n_shift, int64_t n, bool skip_on_done,
                           hipStream_t s);
 // dst (float) = src (double), skipped when the solve is done.
 hipError_t launch_demote(MsState *st, const double2 *src, float2 *dst, int64_t n, hipStream_t s);
-// After a reliable update: rho = sum(partial), count it.
-hipError_t launch_scalar_reliable(MsState *st, const double *partial, int nparts, hipStream_t s);
-// st->scratch[slot] = sum(partial)
-hipError_t launch_reduce_to(MsState *st, int slot, const double *partial, int nparts, hipStream_t s);
-// st->resid_true[i] = sqrt(sum(partial) / bnorm2)
-hipError_t launch_store_true_resid(MsState *st, int i, const double *partial, int nparts, hipStream_t s);
 // r = b - Ax computed elsewhere in double; copy r into a float/double residual and set directions p = r
 hipError_t launch_restart(bool dbl, const double2 *rhi, void *r, void *p, int64_t n, hipStream_t s);
 

@@ -45,8 +45,8 @@ def test_binding_covers_header():
 
 def test_stats_struct_matches_header(lib):
     from paper_1010_5433_amd._abi import CgStats, MAX_SHIFTS
-    # 4 ints + 1 int array + 3 double arrays + 1 double, naturally aligned
-    expect = 4 * 4 + 4 * MAX_SHIFTS + 8 * 3 * MAX_SHIFTS + 8
+    # 4 ints + 1 int array + 3 double arrays + 1 int array + 1 double, naturally aligned
+    expect = 4 * 4 + 4 * MAX_SHIFTS + 8 * 3 * MAX_SHIFTS + 4 * MAX_SHIFTS + 8
     assert ctypes.sizeof(CgStats) == expect
     assert "#define STAG_MAX_SHIFTS 64" in open(HEADER).read()
 
