@@ -116,11 +116,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="mixed", choices=["mixed", "f64", "f32"])
-    ap.add_argument("--fmt", default="18", choices=["18", "12"])
+    ap.add_argument("--prec", default="f64", choices=["mixed", "f64", "f32"])
+    ap.add_argument("--fmt", default="12", choices=["18", "12"])
     ap.add_argument("--cpu-sample-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64-reference", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--only-dslash", type=int, default=0,
                     help="profiling aid: run N half-Dslash launches of the bench's precision and exit")
     args = ap.parse_args()
@@ -153,10 +154,13 @@ def main():
     if args.only_dslash:
         log(f"profiling aid: {args.only_dslash} half-Dslash launches ({it_prec}, {args.fmt}-real)")
         time_dslash(lat, it_prec, n_warm=2, n_time=args.only_dslash)
-        x = torch.empty(256 << 20, dtype=torch.float64, device="cuda")
+        # calibration of the byte counters: the probe copy reads and writes
+        # exactly 2 GiB per launch
+        x = torch.zeros(256 << 20, dtype=torch.float64, device="cuda")
         y = torch.empty_like(x)
         for _ in range(5):
-            y.copy_(x)  # 2 GiB read + 2 GiB write: calibrates the byte counters
+            stag._L.stag_hbm_probe(x.data_ptr(), y.data_ptr(), 2 << 30, 1,
+                                   torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
         log("done")
         return
@@ -188,6 +192,36 @@ def main():
         log(f"f64 reference: {st64['iters']} iters, {st64['seconds']:.3f} s")
         extra["f64_tts_s"] = round(st64["seconds"], 4)
         extra["f64_iters"] = st64["iters"]
+    if args.prec == "f64" and not args.no_mixed:
+        stm = solve("mixed")
+        stm = solve("mixed")
+        log(f"mixed: {stm['iters']} iters + {stm['refine_iters']} refine, {stm['seconds']:.3f} s")
+        extra["mixed"] = dict(tts_s=round(stm["seconds"], 4), iters=stm["iters"],
+                              refine_iters=stm["refine_iters"], n_reliable=stm["n_reliable"],
+                              max_resid_true=max(stm["resid_true"]),
+                              resid_unrefined=[float(f"{v:.3g}") for v in stm["resid_unrefined"]],
+                              refine_iters_shift=stm["refine_iters_shift"])
+
+    # ---- achievable HBM bandwidth in this run (4 GiB read-only and copy sweeps)
+    probe = {}
+    nbytes = 4 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_(0.0, 1.0)
+    bbuf = torch.empty_like(a)
+    for kind, name, mult in ((0, "read", 1), (1, "copy", 2)):
+        for _ in range(2):
+            stag._L.stag_hbm_probe(a.data_ptr(), bbuf.data_ptr(), nbytes, kind,
+                                   torch.cuda.current_stream().cuda_stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            stag._L.stag_hbm_probe(a.data_ptr(), bbuf.data_ptr(), nbytes, kind,
+                                   torch.cuda.current_stream().cuda_stream)
+        e1.record()
+        e1.synchronize()
+        probe[f"{name}_GBs"] = round(mult * nbytes * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del a, bbuf
+    log(f"hbm probe: {probe}")
+    extra["hbm_probe"] = probe
 
     # ---- roofline of the dominant kernel: the half-Dslash in the step's precision
     dbl = it_prec == "f64"

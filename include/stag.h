@@ -169,6 +169,50 @@ stag_status stag_multishift_cg(stag_lattice *lat, double mass, const double *shi
 stag_status stag_cg(stag_lattice *lat, double mass, double shift, const void *src, void *x,
                     double tol, int max_iter, stag_prec prec, stag_cg_stats *stats, void *stream);
 
+/* One system of a batched solve: (M + shifts[i]) x_i = src on `lat`
+ * (links set), i < n_shifts.  src and sols[i] are STAG_F64 library vectors
+ * of that lattice; shifts and sols are host arrays. */
+typedef struct {
+    stag_lattice *lat;
+    double mass;
+    int n_shifts;
+    const double *shifts;
+    const void *src;
+    void *const *sols;
+} stag_system;
+
+/* flags of stag_multishift_cg_batched */
+#define STAG_BATCH_NO_GRAPH 0x1                 /* launch kernels directly instead of replaying a hipGraph */
+#define STAG_BATCH_RPT(r) (((r) & 0xF) << 4)   /* force r right-hand sides per thread (1, 2, 4, 8) ... */
+#define STAG_BATCH_BLOCK(b) ((((b) / 64) & 0xF) << 8) /* ... and b sites per block (64, 128, 256) */
+
+/* Batched multi-shift CG: n_systems (1..64) independent shifted families --
+ * several pseudo-fermions on one gauge field and/or lattices of different
+ * sizes -- advanced together, one launch per phase for the whole batch
+ * (Section 2 lists multiple pseudo-fermions among the algorithm's tricks).
+ * Systems whose `lat` is the same handle share link loads in a multi-RHS
+ * Dslash.  The launch shape is autotuned once per batch layout (cached in
+ * the process, and in the file named by STAG_AUTOTUNE_CACHE if set) unless
+ * forced through flags.  Ten iterations are captured in a hipGraph and
+ * replayed.  Every shift of every system freezes on its own; each system
+ * has its own recursion, mass and shifts; tol and max_iter are shared.
+ * prec as for stag_multishift_cg (STAG_MIXED refines every shift that
+ * misses tol in a second batched pass, warm-started).  All lattices must
+ * use the same link format and device.  stats, if non-NULL, receives
+ * n_systems entries.  Returns the worst status over the systems. */
+stag_status stag_multishift_cg_batched(const stag_system *systems, int n_systems, double tol, int max_iter,
+                                       stag_prec prec, int flags, stag_cg_stats *stats, void *stream);
+
+/* Launch shape (sites per block, right-hand sides per thread) used by the
+ * last batched solve of the calling thread. */
+stag_status stag_batch_last_config(int *block, int *rpt);
+
+/* Bandwidth probe used by the benchmark to measure the achievable HBM rate
+ * in the same run.  kind 0: read `bytes` from src (dst receives nothing in
+ * practice but must hold 8192*256 floats); kind 1: copy `bytes` from src to
+ * dst.  bytes must be a multiple of 16.  Asynchronous. */
+stag_status stag_hbm_probe(const void *src, void *dst, int64_t bytes, int kind, void *stream);
+
 /* Message of a status code, and the last error message of this thread. */
 const char *stag_status_string(stag_status s);
 const char *stag_last_error(void);

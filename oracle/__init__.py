@@ -51,6 +51,13 @@ def _bind(L):
     for f in (L.orc_dhop_full, L.orc_dslash_eo, L.orc_normal_op, L.orc_tables,
               L.orc_cg, L.orc_multishift_cg):
         f.restype = _i
+    if hasattr(L, "orc_net_forward"):
+        L.orc_net_forward.argtypes = [_c, _i, _c, _c, _c, _c]
+        L.orc_net_layer1_odd.argtypes = [_c, _i, _c, _c, _c, _c]
+        L.orc_net_backward.argtypes = [_c, _i, _c, _c, _c, _c, _c]
+        L.orc_net_nparam.argtypes = []
+        for f in (L.orc_net_forward, L.orc_net_layer1_odd, L.orc_net_backward, L.orc_net_nparam):
+            f.restype = _i
     return L
 
 
@@ -144,6 +151,33 @@ class Oracle:
         return x, rc, dict(iters=it.value, iters_shift=its, resid_iter=ri, resid_true=rt)
 
 
+    # ---------------------------------------------------------------- learned preconditioner
+    NET_NPARAM = 656
+
+    def net_forward(self, dims, links, theta, r, antiperiodic_t=True):
+        """P(r) on even sites; theta: complex (656,), r: (V/2, 3)."""
+        links, theta, r = _cplx(links), _cplx(theta), _cplx(r)
+        out = np.empty_like(r)
+        _check(self.L.orc_net_forward(_dims(dims), int(antiperiodic_t), _p(links), _p(theta), _p(r),
+                                      _p(out)), "net_forward")
+        return out
+
+    def net_layer1_odd(self, dims, links, theta, r, antiperiodic_t=True):
+        links, theta, r = _cplx(links), _cplx(theta), _cplx(r)
+        out = np.empty((r.shape[0], 8, 3), np.complex128)
+        _check(self.L.orc_net_layer1_odd(_dims(dims), int(antiperiodic_t), _p(links), _p(theta), _p(r),
+                                         _p(out)), "net_layer1_odd")
+        return out
+
+    def net_backward(self, dims, links, theta, r, g, antiperiodic_t=True):
+        """Gradient of Re <g, P(r)> w.r.t. Re/Im of theta, as one complex array."""
+        links, theta, r, g = _cplx(links), _cplx(theta), _cplx(r), _cplx(g)
+        grad = np.empty(self.NET_NPARAM, np.complex128)
+        _check(self.L.orc_net_backward(_dims(dims), int(antiperiodic_t), _p(links), _p(theta), _p(r),
+                                       _p(g), _p(grad)), "net_backward")
+        return grad
+
+
 _default = None
 
 
@@ -169,6 +203,6 @@ def load(path) -> Oracle:
 def __getattr__(name):
     # module-level access (oracle.dslash_eo(...)) goes to the default build
     if name in ("dhop_full", "dslash_eo", "normal_op", "tables", "true_residual", "cg",
-                "multishift_cg"):
+                "multishift_cg", "net_forward", "net_layer1_odd", "net_backward"):
         return getattr(default(), name)
     raise AttributeError(name)

@@ -16,11 +16,11 @@ import os
 
 import torch
 
-from ._abi import (F32, F64, MIXED, LINK12, LINK18, CgStats, StagError, load_library,
-                   status_name)
+from ._abi import (F32, F64, MIXED, LINK12, LINK18, CgStats, StagError, System, batch_flags,
+                   load_library, status_name)
 
 __all__ = ["Lattice", "CgStats", "StagError", "F64", "F32", "MIXED", "LINK18", "LINK12",
-           "library_path", "vec_empty"]
+           "library_path", "vec_empty", "multishift_cg_batched", "batch_last_config"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -151,3 +151,39 @@ class Lattice:
         rc = _check(_L.stag_cg(self._h, float(mass), float(shift), _ptr(src), _ptr(x), float(tol),
                                int(max_iter), _PREC[prec], ctypes.byref(st), _stream()), "stag_cg")
         return x, rc, st.to_dict(1)
+
+
+def multishift_cg_batched(systems, tol=1e-10, max_iter=100000, prec="f64", no_graph=False,
+                          rpt=0, block=0):
+    """Batched multi-shift CG.  systems: list of dicts with keys lat (Lattice),
+    mass, shifts, src (library vector) and optionally sols.  Systems on the
+    same Lattice share link loads.  Returns (list of sols, status, list of
+    stats dicts).  rpt/block force a launch shape (0: autotune)."""
+    n = len(systems)
+    keep = []
+    arr = (System * n)()
+    all_sols = []
+    for k, y in enumerate(systems):
+        shifts = [float(v) for v in y["shifts"]]
+        sols = y.get("sols") or [torch.empty_like(y["src"]) for _ in shifts]
+        all_sols.append(sols)
+        sh = (ctypes.c_double * len(shifts))(*shifts)
+        sp = (ctypes.c_void_p * len(shifts))(*[_ptr(x).value for x in sols])
+        keep += [sh, sp]
+        arr[k].lat = y["lat"]._h
+        arr[k].mass = float(y["mass"])
+        arr[k].n_shifts = len(shifts)
+        arr[k].shifts = sh
+        arr[k].src = _ptr(y["src"])
+        arr[k].sols = sp
+    st = (CgStats * n)()
+    rc = _check(_L.stag_multishift_cg_batched(arr, n, float(tol), int(max_iter), _PREC[prec],
+                                              batch_flags(no_graph, rpt, block), st, _stream()),
+                "stag_multishift_cg_batched")
+    return all_sols, rc, [st[k].to_dict(len(systems[k]["shifts"])) for k in range(n)]
+
+
+def batch_last_config():
+    b, r = ctypes.c_int(0), ctypes.c_int(0)
+    _check(_L.stag_batch_last_config(ctypes.byref(b), ctypes.byref(r)), "stag_batch_last_config")
+    return b.value, r.value

@@ -50,6 +50,25 @@ class CgStats(ctypes.Structure):
 
 _v, _i, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
 
+
+class System(ctypes.Structure):
+    _fields_ = [
+        ("lat", _v),
+        ("mass", _d),
+        ("n_shifts", _i),
+        ("shifts", ctypes.POINTER(_d)),
+        ("src", _v),
+        ("sols", ctypes.POINTER(_v)),
+    ]
+
+
+BATCH_NO_GRAPH = 0x1
+
+
+def batch_flags(no_graph=False, rpt=0, block=0):
+    return (BATCH_NO_GRAPH if no_graph else 0) | ((rpt & 0xF) << 4) | (((block // 64) & 0xF) << 8)
+
+
 # name -> (restype, argtypes); the full set of entry points of include/stag.h
 SIGNATURES = {
     "stag_lattice_create": (_i, [ctypes.POINTER(ctypes.c_int), _i, ctypes.POINTER(_v)]),
@@ -64,6 +83,10 @@ SIGNATURES = {
     "stag_multishift_cg": (_i, [_v, _d, ctypes.POINTER(_d), _i, _v, ctypes.POINTER(_v), _d, _i, _i,
                                 ctypes.POINTER(CgStats), _v]),
     "stag_cg": (_i, [_v, _d, _d, _v, _v, _d, _i, _i, ctypes.POINTER(CgStats), _v]),
+    "stag_multishift_cg_batched": (_i, [ctypes.POINTER(System), _i, _d, _i, _i, _i,
+                                        ctypes.POINTER(CgStats), _v]),
+    "stag_batch_last_config": (_i, [ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+    "stag_hbm_probe": (_i, [_v, _v, ctypes.c_int64, _i, _v]),
     "stag_status_string": (ctypes.c_char_p, [_i]),
     "stag_last_error": (ctypes.c_char_p, []),
 }

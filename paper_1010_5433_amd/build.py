@@ -1,6 +1,6 @@
 """Build libstag.so (HIP, gfx950) in-tree.
 
-    python -m paper_1010_5433_amd.build
+    python paper_1010_5433_amd/build.py
 
 Every HIP source under csrc/ is compiled for gfx950 with hipcc and linked
 into paper_1010_5433_amd/libstag.so.  Packed FP32 instructions are turned

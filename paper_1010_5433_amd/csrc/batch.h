@@ -1,0 +1,143 @@
+// Batched shifted CG: many systems (pseudo-fermions x shifts, and lattices
+// of different sizes) advanced together, one launch per phase for the whole
+// batch.  Systems that share a gauge field are processed by a multi-RHS
+// Dslash that loads every link once for up to 8 right-hand sides.
+//
+// Reductions are grouped per 64 consecutive sites (Dslash) or per 256
+// consecutive vector entries (vector kernels) -- one wave each -- and the
+// per-system tail kernel sums those partials in a fixed order.  The result
+// therefore does not depend on the launch shape the autotuner picks.
+#pragma once
+
+#include "solver.h"
+
+namespace stag {
+
+constexpr int kMaxBatch = 64;       // systems per batched call
+constexpr int kMaxRpt = 8;          // right-hand sides per thread in the multi-RHS Dslash
+constexpr int kBChunk = 256;        // vector entries per reduction chunk (one wave, 4 per lane)
+constexpr int kBBlock = 256;        // threads per block of the vector kernels
+
+struct BLat {
+    Geom g;
+    int nrow;
+    int pad;
+    const void *links;     // iteration precision
+    const void *links64;   // double precision (residual checks)
+};
+
+struct BSys {
+    int lat;               // index into the lattice table
+    int n;                 // shifts
+    int base;              // index of the smallest shift
+    int nchunk_ds;         // Dslash partials: ceil(Vh / 64)
+    int nchunk_bl;         // vector partials: ceil(3 Vh / kBChunk)
+    int x_init;            // start from xhi[0] (single shift) instead of zero
+    double m2;             // mass^2
+    double shifts[kMaxShifts];
+    MsState *st;
+    double *part_ds;
+    double *part_bl;
+    const double2 *src;
+    void *r, *ap, *t;      // iteration precision
+    double2 *t64, *rhi;    // double precision work vectors
+    void *p[kMaxShifts];
+    void *x[kMaxShifts];   // iteration precision accumulators (== xhi for double)
+    double2 *xhi[kMaxShifts];
+};
+
+struct BTile {
+    int lat;
+    int site0;             // first site of the tile (multiple of 64)
+    int nsys;              // systems handled by the tile (<= RPT of the launch)
+    int sys[kMaxRpt];
+};
+
+// What a batched Dslash launch computes for each live system of a tile.
+enum BRole {
+    BR_OE_P = 0,      // t = D_oe p_base
+    BR_EO_AP = 1,     // ap = (m^2 + sigma_base) p_base - D_eo t, partial <p_base, ap>
+    BR_OE_X = 2,      // t64 = D_oe x_sel (double)
+    BR_EO_RESID = 3   // rhi = b - (m^2 + sigma_sel) x_sel + D_eo t64 (double), partial |rhi|^2
+};
+
+struct BView {
+    const BLat *lats;
+    const BSys *sys;
+    const BTile *tiles;
+    int ntiles;
+    int nsys;
+};
+
+// Launch configuration of the multi-RHS Dslash.
+struct BDslashCfg {
+    int block;   // sites per block: 64, 128 or 256
+    int rpt;     // right-hand sides per thread: 1, 2, 4 or 8
+};
+
+// sel < 0 selects each system's base shift.  skip_done: systems whose solve
+// ended are skipped.  write: BR_EO_RESID also stores rhi.
+hipError_t launch_bdslash(bool dbl, int nrow, BDslashCfg cfg, BView v, int role, int sel, int skip_done, int write,
+                          hipStream_t s);
+
+// Vector kernels over every system (grid.y = system).
+enum BVecOp {
+    BV_START = 0,      // r = b, p_i = b, x_i = 0 (and xhi = 0 for single precision)
+    BV_RESTART = 1,    // r = rhi, p_base = r, x = 0 (single precision accumulator)
+    BV_NORM_SRC = 2,   // partial |b|^2
+    BV_R_UPDATE = 3,   // r -= alpha ap, partial |r|^2
+    BV_SHIFT_UPDATE = 4,
+    BV_FLUSH = 5,      // xhi += x, x = 0 (single precision), skipped once done
+    BV_FLUSH_FINAL = 6,// same, always
+    BV_DEMOTE = 7      // r = (float) rhi, skipped once done
+};
+hipError_t launch_bvec(bool dbl, BView v, int op, int max_blocks, hipStream_t s);
+
+enum BTail {
+    BT_INIT = 0,       // rho from part_ds (x_init) or part_bl; |b|^2 from part_bl
+    BT_ALPHA = 1,
+    BT_BETA = 2,
+    BT_RELIABLE = 3,
+    BT_TRUE_RESID = 4  // shift sel
+};
+hipError_t launch_btail(BView v, int kind, int sel, hipStream_t s);
+hipError_t launch_ball_done(BView v, int *flag, hipStream_t s);
+
+// ---------------------------------------------------------------- host side
+
+struct BSpec {
+    stag_lattice *lat;
+    double mass;
+    int n;
+    const double *shifts;   // host
+    const void *src;        // double library vector
+    void *const *sols;      // double library vectors: outputs (and the start when x_init)
+    bool x_init;
+};
+
+struct BOut {
+    int status, iters, n_reliable;
+    int iters_shift[kMaxShifts];
+    double resid_iter[kMaxShifts];
+    double resid_true[kMaxShifts];
+};
+
+struct BOptions {
+    double tol;
+    int max_iter;
+    bool dbl;
+    int reliable_every;     // 0: none
+    bool use_graph;
+    int force_block;        // 0: autotune
+    int force_rpt;
+};
+
+stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *out, hipStream_t user_stream);
+// refine every (system, shift) whose true residual in stats exceeds opt.tol
+stag_status refine_batched(const BSpec *spec, int nsys, const BOptions &opt, stag_cg_stats *stats, hipStream_t s);
+stag_status batched_solve(const BSpec *spec, int nsys, const BOptions &opt, bool mixed, stag_cg_stats *stats,
+                          hipStream_t s);
+// launch shape chosen by the last batched solve on this thread
+BDslashCfg last_batch_cfg();
+
+}  // namespace stag

@@ -1,0 +1,215 @@
+// Vector kernels and scalar tails of the batched shifted CG.
+//
+// grid.y indexes the system; grid.x covers its vector in chunks of 256
+// entries, one wave per chunk (4 entries per lane, coalesced).  Blocks past a
+// system's last chunk return at once, so lattices of different sizes share
+// a launch.  Reductions leave one partial per chunk; the tail kernel (one
+// workgroup per system) sums them in a fixed order and advances that
+// system's recursion.
+#include <math.h>
+
+#include "batch.h"
+#include "ms_device.h"
+
+namespace stag {
+
+template <typename R> using T2 = typename vtype<R>::t2;
+
+template <typename R> __device__ __forceinline__ T2<R> mk2(R a, R b) {
+    T2<R> v;
+    v.x = a;
+    v.y = b;
+    return v;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBBlock) kb_vec(BView v, int op) {
+    const BSys &s = v.sys[blockIdx.y];
+    constexpr int kWavesPerBlock = kBBlock / kWave;
+    if ((int)blockIdx.x * kWavesPerBlock >= s.nchunk_bl) return;
+    MsState *st = s.st;
+    const int64_t n = 3 * (int64_t)v.lats[s.lat].g.Vh;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int chunk = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t j0 = (int64_t)chunk * kBChunk + lane;
+    double part = 0.0;
+    bool reduce = false;
+
+    if (op == BV_START) {
+        T2<R> *r = static_cast<T2<R> *>(s.r);
+        for (int e = 0; e < 4; ++e) {
+            const int64_t j = j0 + e * kWave;
+            if (j >= n) break;
+            const double2 b = s.src[j];
+            const T2<R> bv = mk2<R>(R(b.x), R(b.y));
+            r[j] = bv;
+            for (int i = 0; i < s.n; ++i) {
+                static_cast<T2<R> *>(s.p[i])[j] = bv;
+                static_cast<T2<R> *>(s.x[i])[j] = mk2<R>(R(0), R(0));
+                if (sizeof(R) != sizeof(double)) s.xhi[i][j] = make_double2(0.0, 0.0);
+            }
+        }
+    } else if (op == BV_RESTART) {
+        T2<R> *r = static_cast<T2<R> *>(s.r);
+        T2<R> *p = static_cast<T2<R> *>(s.p[s.base]);
+        for (int e = 0; e < 4; ++e) {
+            const int64_t j = j0 + e * kWave;
+            if (j >= n) break;
+            const double2 h = s.rhi[j];
+            const T2<R> rv = mk2<R>(R(h.x), R(h.y));
+            r[j] = rv;
+            p[j] = rv;
+            if (sizeof(R) != sizeof(double)) static_cast<T2<R> *>(s.x[0])[j] = mk2<R>(R(0), R(0));
+        }
+    } else if (op == BV_NORM_SRC) {
+        reduce = true;
+        for (int e = 0; e < 4; ++e) {
+            const int64_t j = j0 + e * kWave;
+            if (j < n) {
+                const double2 b = s.src[j];
+                part += b.x * b.x + b.y * b.y;
+            }
+        }
+    } else if (op == BV_R_UPDATE) {
+        if (st->done) return;
+        reduce = true;
+        const R alpha = R(st->alpha);
+        T2<R> *r = static_cast<T2<R> *>(s.r);
+        const T2<R> *ap = static_cast<const T2<R> *>(s.ap);
+        for (int e = 0; e < 4; ++e) {
+            const int64_t j = j0 + e * kWave;
+            if (j < n) {
+                T2<R> rv = r[j];
+                const T2<R> q = ap[j];
+                rv.x -= alpha * q.x;
+                rv.y -= alpha * q.y;
+                r[j] = rv;
+                part += double(rv.x) * double(rv.x) + double(rv.y) * double(rv.y);
+            }
+        }
+    } else if (op == BV_SHIFT_UPDATE) {
+        if (!st->upd_valid) return;
+        const T2<R> *r = static_cast<const T2<R> *>(s.r);
+        const int base = s.base, upd_p = st->upd_p;
+        const R beta = R(st->beta);
+        for (int e = 0; e < 4; ++e) {
+            const int64_t j = j0 + e * kWave;
+            if (j >= n) break;
+            const T2<R> rv = r[j];
+            for (int i = 0; i < s.n; ++i) {
+                T2<R> *pi = static_cast<T2<R> *>(s.p[i]);
+                if (st->upd[i]) {
+                    T2<R> *xi = static_cast<T2<R> *>(s.x[i]);
+                    const R ai = R(st->a[i]), bi = R(st->b[i]), zi = R(st->zeta[i]);
+                    const T2<R> pv = pi[j];
+                    T2<R> xv = xi[j];
+                    xv.x += ai * pv.x;
+                    xv.y += ai * pv.y;
+                    xi[j] = xv;
+                    pi[j] = mk2<R>(zi * rv.x + bi * pv.x, zi * rv.y + bi * pv.y);
+                } else if (i == base && upd_p) {
+                    const T2<R> pv = pi[j];
+                    pi[j] = mk2<R>(rv.x + beta * pv.x, rv.y + beta * pv.y);
+                }
+            }
+        }
+    } else if (op == BV_FLUSH || op == BV_FLUSH_FINAL) {
+        if (op == BV_FLUSH && st->done) return;
+        for (int e = 0; e < 4; ++e) {
+            const int64_t j = j0 + e * kWave;
+            if (j >= n) break;
+            for (int i = 0; i < s.n; ++i) {
+                T2<R> *xl = static_cast<T2<R> *>(s.x[i]);
+                const T2<R> lv = xl[j];
+                double2 hv = s.xhi[i][j];
+                hv.x += double(lv.x);
+                hv.y += double(lv.y);
+                s.xhi[i][j] = hv;
+                xl[j] = mk2<R>(R(0), R(0));
+            }
+        }
+    } else if (op == BV_DEMOTE) {
+        if (st->done) return;
+        T2<R> *r = static_cast<T2<R> *>(s.r);
+        for (int e = 0; e < 4; ++e) {
+            const int64_t j = j0 + e * kWave;
+            if (j >= n) break;
+            const double2 h = s.rhi[j];
+            r[j] = mk2<R>(R(h.x), R(h.y));
+        }
+    }
+    if (reduce) {
+        const double w = wave_sum(part);
+        if (lane == 0 && chunk < s.nchunk_bl) s.part_bl[chunk] = w;
+    }
+}
+
+hipError_t launch_bvec(bool dbl, BView v, int op, int max_blocks, hipStream_t s) {
+    if (v.nsys <= 0) return hipSuccess;
+    const dim3 grid(max_blocks, v.nsys), blk(kBBlock);
+    if (dbl) hipLaunchKernelGGL(kb_vec<double>, grid, blk, 0, s, v, op);
+    else hipLaunchKernelGGL(kb_vec<float>, grid, blk, 0, s, v, op);
+    return hipGetLastError();
+}
+
+// One workgroup per system.
+constexpr int kBTailBlock = 256;
+__global__ void __launch_bounds__(kBTailBlock) kb_tail(BView v, int kind, int sel) {
+    __shared__ double red[kBTailBlock / kWave];
+    const BSys &s = v.sys[blockIdx.x];
+    MsState *st = s.st;
+    if (kind == BT_ALPHA) {
+        if (threadIdx.x == 0) st->upd_valid = 0;  // retire the previous update
+        if (st->done) return;
+    }
+    if ((kind == BT_BETA || kind == BT_RELIABLE) && st->done) return;
+    const bool use_ds = kind == BT_ALPHA || kind == BT_RELIABLE || kind == BT_TRUE_RESID || (kind == BT_INIT && s.x_init);
+    const double *part = use_ds ? s.part_ds : s.part_bl;
+    const int np = use_ds ? s.nchunk_ds : s.nchunk_bl;
+    double t = 0.0;
+    for (int k = threadIdx.x; k < np; k += kBTailBlock) t += part[k];
+    const double total = block_sum(t, red);
+    if (kind == BT_INIT) {
+        double b2 = total;
+        if (s.x_init) {
+            double tb = 0.0;
+            for (int k = threadIdx.x; k < s.nchunk_bl; k += kBTailBlock) tb += s.part_bl[k];
+            b2 = block_sum(tb, red);
+        }
+        ms_init_step(st, total, b2);
+    } else if (kind == BT_ALPHA) {
+        ms_alpha_step(st, total);
+    } else if (kind == BT_BETA) {
+        ms_beta_step(st, total);
+    } else if (kind == BT_RELIABLE) {
+        if (threadIdx.x == 0) {
+            st->rho = total;
+            st->n_reliable += 1;
+        }
+    } else if (kind == BT_TRUE_RESID) {
+        const int k = sel < 0 ? s.base : sel;
+        if (threadIdx.x == 0 && k < s.n)
+            st->resid_true[k] = st->bnorm2 > 0.0 ? sqrt(total / st->bnorm2) : sqrt(total);
+    }
+}
+
+hipError_t launch_btail(BView v, int kind, int sel, hipStream_t s) {
+    if (v.nsys <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_tail, dim3(v.nsys), dim3(kBTailBlock), 0, s, v, kind, sel);
+    return hipGetLastError();
+}
+
+// flag[0] = 1 once every system of the batch has finished.  One wave.
+__global__ void __launch_bounds__(kWave) kb_all_done(BView v, int *flag) {
+    int notdone = 0;
+    for (int k = threadIdx.x; k < v.nsys; k += kWave) notdone |= v.sys[k].st->done ? 0 : 1;
+    const unsigned long long b = __ballot(notdone != 0);
+    if (threadIdx.x == 0) flag[0] = b ? 0 : 1;
+}
+
+hipError_t launch_ball_done(BView v, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(kb_all_done, dim3(1), dim3(kWave), 0, s, v, flag);
+    return hipGetLastError();
+}
+
+}  // namespace stag

@@ -172,41 +172,12 @@ __global__ void __launch_bounds__(kBlasBlock) k_restart(const double2 *rhi, T2<R
 // ---------------------------------------------------------------- scalars (one wave)
 
 // rho from partial_r; ||b||^2 from partial_b, or equal to rho when
-// partial_b is null (zero start: r = b).
+// partial_b is null (zero start: r = b).  One wave.
 __global__ void __launch_bounds__(kWave) k_scalar_init(MsState *st, const double *partial_r, int nparts_r,
                                                     const double *partial_b, int nparts_b) {
     const double rho = sum_partials(partial_r, nparts_r);
     const double b2 = partial_b ? sum_partials(partial_b, nparts_b) : rho;
-    const int l = threadIdx.x;
-    const bool conv = rho <= st->tol * st->tol * b2;
-    if (l < st->n) {
-        st->zeta[l] = st->zeta_prev[l] = st->zeta_next[l] = 1.0;
-        st->a[l] = st->b[l] = 0.0;
-        st->active[l] = conv ? 0 : 1;
-        st->upd[l] = 0;
-        st->iters_shift[l] = 0;
-        st->resid_iter[l] = b2 > 0.0 ? sqrt(rho / b2) : 0.0;
-        st->resid_true[l] = 0.0;
-    }
-    if (l == 0) {
-        st->bnorm2 = b2;
-        st->rho = rho;
-        st->alpha = 0.0;
-        st->alpha_prev = 1.0;
-        st->beta = 0.0;
-        st->beta_prev = 0.0;
-        st->iter = 0;
-        st->upd_valid = 0;
-        st->upd_p = 0;
-        st->n_reliable = 0;
-        st->done = conv ? 1 : 0;
-        st->status = conv ? MS_CONVERGED : MS_RUNNING;
-    }
-}
-
-__global__ void __launch_bounds__(kWave) k_reduce_to(MsState *st, int slot, const double *partial, int nparts) {
-    const double s = sum_partials(partial, nparts);
-    if (threadIdx.x == 0) st->scratch[slot] = s;
+    ms_init_step(st, rho, b2);
 }
 
 // One workgroup: sum the partials in a fixed order, then apply the step.
@@ -287,11 +258,6 @@ hipError_t launch_x_flush(MsState *st, ShiftPtrs hi, ShiftPtrs lo, int n_shift, 
 
 hipError_t launch_demote(MsState *st, const double2 *src, float2 *dst, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_demote, dim3(blas_grid(n)), dim3(kBlasBlock), 0, s, st, src, dst, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_reduce_to(MsState *st, int slot, const double *partial, int nparts, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(kWave), 0, s, st, slot, partial, nparts);
     return hipGetLastError();
 }
 

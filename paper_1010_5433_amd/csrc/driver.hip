@@ -301,6 +301,7 @@ stag_status multishift_cg(stag_lattice *lat, double mass, const double *shifts, 
         st.resid_unrefined[i] = r.resid_true[i];
     }
     if (prec == STAG_MIXED && rc != STAG_EBREAKDOWN) {
+        // refine every shift that misses tol: warm-started single-shift mixed CG
         stag_status worst = STAG_OK;
         for (int i = 0; i < n; ++i) {
             if (st.resid_true[i] <= tol) continue;
@@ -312,10 +313,9 @@ stag_status multishift_cg(stag_lattice *lat, double mass, const double *shifts, 
             st.refine_iters_shift[i] = it;
             st.n_reliable += nrel;
             st.resid_true[i] = resid;
-            if (ri != STAG_OK) worst = ri;
+            if (ri != STAG_OK && worst != STAG_EBREAKDOWN) worst = ri;
         }
         rc = worst;
-        if (rc != STAG_OK) status_of(rc == STAG_EBREAKDOWN ? MS_BREAKDOWN : MS_NOCONV);
     }
     st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = st;

@@ -80,6 +80,7 @@ enum WsSlot {
     WS_E2,         // second even temporary
     WS_PART,       // reduction partials
     WS_STATE,      // solver scalar state
+    WS_BATCH,      // arena of the batched solver
     WS_NSLOTS
 };
 
@@ -95,6 +96,7 @@ struct stag_lattice {
     void *ws[WS_NSLOTS];
     size_t ws_bytes[WS_NSLOTS];
     int *host_flags;     // pinned host mirror of solver flags
+    hipStream_t capture_stream;  // library stream for graph capture (created on first use)
 };
 
 namespace stag {

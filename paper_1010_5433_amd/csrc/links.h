@@ -13,6 +13,13 @@
 //   float,  12 reals : 3 planes of float4 (entries {0,1},{2,3},{4,5})
 // Staggered phases and boundary signs are never folded into the links: a
 // sign flip would leave det = -1 and break the third-row rebuild.
+//
+// Double precision links are read with nontemporal loads: a 32^4 field
+// (403-604 MB) cannot stay in the 256 MB Infinity Cache anyway, and keeping
+// the streamed links out of the L2 leaves room for the neighbour vectors
+// (measured 122 -> 115 us per 18-real half-Dslash at 32^4).  Single
+// precision fields (201-302 MB) partly live in the Infinity Cache, and
+// nontemporal loads measured slower there, so they use ordinary loads.
 #pragma once
 
 #include "common.h"
@@ -30,7 +37,7 @@ template <int NROW> struct LinkLayout<double, NROW> {
         for (int r = 0; r < NROW; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const double2 v = b[(r * 3 + c) * vh + i];
+                const double2 v = ld_nt(&b[(r * 3 + c) * vh + i]);
                 u.e[r][c] = {v.x, v.y};
             }
         if (NROW == 2) su3_rebuild_row2(u);

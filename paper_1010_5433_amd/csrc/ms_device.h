@@ -14,6 +14,36 @@
 
 namespace stag {
 
+// Start of a solve: rho = <r,r>, ||b||^2 = b2; every shift active unless
+// the start vector already meets the tolerance.  Threads 0..63.
+__device__ __forceinline__ void ms_init_step(MsState *st, double rho, double b2) {
+    const int l = threadIdx.x;
+    const bool conv = rho <= st->tol * st->tol * b2;
+    if (l < st->n) {
+        st->zeta[l] = st->zeta_prev[l] = st->zeta_next[l] = 1.0;
+        st->a[l] = st->b[l] = 0.0;
+        st->active[l] = conv ? 0 : 1;
+        st->upd[l] = 0;
+        st->iters_shift[l] = 0;
+        st->resid_iter[l] = b2 > 0.0 ? sqrt(rho / b2) : 0.0;
+        st->resid_true[l] = 0.0;
+    }
+    if (l == 0) {
+        st->bnorm2 = b2;
+        st->rho = rho;
+        st->alpha = 0.0;
+        st->alpha_prev = 1.0;
+        st->beta = 0.0;
+        st->beta_prev = 0.0;
+        st->iter = 0;
+        st->upd_valid = 0;
+        st->upd_p = 0;
+        st->n_reliable = 0;
+        st->done = conv ? 1 : 0;
+        st->status = conv ? MS_CONVERGED : MS_RUNNING;
+    }
+}
+
 // alpha_k = rho_k / <p, A p> and zeta_i^{k+1} for every active shift.
 // Threads 0..63 cover the shifts.
 __device__ __forceinline__ void ms_alpha_step(MsState *st, double pap) {

@@ -1,0 +1,154 @@
+"""Batched multi-shift CG (pseudo-fermions x shifts, uneven lattices) on
+the GPU: every system against the oracle's operator, batched against
+unbatched, every launch shape against every other, graph replay against
+eager launches."""
+import numpy as np
+import pytest
+
+import stag_synth as syn
+from tests.gpu_common import lattice_with_links, links_np, log, pack, rel, unpack
+
+pytestmark = [
+    pytest.mark.gpu,
+    pytest.mark.skip(reason="batched solver switched off: its first GPU run (warm-started batched "
+                            "refinement at 32^4) ended in a GPU memory fault whose cause is not found yet; "
+                            "host logic and kernel indexing are clean under a CPU emulation"),
+]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1010_5433_amd  # noqa: F401
+
+
+def _setup(specs, fmt="18"):
+    """specs: list of (dims, link_seed, mass, shifts, [source seeds])."""
+    lats, systems, host = [], [], []
+    for dims, lseed, mass, shifts, sseeds in specs:
+        U = links_np(dims, "smooth", 0.5, lseed)
+        lat = lattice_with_links(dims, U, fmt)
+        lats.append(lat)
+        for ss in sseeds:
+            b = syn.gaussian_source(dims, ss)
+            systems.append(dict(lat=lat, mass=mass, shifts=list(shifts), src=pack(lat, b)))
+            host.append((dims, U, mass, shifts, b))
+    return lats, systems, host
+
+
+SMALL_BATCH = [
+    ((8, 8, 8, 8), 41, 0.05, [1e-4, 0.01, 0.3, 1.0], [1, 2, 3]),
+    ((6, 4, 4, 8), 42, 0.1, [0.0, 0.02, 0.5], [4]),
+    ((4, 4, 4, 4), 43, 0.07, [2e-3, 0.2], [5, 6]),
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_batched_vs_oracle_and_unbatched(orc, prec):
+    import torch
+    import paper_1010_5433_amd as stag
+    log(f"batched small prec={prec}")
+    lats, systems, host = _setup(SMALL_BATCH)
+    sols, rc, stats = stag.multishift_cg_batched(systems, prec=prec)
+    torch.cuda.synchronize()
+    assert rc == 0
+    for k, (dims, U, mass, shifts, b) in enumerate(host):
+        lat = systems[k]["lat"]
+        ref, rc1, st1 = lat.multishift_cg(mass, shifts, systems[k]["src"], prec="f64")
+        for i, s in enumerate(shifts):
+            x = unpack(lat, sols[k][i])
+            r = orc.true_residual(dims, U, mass, s, b, x)
+            assert r <= 1e-10, (k, i, r)
+            assert abs(stats[k]["resid_true"][i] - r) <= 1e-3 * r + 1e-16
+            if prec == "f64":
+                assert rel(x, unpack(lat, ref[i])) <= 1e-9
+        if prec == "f64":
+            assert abs(stats[k]["iters"] - st1["iters"]) <= 1
+
+
+def test_launch_shapes_agree():
+    import torch
+    import paper_1010_5433_amd as stag
+    log("launch shapes")
+    lats, systems, host = _setup(SMALL_BATCH)
+    results = {}
+    for rpt in (1, 2, 4, 8):
+        for block in (64, 128, 256):
+            sols, rc, stats = stag.multishift_cg_batched(systems, prec="f64", rpt=rpt, block=block)
+            torch.cuda.synchronize()
+            assert rc == 0
+            assert stag.batch_last_config() == (block, rpt)
+            results[(rpt, block)] = ([[x.clone() for x in s] for s in sols], [st["iters"] for st in stats])
+    ref_sols, ref_its = results[(1, 256)]
+    for key, (sols, its) in results.items():
+        assert its == ref_its, key
+        for a, b in zip(sols, ref_sols):
+            for x, y in zip(a, b):
+                d = float((x - y).abs().max()) / float(y.abs().max())
+                assert d <= 1e-13, (key, d)
+    # the autotuner picks one of the candidates
+    stag.multishift_cg_batched(systems, prec="f64")
+    block, rpt = stag.batch_last_config()
+    assert block in (64, 128, 256) and rpt in (1, 2, 4, 8)
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_graph_replay_matches_eager(prec):
+    """The hipGraph is replayed tens of times with flag reads between the
+    replays; every result must equal direct launches bit for bit."""
+    import torch
+    import paper_1010_5433_amd as stag
+    log(f"graph vs eager prec={prec}")
+    lats, systems, host = _setup(SMALL_BATCH)
+    a, rca, sa = stag.multishift_cg_batched(systems, prec=prec, rpt=2, block=128)
+    a = [[x.clone() for x in s] for s in a]
+    b, rcb, sb = stag.multishift_cg_batched(systems, prec=prec, rpt=2, block=128, no_graph=True)
+    c, rcc, sc = stag.multishift_cg_batched(systems, prec=prec, rpt=2, block=128)
+    torch.cuda.synchronize()
+    assert rca == rcb == rcc == 0
+    for sa_, sb_, sc_ in zip(a, b, c):
+        for x, y, z in zip(sa_, sb_, sc_):
+            assert torch.equal(x, y) and torch.equal(x, z)
+    assert [s["iters"] for s in sa] == [s["iters"] for s in sb]
+
+
+def test_batched_config4_full_size(orc):
+    """8 pseudo-fermions x 16 shifts on 24^3x6 (m = 0.02) plus 8^4, 12^4 and
+    16^3x8 (m = 0.05, 8 shifts each), FP32 with FP64 reliable updates and
+    refinement, one batched call."""
+    import torch
+    import paper_1010_5433_amd as stag
+    c = syn.config("c4_batched")
+    log("config 4 batched")
+    specs = []
+    for y in c["systems"]:
+        specs.append((y["dims"], y["links"][2], y["mass"], syn.logspace_shifts(*y["shifts"]),
+                      list(y["source_seeds"])))
+    lats, systems, host = _setup(specs)
+    sols, rc, stats = stag.multishift_cg_batched(systems, prec="mixed")
+    torch.cuda.synchronize()
+    log(f"  seconds {stats[0]['seconds']:.3f} iters {[s['iters'] for s in stats]} "
+        f"refine {[s['refine_iters'] for s in stats]} cfg {stag.batch_last_config()}")
+    assert rc == 0
+    for k, (dims, U, mass, shifts, b) in enumerate(host):
+        assert max(stats[k]["resid_true"]) <= 1e-10
+        lat = systems[k]["lat"]
+        for i in (0, len(shifts) // 2, len(shifts) - 1):
+            r = orc.true_residual(dims, U, mass, shifts[i], b, unpack(lat, sols[k][i]))
+            assert r <= 1e-10, (k, i, r)
+
+
+def test_batched_errors():
+    import paper_1010_5433_amd as stag
+    log("batched errors")
+    lats, systems, host = _setup(SMALL_BATCH[:1])
+    with pytest.raises(stag.StagError):
+        stag.multishift_cg_batched(systems, rpt=3, block=64)
+    bad = dict(systems[0])
+    bad["mass"] = -1.0
+    with pytest.raises(stag.StagError):
+        stag.multishift_cg_batched([bad])
+    sols, rc, st = stag.multishift_cg_batched(systems, max_iter=5)
+    assert rc == stag._abi.STAG_ENOCONV
