@@ -207,6 +207,72 @@ stag_status stag_multishift_cg_batched(const stag_system *systems, int n_systems
  * last batched solve of the calling thread. */
 stag_status stag_batch_last_config(int *block, int *rpt);
 
+/* ------------------------------------------------------------------ learned preconditioner
+ * Not part of the paper: an extension that preconditions the double
+ * precision single-shift solve of the Metropolis step (Section 4 keeps that
+ * inversion in double precision; Section 6 uses CG for it).
+ *
+ * Network P(r), r on even sites, 8 channels, weights shared by all sites and
+ * colours (so P commutes with gauge transformations and is linear in r):
+ *   hops    (T_{+mu} psi)(x) = eta_mu(x) s_mu(x)    U_mu(x)        psi(x+mu)
+ *           (T_{-mu} psi)(x) = eta_mu(x) s_mu(x-mu) U_mu(x-mu)^dag psi(x-mu)
+ *           d = mu for +mu, d = 4 + mu for -mu (eta, s as in the operator).
+ *   layer 1 phi1[c](x) = w1s[c] r(x) on even x,
+ *           phi1[c](y) = sum_d w1h[c][d] (T_d r)(y) on odd y;
+ *   layer 2 on even x: inputs f_c' = phi1[c'](x), f_{8+8d+c'} = (T_d phi1[c'])(x),
+ *           phi2[c](x) = sum_k W2[c][k] f_k(x)  (72 inputs per channel);
+ *   output  P(r)(x) = sum_c wout[c] phi2[c](x).
+ * Parameters: 656 complex numbers theta = [w1s(8) | w1h(8x8, [c][d]) |
+ * W2(8x72, [c][k]) | wout(8)], passed through the ABI as 1312 doubles
+ * (re, im interleaved); the device keeps FP32 master copies.
+ * r and outputs are STAG_F32 library vectors of the lattice; the network
+ * reads the lattice's single precision links.
+ * mode 0: layer-2 channel mixing in BF16 on the matrix cores with FP32
+ *         accumulation (the solver uses this mode);
+ * mode 1: the same mixing in FP32 on the vector ALU (a check of mode 0).
+ * The backward pass is FP32 in both modes; gradients are summed in a fixed
+ * order (deterministic). */
+typedef struct stag_net stag_net;
+
+/* Create a network on the current device with every parameter zero. */
+stag_status stag_net_create(stag_net **out);
+stag_status stag_net_destroy(stag_net *net);
+
+/* Set / read the 656 complex parameters (HOST arrays of 1312 doubles).
+ * Setting them resets the optimiser state.  Synchronous. */
+stag_status stag_net_set_params(stag_net *net, const double *theta);
+stag_status stag_net_get_params(const stag_net *net, double *theta);
+
+/* out = P(r).  Asynchronous on `stream`.  r and out must differ. */
+stag_status stag_net_apply(stag_net *net, stag_lattice *lat, const void *r, void *out, int mode,
+                           void *stream);
+
+/* Gradient of L = Re sum_x <g(x), P(r)(x)> with respect to the parameters,
+ * written to the HOST array grad[1312] as dL/dRe, dL/dIm of each theta_j.
+ * r, g: STAG_F32 library vectors.  Synchronous. */
+stag_status stag_net_grad(stag_net *net, stag_lattice *lat, const void *r, const void *g, double *grad,
+                          int mode, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, step size lr) on the
+ * loss (1/n) sum_k ||P(b_k) - x_k||^2 / ||x_k||^2 over n pairs (1..1024).
+ * b, x: n STAG_F32 library vectors stored back to back (3*V/2 float2 each).
+ * *loss (host, may be NULL) receives the loss before the step; when loss
+ * is non-NULL the call waits for the stream. */
+stag_status stag_net_train_step(stag_net *net, stag_lattice *lat, const void *b, const void *x, int n,
+                                double lr, int mode, double *loss, void *stream);
+
+/* Flexible CG with P as preconditioner (Polak-Ribiere beta) for
+ * (M + shift) x = src from the x passed in (STAG_F64 library vectors; sol
+ * is read and overwritten).  net == NULL runs plain double precision CG.
+ * The residual is re-computed in double precision from x whenever the
+ * iterated one reaches tol ||src|| (the judge), and the solver falls back
+ * to plain double precision CG, warm-started, when <r, P r> <= 0, a
+ * curvature is not positive or finite, or the residual stalls for 50
+ * iterations (stats->fallback_used = 1).  stats->iters counts both parts;
+ * stats->resid_true[0] is the final relative true residual.  Synchronous. */
+stag_status stag_fcg_solve(stag_lattice *lat, double mass, double shift, const void *src, void *sol,
+                           stag_net *net, double tol, int max_iter, stag_cg_stats *stats, void *stream);
+
 /* Bandwidth probe used by the benchmark to measure the achievable HBM rate
  * in the same run.  kind 0: read `bytes` from src (dst receives nothing in
  * practice but must hold 8192*256 floats); kind 1: copy `bytes` from src to

@@ -16,11 +16,12 @@ import os
 
 import torch
 
-from ._abi import (F32, F64, MIXED, LINK12, LINK18, CgStats, StagError, System, batch_flags,
-                   load_library, status_name)
+from ._abi import (F32, F64, MIXED, LINK12, LINK18, MIX_BF16, MIX_FP32, NET_NPARAM, CgStats, StagError,
+                   System, batch_flags, load_library, status_name)
 
 __all__ = ["Lattice", "CgStats", "StagError", "F64", "F32", "MIXED", "LINK18", "LINK12",
-           "library_path", "vec_empty", "multishift_cg_batched", "batch_last_config"]
+           "library_path", "vec_empty", "multishift_cg_batched", "batch_last_config", "Net",
+           "NET_NPARAM"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -151,6 +152,85 @@ class Lattice:
         rc = _check(_L.stag_cg(self._h, float(mass), float(shift), _ptr(src), _ptr(x), float(tol),
                                int(max_iter), _PREC[prec], ctypes.byref(st), _stream()), "stag_cg")
         return x, rc, st.to_dict(1)
+
+    def fcg_solve(self, mass, shift, src: torch.Tensor, x: torch.Tensor, net=None, tol=1e-10,
+                  max_iter=100000):
+        """Flexible CG for (M + shift) x = src preconditioned by `net` (a Net, or
+        None for plain double precision CG), from the given x (overwritten)."""
+        st = CgStats()
+        rc = _check(_L.stag_fcg_solve(self._h, float(mass), float(shift), _ptr(src), _ptr(x),
+                                      net._h if net is not None else None, float(tol), int(max_iter),
+                                      ctypes.byref(st), _stream()), "stag_fcg_solve")
+        return x, rc, st.to_dict(1)
+
+
+_MIX = {"bf16": MIX_BF16, "fp32": MIX_FP32, MIX_BF16: MIX_BF16, MIX_FP32: MIX_FP32}
+
+
+class Net:
+    """The learned gauge-equivariant preconditioner (656 complex parameters).
+
+    Vectors are single precision library vectors (float32, (3, V/2, 2)) of the
+    lattice passed to each call."""
+
+    def __init__(self, theta=None):
+        h = ctypes.c_void_p()
+        _check(_L.stag_net_create(ctypes.byref(h)), "stag_net_create")
+        self._h = h
+        if theta is not None:
+            self.set_params(theta)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _L.stag_net_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _as_doubles(theta):
+        import numpy as np
+        t = np.ascontiguousarray(np.asarray(theta, dtype=np.complex128).reshape(NET_NPARAM))
+        return t, t.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    def set_params(self, theta):
+        """theta: 656 complex numbers (array-like)."""
+        t, p = self._as_doubles(theta)
+        _check(_L.stag_net_set_params(self._h, p), "stag_net_set_params")
+
+    def get_params(self):
+        import numpy as np
+        t = np.zeros(NET_NPARAM, np.complex128)
+        _check(_L.stag_net_get_params(self._h, t.view(np.float64).ctypes.data_as(
+            ctypes.POINTER(ctypes.c_double))), "stag_net_get_params")
+        return t
+
+    def apply(self, lat: Lattice, r: torch.Tensor, out=None, mode="bf16") -> torch.Tensor:
+        out = torch.empty_like(r) if out is None else out
+        _check(_L.stag_net_apply(self._h, lat._h, _ptr(r), _ptr(out), _MIX[mode], _stream()),
+               "stag_net_apply")
+        return out
+
+    def grad(self, lat: Lattice, r: torch.Tensor, g: torch.Tensor, mode="fp32"):
+        """Gradient of Re <g, P(r)> as 656 complex numbers dL/dRe + i dL/dIm."""
+        import numpy as np
+        out = np.zeros(NET_NPARAM, np.complex128)
+        _check(_L.stag_net_grad(self._h, lat._h, _ptr(r), _ptr(g), out.view(np.float64).ctypes.data_as(
+            ctypes.POINTER(ctypes.c_double)), _MIX[mode], _stream()), "stag_net_grad")
+        return out
+
+    def train_step(self, lat: Lattice, b: torch.Tensor, x: torch.Tensor, lr: float, mode="bf16") -> float:
+        """One Adam step on n pairs; b, x: float32 (n, 3, V/2, 2).  Returns the loss."""
+        if b.dim() != 4 or b.shape != x.shape:
+            raise ValueError("b and x must be (n, 3, V/2, 2) with equal shapes")
+        loss = ctypes.c_double(0.0)
+        _check(_L.stag_net_train_step(self._h, lat._h, _ptr(b), _ptr(x), int(b.shape[0]), float(lr),
+                                      _MIX[mode], ctypes.byref(loss), _stream()), "stag_net_train_step")
+        return loss.value
 
 
 def multishift_cg_batched(systems, tol=1e-10, max_iter=100000, prec="f64", no_graph=False,

@@ -10,6 +10,8 @@ STAG_EINVAL, STAG_ENOMEM, STAG_EHIP = -1, -2, -3
 F64, F32, MIXED = 0, 1, 2
 LINK18, LINK12 = 0, 1
 MAX_SHIFTS = 64
+NET_NPARAM = 656
+MIX_BF16, MIX_FP32 = 0, 1
 
 _NAMES = {0: "STAG_OK", 1: "STAG_ENOCONV", 2: "STAG_EBREAKDOWN", -1: "STAG_EINVAL",
           -2: "STAG_ENOMEM", -3: "STAG_EHIP"}
@@ -86,6 +88,14 @@ SIGNATURES = {
     "stag_multishift_cg_batched": (_i, [ctypes.POINTER(System), _i, _d, _i, _i, _i,
                                         ctypes.POINTER(CgStats), _v]),
     "stag_batch_last_config": (_i, [ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+    "stag_net_create": (_i, [ctypes.POINTER(_v)]),
+    "stag_net_destroy": (_i, [_v]),
+    "stag_net_set_params": (_i, [_v, ctypes.POINTER(_d)]),
+    "stag_net_get_params": (_i, [_v, ctypes.POINTER(_d)]),
+    "stag_net_apply": (_i, [_v, _v, _v, _v, _i, _v]),
+    "stag_net_grad": (_i, [_v, _v, _v, _v, ctypes.POINTER(_d), _i, _v]),
+    "stag_net_train_step": (_i, [_v, _v, _v, _v, _i, _d, _i, ctypes.POINTER(_d), _v]),
+    "stag_fcg_solve": (_i, [_v, _d, _d, _v, _v, _v, _d, _i, ctypes.POINTER(CgStats), _v]),
     "stag_hbm_probe": (_i, [_v, _v, ctypes.c_int64, _i, _v]),
     "stag_status_string": (ctypes.c_char_p, [_i]),
     "stag_last_error": (ctypes.c_char_p, []),
