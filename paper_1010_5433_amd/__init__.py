@@ -211,7 +211,7 @@ class Net:
 
     def apply(self, lat: Lattice, r: torch.Tensor, out=None, mode="bf16") -> torch.Tensor:
         out = torch.empty_like(r) if out is None else out
-        _check(_L.stag_net_apply(self._h, lat._h, _ptr(r), _ptr(out), _MIX[mode], _stream()),
+        _check(_L.stag_net_apply(self._h, lat._h, _ptr(r), _ptr(out), _MIX.get(mode, mode), _stream()),
                "stag_net_apply")
         return out
 
@@ -220,7 +220,7 @@ class Net:
         import numpy as np
         out = np.zeros(NET_NPARAM, np.complex128)
         _check(_L.stag_net_grad(self._h, lat._h, _ptr(r), _ptr(g), out.view(np.float64).ctypes.data_as(
-            ctypes.POINTER(ctypes.c_double)), _MIX[mode], _stream()), "stag_net_grad")
+            ctypes.POINTER(ctypes.c_double)), _MIX.get(mode, mode), _stream()), "stag_net_grad")
         return out
 
     def train_step(self, lat: Lattice, b: torch.Tensor, x: torch.Tensor, lr: float, mode="bf16") -> float:
@@ -229,7 +229,7 @@ class Net:
             raise ValueError("b and x must be (n, 3, V/2, 2) with equal shapes")
         loss = ctypes.c_double(0.0)
         _check(_L.stag_net_train_step(self._h, lat._h, _ptr(b), _ptr(x), int(b.shape[0]), float(lr),
-                                      _MIX[mode], ctypes.byref(loss), _stream()), "stag_net_train_step")
+                                      _MIX.get(mode, mode), ctypes.byref(loss), _stream()), "stag_net_train_step")
         return loss.value
 
 

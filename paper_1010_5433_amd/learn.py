@@ -1,0 +1,102 @@
+"""Training and evaluation of the learned preconditioner.
+
+Everything numerical runs in the library's kernels: the training pairs are
+made with the library's double precision operator and solver, the network
+is trained by its forward, backward and Adam kernels, and it is judged inside
+its flexible CG.  This module only drives those calls.
+
+Training pairs.  For a source/solution pair (b, x) of M x = b the loss
+||P(b) - x||^2 / ||x||^2 weighs each eigenmode of M by the size of its
+component in x.  With x drawn white and b = M x the loss is the mean of
+|1 - lambda p(lambda)|^2 over the spectrum, which is what a preconditioner of
+CG needs; with b drawn white (x = M^-1 b from the solver) the low modes carry
+weights 1/lambda^2, and the fitted network is in general not positive
+definite.  make_pairs therefore draws x and forms b = M x in double
+precision; solve_pairs (b white, x from the solver) is kept for comparison.
+"""
+from __future__ import annotations
+
+import time
+
+import torch
+
+from . import Lattice, Net, NET_NPARAM
+
+
+def _white(shape, gen, device="cuda"):
+    """Complex Gaussian library vectors (float64), unit variance per complex entry."""
+    return torch.randn(shape, generator=gen, dtype=torch.float64, device=device) * (0.5 ** 0.5)
+
+
+def make_pairs(lat: Lattice, mass: float, n: int, seed: int):
+    """n pairs (b, x) with x white and b = M x (double precision operator),
+    returned as float32 tensors (n, 3, V/2, 2)."""
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(int(seed))
+    B = torch.empty((n, 3, lat.Vh, 2), dtype=torch.float32, device="cuda")
+    X = torch.empty_like(B)
+    b64 = torch.empty((3, lat.Vh, 2), dtype=torch.float64, device="cuda")
+    for k in range(n):
+        x = _white((3, lat.Vh, 2), gen)
+        lat.normal_op(mass, 0.0, x, out=b64)
+        B[k].copy_(b64)
+        X[k].copy_(x)
+    return B, X
+
+
+def solve_pairs(lat: Lattice, mass: float, n: int, seed: int, tol=1e-10):
+    """n pairs with b white and x = M^-1 b from the double precision CG."""
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(int(seed))
+    B = torch.empty((n, 3, lat.Vh, 2), dtype=torch.float32, device="cuda")
+    X = torch.empty_like(B)
+    for k in range(n):
+        b = _white((3, lat.Vh, 2), gen)
+        x = torch.zeros_like(b)
+        lat.cg(mass, 0.0, b, x, tol=tol)
+        B[k].copy_(b)
+        X[k].copy_(x)
+    return B, X
+
+
+def init_theta(seed: int, scale: float = 0.1):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    return scale * (rng.standard_normal(NET_NPARAM) + 1j * rng.standard_normal(NET_NPARAM))
+
+
+def train(net: Net, data, steps: int, batch: int, lr: float, mode="bf16", seed: int = 0, log=None):
+    """Adam on minibatches.  data: list of (Lattice, B, X); step k uses field
+    k mod len(data) and a minibatch drawn from its pairs.  Returns the loss
+    history (one value per step)."""
+    gen = torch.Generator()
+    gen.manual_seed(int(seed))
+    losses = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        lat, B, X = data[k % len(data)]
+        n = B.shape[0]
+        if batch >= n:
+            b, x = B, X
+        else:
+            start = int(torch.randint(0, n - batch + 1, (1,), generator=gen))
+            b, x = B[start:start + batch], X[start:start + batch]
+        losses.append(net.train_step(lat, b, x, lr, mode))
+        if log and (k + 1) % max(1, steps // 10) == 0:
+            log(f"step {k + 1}/{steps} loss {losses[-1]:.5f} ({time.perf_counter() - t0:.1f} s)")
+    return losses
+
+
+def compare(lat: Lattice, net: Net, mass: float, src: torch.Tensor, shift=0.0, tol=1e-10, max_iter=100000):
+    """Plain double precision CG against flexible CG with the network, both
+    from x = 0 on the same source: iterations, time and true residuals."""
+    out = {}
+    for name, n in (("plain", None), ("net", net)):
+        x = torch.zeros_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rc, st = lat.fcg_solve(mass, shift, src, x, net=n, tol=tol, max_iter=max_iter)
+        torch.cuda.synchronize()
+        out[name] = dict(status=rc, iters=st["iters"], seconds=time.perf_counter() - t0,
+                         resid_true=st["resid_true"][0], fallback=st["fallback_used"])
+    return out

@@ -1,0 +1,276 @@
+"""GPU parity of the learned preconditioner (C ABI) with the FP64 oracle.
+
+Tolerances:
+  * FP32 mode: links, input and weights rounded to single precision and
+    about 10^2 single precision operations per output; measured ~2e-7,
+    bound 1e-5 norm-relative, for outputs and for every block of the
+    gradient.
+  * BF16 mode: the 144 real layer-2 inputs are rounded to bfloat16 (8-bit
+    significand, 2^-9 relative) before the matrix-core contraction with
+    bfloat16 weights; sums of ~10^2 such terms give ~3e-3 norm-relative,
+    bound 1e-2.  In the gradient only the output-weight block uses the
+    BF16 layer-2 values; the other blocks stay at the FP32 bound.
+  * Flexible CG: the FP64 true residual of the result <= tol (1e-10),
+    checked with the oracle's operator.
+"""
+import numpy as np
+import pytest
+
+import stag_synth as syn
+from tests import lattice_np as ln
+from tests.gpu_common import lattice_with_links, links_np, log, pack, rel, to_dev, unpack
+
+pytestmark = pytest.mark.gpu
+
+NP = 656
+W1S, W1H, W2, WOUT = 0, 8, 72, 648
+BLOCKS = {"w1s": (0, 8), "w1h": (8, 72), "W2": (72, 648), "wout": (648, 656)}
+CASES = [((4, 4, 4, 4), "haar", "18"), ((4, 6, 4, 2), "smooth", "12"), ((8, 8, 8, 8), "smooth", "12"),
+         ((6, 4, 2, 8), "haar", "18")]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1010_5433_amd  # noqa: F401
+
+
+def rand_theta(seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    return scale * (rng.standard_normal(NP) + 1j * rng.standard_normal(NP))
+
+
+def poly_theta(c_self, c_dd, scale=1.0):
+    """P = scale * (c_self + c_dd D_eo D_oe) through channel 0."""
+    th = np.zeros(NP, np.complex128)
+    th[W1S] = 1.0
+    for d in range(8):
+        th[W1H + d] = 0.5 if d < 4 else -0.5
+        th[W2 + 8 + 8 * d] = c_dd * (0.5 if d < 4 else -0.5)
+    th[W2] = c_self
+    th[WOUT] = scale
+    return th
+
+
+def _setup(dims, kind, fmt, seed=21):
+    U = links_np(dims, kind, 0.5, seed)
+    return U, lattice_with_links(dims, U, fmt)
+
+
+@pytest.mark.parametrize("dims,kind,fmt", CASES)
+def test_net_forward_fp32_vs_oracle(orc, dims, kind, fmt):
+    import paper_1010_5433_amd as stag
+    log(f"net forward fp32 {dims} {kind} fmt={fmt}")
+    U, lat = _setup(dims, kind, fmt)
+    th = rand_theta(3)
+    r = syn.gaussian_source(dims, 4)
+    net = stag.Net(th)
+    got = unpack(lat, net.apply(lat, pack(lat, r, "f32"), mode="fp32"))
+    want = orc.net_forward(dims, U, th, r)
+    assert rel(got, want) <= 1e-5
+
+
+@pytest.mark.parametrize("dims,kind,fmt", CASES)
+def test_net_forward_bf16_matrix_cores(orc, dims, kind, fmt):
+    """BF16 mode vs the oracle and vs the FP32 mode: a wrong operand or
+    result layout of the matrix-core instruction gives O(1) errors."""
+    import paper_1010_5433_amd as stag
+    log(f"net forward bf16 {dims} {kind} fmt={fmt}")
+    U, lat = _setup(dims, kind, fmt)
+    th = rand_theta(5)
+    r = syn.gaussian_source(dims, 6)
+    net = stag.Net(th)
+    r32 = pack(lat, r, "f32")
+    got = unpack(lat, net.apply(lat, r32, mode="bf16"))
+    ref32 = unpack(lat, net.apply(lat, r32, mode="fp32"))
+    want = orc.net_forward(dims, U, th, r)
+    e = rel(got, want)
+    log(f"  bf16 rel {e:.2e}")
+    assert e <= 1e-2
+    assert rel(got, ref32) <= 1e-2
+    # the error is spread over sites, not concentrated in a tile
+    per_site = np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1).mean()
+    assert per_site.max() <= 5e-2
+
+
+@pytest.mark.parametrize("dims,kind,fmt", CASES)
+def test_net_grad_vs_oracle(orc, dims, kind, fmt):
+    import paper_1010_5433_amd as stag
+    log(f"net grad {dims} {kind} fmt={fmt}")
+    U, lat = _setup(dims, kind, fmt)
+    th = rand_theta(7)
+    r = syn.gaussian_source(dims, 8)
+    g = syn.gaussian_source(dims, 9)
+    net = stag.Net(th)
+    r32, g32 = pack(lat, r, "f32"), pack(lat, g, "f32")
+    want = orc.net_backward(dims, U, th, r, g)
+    for mode in ("fp32", "bf16"):
+        got = net.grad(lat, r32, g32, mode=mode)
+        for name, (a, b) in BLOCKS.items():
+            bound = 1e-2 if (mode == "bf16" and name == "wout") else 1e-5
+            e = rel(got[a:b], want[a:b])
+            log(f"  {mode} {name} rel {e:.2e}")
+            assert e <= bound, (mode, name, e)
+
+
+def test_net_grad_deterministic():
+    import paper_1010_5433_amd as stag
+    dims = (8, 8, 8, 8)
+    U, lat = _setup(dims, "smooth", "12")
+    net = stag.Net(rand_theta(11))
+    r32 = pack(lat, syn.gaussian_source(dims, 1), "f32")
+    g32 = pack(lat, syn.gaussian_source(dims, 2), "f32")
+    a = net.grad(lat, r32, g32, mode="bf16")
+    b = net.grad(lat, r32, g32, mode="bf16")
+    assert np.array_equal(a, b)
+
+
+def test_net_reduces_to_normal_operator_on_gpu(orc):
+    """P with the weights of m^2 - D_eo D_oe equals the library's own normal
+    operator (FP32 mode)."""
+    import paper_1010_5433_amd as stag
+    dims = (8, 8, 8, 8)
+    U, lat = _setup(dims, "smooth", "18")
+    m = 0.3
+    net = stag.Net(poly_theta(m * m, -1.0))
+    r = syn.gaussian_source(dims, 3)
+    got = unpack(lat, net.apply(lat, pack(lat, r, "f32"), mode="fp32"))
+    assert rel(got, orc.normal_op(dims, U, m, 0.0, r)) <= 1e-5
+
+
+def test_net_gauge_equivariant_on_gpu():
+    import paper_1010_5433_amd as stag
+    dims = (4, 4, 4, 8)
+    V = int(np.prod(dims))
+    U = syn.haar_links(dims, 7)
+    omega = syn.haar_su3(V, np.random.default_rng(9))
+    Ug = ln.gauge_transform(dims, U, omega)
+    ev = ln.sites_of_parity(dims, 0)
+    r = syn.gaussian_source(dims, 8)
+    net = stag.Net(rand_theta(10))
+    lat, latg = lattice_with_links(dims, U, "18"), lattice_with_links(dims, Ug, "18")
+    rg = np.einsum("nij,nj->ni", omega[ev], r)
+    for mode in ("fp32", "bf16"):
+        lhs = unpack(latg, net.apply(latg, pack(latg, rg, "f32"), mode=mode))
+        rhs = np.einsum("nij,nj->ni", omega[ev], unpack(lat, net.apply(lat, pack(lat, r, "f32"), mode=mode)))
+        assert rel(lhs, rhs) <= (1e-5 if mode == "fp32" else 2e-2)
+
+
+def test_net_params_roundtrip_and_validation():
+    import paper_1010_5433_amd as stag
+    th = rand_theta(1)
+    net = stag.Net(th)
+    got = net.get_params()
+    assert np.allclose(got, th.astype(np.complex64), rtol=0, atol=1e-6)
+    dims = (4, 4, 4, 4)
+    U, lat = _setup(dims, "haar", "18")
+    r32 = pack(lat, syn.gaussian_source(dims, 1), "f32")
+    with pytest.raises(stag.StagError):
+        net.apply(lat, r32, out=r32)           # in place is rejected
+    with pytest.raises(stag.StagError):
+        net.apply(lat, r32, mode=7)
+
+
+def test_train_step_reduces_loss():
+    import paper_1010_5433_amd as stag
+    from paper_1010_5433_amd import learn
+    dims = (4, 4, 4, 8)
+    U, lat = _setup(dims, "smooth", "18")
+    B, X = learn.make_pairs(lat, 0.1, 8, seed=3)
+    net = stag.Net(learn.init_theta(0))
+    losses = learn.train(net, [(lat, B, X)], steps=60, batch=8, lr=1e-2)
+    log(f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert np.isfinite(losses).all()
+    assert losses[-1] < 0.6 * losses[0]
+
+
+def _lambda_max(lat, mass, dims, iters=60):
+    import torch
+    x = pack(lat, syn.gaussian_source(dims, 99))
+    lam = 0.0
+    for _ in range(iters):
+        y = lat.normal_op(mass, 0.0, x)
+        lam = float((x * y).sum() / (x * x).sum())
+        x = y / torch.linalg.vector_norm(y)
+    return lam
+
+
+def test_fcg_plain_matches_oracle(orc):
+    dims = (8, 8, 8, 8)
+    U, lat = _setup(dims, "smooth", "12")
+    m = 0.05
+    b = syn.gaussian_source(dims, 31)
+    src = pack(lat, b)
+    import torch
+    x = torch.zeros_like(src)
+    _, rc, st = lat.fcg_solve(m, 0.0, src, x, net=None, tol=1e-10)
+    sol = unpack(lat, x)
+    assert rc == 0 and st["fallback_used"] == 0
+    assert orc.true_residual(dims, U, m, 0.0, b, sol) <= 1e-10
+
+
+def test_fcg_polynomial_preconditioner_gains(orc):
+    """P = (a + b) - M, a and b bounds of the spectrum of M: the preconditioned
+    operator has condition number (a+b)^2/(4ab) instead of b/a, so flexible
+    CG needs about half the iterations; the result meets tol."""
+    import torch
+    import paper_1010_5433_amd as stag
+    dims = (8, 8, 8, 8)
+    U, lat = _setup(dims, "smooth", "12")
+    m = 0.05
+    lmax = 1.02 * _lambda_max(lat, m, dims)
+    a, bb = m * m, lmax
+    net = stag.Net(poly_theta(a + bb - m * m, 1.0, scale=1.0 / bb))
+    b = syn.gaussian_source(dims, 32)
+    src = pack(lat, b)
+    x0, x1 = torch.zeros_like(src), torch.zeros_like(src)
+    _, rc0, st0 = lat.fcg_solve(m, 0.0, src, x0, net=None, tol=1e-10)
+    _, rc1, st1 = lat.fcg_solve(m, 0.0, src, x1, net=net, tol=1e-10)
+    log(f"plain {st0['iters']} iterations, polynomial-preconditioned {st1['iters']} (lambda_max {lmax:.3f})")
+    assert rc1 == 0 and st1["fallback_used"] == 0
+    assert orc.true_residual(dims, U, m, 0.0, b, unpack(lat, x1)) <= 1e-10
+    assert st1["iters"] <= 0.7 * st0["iters"]
+
+
+def test_fcg_fallback_on_indefinite_preconditioner(orc):
+    """P = -I makes <r, P r> < 0: the solver abandons the network, finishes
+    with plain CG from where it was and still meets tol."""
+    import torch
+    import paper_1010_5433_amd as stag
+    dims = (4, 4, 4, 8)
+    U, lat = _setup(dims, "smooth", "18")
+    m = 0.1
+    net = stag.Net(poly_theta(-1.0, 0.0))
+    b = syn.gaussian_source(dims, 33)
+    src = pack(lat, b)
+    x = torch.zeros_like(src)
+    _, rc, st = lat.fcg_solve(m, 0.0, src, x, net=net, tol=1e-10)
+    assert rc == 0 and st["fallback_used"] == 1
+    assert orc.true_residual(dims, U, m, 0.0, b, unpack(lat, x)) <= 1e-10
+
+
+def test_trained_network_gains_over_plain_cg(orc):
+    """Train on two fields (pairs b = M x), evaluate on a held-out field:
+    fewer iterations than plain CG, same FP64 residual."""
+    import paper_1010_5433_amd as stag
+    from paper_1010_5433_amd import learn
+    dims, m = (8, 8, 8, 8), 0.05
+    data = []
+    for k, seed in enumerate((500, 501)):
+        U = links_np(dims, "smooth", 0.5, seed)
+        lat = lattice_with_links(dims, U, "12")
+        B, X = learn.make_pairs(lat, m, 16, seed=600 + k)
+        data.append((lat, B, X))
+    net = stag.Net(learn.init_theta(0))
+    losses = learn.train(net, data, steps=300, batch=8, lr=1e-2, log=log)
+    Ut = links_np(dims, "smooth", 0.5, 550)
+    latt = lattice_with_links(dims, Ut, "12")
+    b = syn.gaussian_source(dims, 650)
+    res = learn.compare(latt, net, m, pack(latt, b))
+    log(f"held-out: {res}")
+    assert res["net"]["status"] == 0 and res["net"]["fallback"] == 0
+    assert res["net"]["resid_true"] <= 1e-10
+    assert res["net"]["iters"] <= 0.8 * res["plain"]["iters"]
+    assert losses[-1] < losses[0]
