@@ -113,6 +113,74 @@ def cpu_baseline(dims, U, b, mass, shifts, gpu_iters, sample_iters):
                        f"{gpu_iters} iterations; {per_iter * 1e3:.1f} ms per iteration")
 
 
+def learned_experiment(args, n_test_fields):
+    """Train the gauge-equivariant preconditioner on 16^4 fields and judge it
+    in flexible CG on held-out 32^4 fields against plain FP64 CG."""
+    import numpy as np
+    import torch
+
+    import paper_1010_5433_amd as stag
+    import stag_synth as syn
+    from paper_1010_5433_amd import learn
+
+    c = syn.config("c5_learned")
+    mass, tol = c["mass"], c["tol"]
+    nf = args.train_fields or len(c["train_link_seeds"])
+    npairs = args.train_pairs or c["sources_per_field"]
+    t0 = time.perf_counter()
+    data = []
+    for k, seed in enumerate(c["train_link_seeds"][:nf]):
+        U = syn.smooth_links(c["train_dims"], c["eps"], seed)
+        lat = stag.Lattice(c["train_dims"])
+        lat.set_links(torch.from_numpy(U).cuda(), "12")
+        maker = learn.solve_pairs if args.pairs == "solve" else learn.make_pairs
+        B, X = maker(lat, mass, npairs, seed=c["train_source_seed"] + k)
+        data.append((lat, B, X))
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    log(f"learned: {nf} fields x {npairs} pairs ({args.pairs}) in {t_data:.1f} s")
+    net = stag.Net(learn.init_theta(0, args.init_scale))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = []
+    lr = args.lr
+    for phase in range(3):   # step size lr, lr/3, lr/10
+        n = args.train_steps // 3 if phase < 2 else args.train_steps - 2 * (args.train_steps // 3)
+        losses += learn.train(net, data, n, args.batch, lr, seed=phase, log=log)
+        lr = args.lr / (3.0 if phase == 0 else 10.0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"learned: {args.train_steps} Adam steps of {args.batch} pairs in {t_train:.1f} s, "
+        f"loss {losses[0]:.4f} -> {np.mean(losses[-20:]):.4f}")
+    del data
+    evals = []
+    for k, seed in enumerate(c["test_link_seeds"][:n_test_fields]):
+        U = syn.smooth_links(c["test_dims"], c["eps"], seed)
+        lat = stag.Lattice(c["test_dims"])
+        lat.set_links(torch.from_numpy(U).cuda(), args.fmt)
+        b = syn.gaussian_source(c["test_dims"], c["test_source_seed"] + k)
+        src = lat.pack(torch.from_numpy(b).cuda())
+        learn.compare(lat, net, mass, src, tol=tol)          # warm-up
+        res = learn.compare(lat, net, mass, src, tol=tol)
+        for name in ("plain", "net"):
+            if res[name]["status"] != 0 or res[name]["resid_true"] > tol:
+                raise RuntimeError(f"learned evaluation failed: {name} {res[name]}")
+        log(f"held-out field {seed}: plain {res['plain']['iters']} it {res['plain']['seconds']:.4f} s, "
+            f"net {res['net']['iters']} it {res['net']['seconds']:.4f} s")
+        evals.append(dict(field_seed=seed, **{f"{n}_{k2}": v for n in ("plain", "net")
+                                               for k2, v in res[n].items() if k2 != "status"}))
+        del lat
+    it_gain = float(np.mean([e["plain_iters"] / e["net_iters"] for e in evals]))
+    tts_gain = float(np.mean([e["plain_seconds"] / e["net_seconds"] for e in evals]))
+    return dict(train=dict(dims=list(c["train_dims"]), fields=nf, pairs_per_field=npairs, pairs=args.pairs,
+                           steps=args.train_steps, batch=args.batch, lr=args.lr, mode="bf16",
+                           seconds=round(t_train, 2), data_seconds=round(t_data, 2),
+                           loss_first=round(losses[0], 5), loss_last=round(float(np.mean(losses[-20:])), 5)),
+                test=dict(dims=list(c["test_dims"]), mass=mass, shift=0.0, tol=tol, links=f"{args.fmt}-real",
+                          fields=evals),
+                iteration_gain=round(it_gain, 3), tts_gain=round(tts_gain, 3))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +194,17 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--only-dslash", type=int, default=0,
                     help="profiling aid: run N half-Dslash launches of the bench's precision and exit")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner experiment")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="run only the learned-preconditioner experiment (all held-out fields)")
+    ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=1e-2)
+    ap.add_argument("--init-scale", type=float, default=0.1)
+    ap.add_argument("--train-fields", type=int, default=0)
+    ap.add_argument("--train-pairs", type=int, default=0)
+    ap.add_argument("--pairs", default="mx", choices=["mx", "solve"])
+    ap.add_argument("--test-fields", type=int, default=4, help="held-out fields of --learned-only")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -138,6 +217,11 @@ def main():
 
     import paper_1010_5433_amd as stag
     import stag_synth as syn
+
+    if args.learned_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"learned": learned_experiment(args, args.test_fields)}), flush=True)
+        return
 
     c = syn.config("c3_32x32x32x32_smooth")
     dims, mass, tol = c["dims"], c["mass"], c["tol"]
@@ -244,6 +328,9 @@ def main():
         gbs = dslash_bytes_per_site(d, nrow) * lat.Vh / s / 1e9
         dsl[f"{p}_{args.fmt}"] = dict(us=round(s * 1e6, 2), GBs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
     log(f"dslash: {dsl}")
+
+    if not args.no_learned:
+        extra["learned"] = learned_experiment(args, 1)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -11,7 +11,6 @@ namespace stag {
 
 constexpr int kNetC = 8;                 // channels
 constexpr int kNetK = 72;                // layer-2 inputs per channel: self (8) + 8 hops x 8 channels
-constexpr int kNetKR = 160;              // real layer-2 inputs padded to 5 x 32 for the matrix cores
 constexpr int kNetW1S = 0, kNetW1H = 8, kNetW2 = 72, kNetWout = 648, kNetNParam = 656;
 
 enum NetMix { kMixBF16 = 0, kMixFP32 = 1 };
@@ -22,7 +21,8 @@ struct NetDev {
     float2 w1h[kNetC][8];          // [c][d]
     float2 W2[kNetC][kNetK];       // [c][k]
     float2 wout[kNetC];
-    __hip_bfloat16 B[16][kNetKR];  // real form of W2 for the matrix cores: B[n][kr]
+    alignas(16) __hip_bfloat16 B[5 * 4 * 16 * 8];   // real form of W2 in matrix-core operand order
+                                                     // [step][lane group][column][8 K values]
 };
 
 struct NetArgs {
@@ -32,17 +32,29 @@ struct NetArgs {
     const NetDev *w;
     const float2 *r;        // input  (samples x [3][V/2]) even sites
     float2 *out;            // output (samples x [3][V/2]) even sites
-    float2 *phi1;           // layer-1 field, odd sites: samples x [V/2][8][3]
-    float2 *phi2;           // layer-2 field, even sites: samples x [V/2][8][3] (training only; may be null)
+    float2 *phi1;           // layer-1 field, odd sites: samples x [8][3][V/2] (24 planes)
+    float2 *phi2;           // layer-2 field, even sites: samples x [8][3][V/2] (training only; may be null)
     int64_t vstride;        // complex entries between samples of r/out (3 V/2)
+    const int *skip;        // if non-null and *skip != 0 the forward kernels return at once
 };
 
-// per-lattice work buffers of the network (owned by the net handle)
-struct NetWork {
-    void *buf;
-    size_t bytes;
+// Work buffers of the network for n samples of a lattice (carved from the
+// net handle's arena).
+struct NetBufs {
+    float2 *phi1, *phi2, *out, *g, *g2, *partE, *partO;
+    double *xnorm2, *norm_part, *loss_part, *loss_rows;
+    double2 *grad;
 };
 
+}  // namespace stag
+
+struct stag_net;
+namespace stag {
+stag_status net_work(stag_net *net, const stag_lattice *lat, int n, NetBufs *b);
+NetArgs net_args(const stag_net *net, const stag_lattice *lat, const void *r, float2 *out, const NetBufs &b,
+                 bool keep_phi2);
+hipError_t net_launch_prep(const float2 *theta, NetDev *w, hipStream_t s);
+hipError_t net_launch_forward(const NetArgs &a, int n_samples, int mix, hipStream_t s);
 }  // namespace stag
 
 struct stag_net {

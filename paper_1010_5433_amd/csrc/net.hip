@@ -10,11 +10,13 @@
 // No weight touches colour, so P commutes with gauge transformations.
 //
 // Layer 2 is the dense contraction: per even site and colour, 72 complex
-// inputs against the 8 x 72 complex W2.  In BF16 mode the inputs of 64
-// sites are staged in LDS as BF16 and contracted on the matrix cores
-// (v_mfma_f32_16x16x32_bf16, FP32 accumulation) with the real 16 x 160 form
-// of W2; the FP32 mode runs the same contraction on the vector ALU.  The hop
-// gathers (links times colour vectors) are bandwidth work on the vector ALU.
+// inputs against the 8 x 72 complex W2.  In BF16 mode each lane rounds the
+// inputs it gathers to BF16 and feeds them, from registers, to the matrix
+// cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation) against a real
+// 16 x 160 form of W2; the FP32 mode runs the same contraction on the vector
+// ALU.  The hop gathers (links times colour vectors) are bandwidth work on
+// the vector ALU.  Feature fields are stored as 24 planes [channel][colour]
+// of V/2 sites so that neighbouring lanes read neighbouring words.
 // The backward pass runs in FP32 on the vector ALU in both modes; its
 // weight gradients are reduced per block into partials that one workgroup
 // per parameter sums in a fixed order.
@@ -74,22 +76,34 @@ __device__ __forceinline__ int hop_setup(const Geom &g, const void *links, int p
     return j;
 }
 
-// 24 complex (8 channels x 3 colours) of a site in a [V/2][8][3] field
-__device__ __forceinline__ void load24(const float2 *f, int j, float2 v[kNetC][3]) {
-    const float4 *p = reinterpret_cast<const float4 *>(f + (size_t)j * 24);
+// 24 complex (8 channels x 3 colours) of site j of a feature field stored as
+// 24 planes [channel][colour][V/2]: lanes of consecutive sites touch
+// consecutive 8-byte words of every plane.
+__device__ __forceinline__ void load24(const float2 *f, int64_t vh, int j, float2 v[kNetC][3]) {
 #pragma unroll
-    for (int q = 0; q < 12; ++q) {
-        const float4 t = p[q];
-        v[(2 * q) / 3][(2 * q) % 3] = make_float2(t.x, t.y);
-        v[(2 * q + 1) / 3][(2 * q + 1) % 3] = make_float2(t.z, t.w);
-    }
+    for (int c = 0; c < kNetC; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) v[c][b] = f[(c * 3 + b) * vh + j];
 }
-__device__ __forceinline__ void store24(float2 *f, int j, const float2 v[kNetC][3]) {
-    float4 *p = reinterpret_cast<float4 *>(f + (size_t)j * 24);
+__device__ __forceinline__ void store24(float2 *f, int64_t vh, int j, const float2 v[kNetC][3]) {
 #pragma unroll
-    for (int q = 0; q < 12; ++q)
-        p[q] = make_float4(v[(2 * q) / 3][(2 * q) % 3].x, v[(2 * q) / 3][(2 * q) % 3].y, v[(2 * q + 1) / 3][(2 * q + 1) % 3].x,
-                           v[(2 * q + 1) / 3][(2 * q + 1) % 3].y);
+    for (int c = 0; c < kNetC; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) f[(c * 3 + b) * vh + j] = v[c][b];
+}
+
+// Position p (0..39) of the K values that lane group kq feeds the matrix
+// cores, as an index kr into the real layer-2 input vector
+// (kr = 2 k + {0: re, 1: im}; k < 8 self inputs, k = 8 + 8 d + c' hop inputs),
+// or -1 for padding.  Group kq owns hops 2kq and 2kq+1 (positions 0..31) and
+// the self inputs of channels 2kq and 2kq+1 (positions 32..35).
+__device__ __forceinline__ int mfma_feature(int kq, int p) {
+    if (p < 32) {
+        const int d = 2 * kq + (p >> 4), cp = (p & 15) >> 1;
+        return 2 * (8 + 8 * d + cp) + (p & 1);
+    }
+    if (p < 36) return 2 * (2 * kq + ((p - 32) >> 1)) + (p & 1);
+    return -1;
 }
 
 // ---------------------------------------------------------------- weights
@@ -99,11 +113,14 @@ __global__ void __launch_bounds__(kNetBlock) k_net_prep(const float2 *theta, Net
     for (int j = t; j < kNetC * 8; j += kNetBlock) w->w1h[j / 8][j % 8] = theta[kNetW1H + j];
     for (int j = t; j < kNetC * kNetK; j += kNetBlock) w->W2[j / kNetK][j % kNetK] = theta[kNetW2 + j];
     for (int j = t; j < kNetC; j += kNetBlock) w->wout[j] = theta[kNetWout + j];
-    // real form: out_{2c} = sum_k Re W Re f - Im W Im f;  out_{2c+1} = sum_k Im W Re f + Re W Im f
-    for (int j = t; j < 16 * kNetKR; j += kNetBlock) {
-        const int n = j / kNetKR, kr = j % kNetKR;
+    // real form of W2: out_{2c} = sum_k Re W Re f - Im W Im f,
+    // out_{2c+1} = sum_k Im W Re f + Re W Im f; stored in the order the
+    // matrix-core B operand is read: B[step c][group kq][column n][8 values]
+    for (int j = t; j < 5 * 4 * 16 * 8; j += kNetBlock) {
+        const int e = j & 7, n = (j >> 3) & 15, kq = (j >> 7) & 3, c = j >> 9;
+        const int kr = mfma_feature(kq, 8 * c + e);
         float v = 0.f;
-        if (kr < 2 * kNetK) {
+        if (kr >= 0) {
             const float2 W = theta[kNetW2 + (n >> 1) * kNetK + (kr >> 1)];
             if ((n & 1) == 0) v = (kr & 1) ? -W.y : W.x;
             else v = (kr & 1) ? W.x : W.y;
@@ -115,7 +132,8 @@ __global__ void __launch_bounds__(kNetBlock) k_net_prep(const float2 *theta, Net
 // ---------------------------------------------------------------- forward layer 1 (odd sites)
 template <int NROW>
 __global__ void __launch_bounds__(kNetBlock) k_net_l1(NetArgs a) {
-    const int i = blockIdx.x * kNetBlock + threadIdx.x;
+    if (a.skip && *a.skip) return;
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * kNetBlock + threadIdx.x;
     const Geom &g = a.g;
     if (i >= g.Vh) return;
     const size_t so = blockIdx.y;
@@ -143,15 +161,23 @@ __global__ void __launch_bounds__(kNetBlock) k_net_l1(NetArgs a) {
             for (int b = 0; b < 3; ++b) acc[c][b] = caddf(acc[c][b], cmulf(w, h[b]));
         }
     }
-    store24(phi1, i, acc);
+    store24(phi1, g.Vh, i, acc);
 }
 
 // ---------------------------------------------------------------- forward layer 2 (even sites)
-// Block: 64 even sites x 4 threads; thread (sl, q) builds the inputs of the
-// hops d = 2q and 2q + 1 of its site (and the self inputs when q = 0).
+// Block: 4 waves x 16 even sites.  Lane (s16, kq) = (lane % 16, lane / 16)
+// builds, for site s16 of its wave, the inputs of hops 2kq and 2kq+1 and the
+// self inputs of channels 2kq and 2kq+1.  In BF16 mode these 36 (+4 zero)
+// real values per colour are exactly the lane's share of the A operand of
+// five v_mfma_f32_16x16x32_bf16 steps (16 sites x 160 K), so the
+// contraction with W2 runs from registers; the FP32 mode accumulates the
+// same products on the vector ALU and sums the four lane groups.
+// Operand layout of v_mfma_f32_16x16x32_bf16: lane l supplies row (A) or
+// column (B) l % 16 and the K values 8 (l / 16) .. 8 (l / 16) + 7 of each
+// step; it receives D rows 4 (l / 16) .. 4 (l / 16) + 3 of column l % 16.
 template <int NROW, int MIX>
 __global__ void __launch_bounds__(kNetBlock) k_net_l2(NetArgs a) {
-    __shared__ __attribute__((aligned(16))) __bf16 F[MIX == kMixBF16 ? 3 * kL2Sites * kNetKR : 8];
+    if (a.skip && *a.skip) return;
     const Geom &g = a.g;
     const size_t so = blockIdx.y;
     const float2 *r = a.r + so * a.vstride;
@@ -159,127 +185,133 @@ __global__ void __launch_bounds__(kNetBlock) k_net_l2(NetArgs a) {
     float2 *out = a.out + so * a.vstride;
     float2 *phi2 = a.phi2 ? a.phi2 + so * (size_t)g.Vh * 24 : nullptr;
     const NetDev *w = a.w;
-    const int t = threadIdx.x, sl = t >> 2, q = t & 3;
-    const int i = blockIdx.x * kL2Sites + sl;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int s16 = lane & 15, kq = lane >> 4;
+    const int site0 = xcd_tile(blockIdx.x, gridDim.x) * kL2Sites + 16 * wv;
+    const int i = site0 + s16;
     const bool valid = i < g.Vh;
-
-    float2 acc[kNetC][3];   // FP32 mode: this thread's share of phi2
-#pragma unroll
-    for (int c = 0; c < kNetC; ++c)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) acc[c][b] = make_float2(0.f, 0.f);
     int x[4] = {0, 0, 0, 0};
     if (valid) site_coords(g, 0, i, x);
 
-    if (q == 0) {   // self inputs f_c' = w1s[c'] r(x)
-        float2 rv[3];
+    // self inputs of channels 2kq, 2kq+1
+    float2 rv[3];
 #pragma unroll
-        for (int b = 0; b < 3; ++b) rv[b] = valid ? r[(size_t)b * g.Vh + i] : make_float2(0.f, 0.f);
+    for (int b = 0; b < 3; ++b) rv[b] = valid ? r[(size_t)b * g.Vh + i] : make_float2(0.f, 0.f);
+    float2 fs[2][3];
 #pragma unroll
-        for (int cp = 0; cp < kNetC; ++cp) {
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const float2 f = cmulf(w->w1s[cp], rv[b]);
-                if (MIX == kMixBF16) {
-                    F[(b * kL2Sites + sl) * kNetKR + 2 * cp] = static_cast<__bf16>(f.x);
-                    F[(b * kL2Sites + sl) * kNetKR + 2 * cp + 1] = static_cast<__bf16>(f.y);
-                } else {
-#pragma unroll
-                    for (int c = 0; c < kNetC; ++c) acc[c][b] = caddf(acc[c][b], cmulf(w->W2[c][cp], f));
-                }
-            }
-        }
-    } else if (q == 1 && MIX == kMixBF16) {   // zero padding of K
-        for (int b = 0; b < 3; ++b)
-            for (int kr = 2 * kNetK; kr < kNetKR; ++kr) F[(b * kL2Sites + sl) * kNetKR + kr] = static_cast<__bf16>(0.f);
-    }
-    for (int dd = 0; dd < 2; ++dd) {   // hop inputs f_{8+8d+c'} = (T_d phi1[c'])(x)
-        const int d = 2 * q + dd;
-        float2 v[kNetC][3];
-        su3<float> u;
-        float s = 0.f;
-        if (valid) {
-            const int j = hop_setup<NROW>(g, a.links, 0, i, x, d, u, s);
-            load24(phi1, j, v);
-        }
-#pragma unroll
-        for (int cp = 0; cp < kNetC; ++cp) {
-            float2 h[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-            if (valid) transport(u, s, d < 4, v[cp], h);
-            const int k = 8 + 8 * d + cp;
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                if (MIX == kMixBF16) {
-                    F[(b * kL2Sites + sl) * kNetKR + 2 * k] = static_cast<__bf16>(h[b].x);
-                    F[(b * kL2Sites + sl) * kNetKR + 2 * k + 1] = static_cast<__bf16>(h[b].y);
-                } else {
-#pragma unroll
-                    for (int c = 0; c < kNetC; ++c) acc[c][b] = caddf(acc[c][b], cmulf(w->W2[c][k], h[b]));
-                }
-            }
-        }
-    }
+        for (int b = 0; b < 3; ++b) fs[h][b] = cmulf(w->w1s[2 * kq + h], rv[b]);
 
     if (MIX == kMixBF16) {
-        __syncthreads();
-        // Wave wv contracts sites 16 wv .. 16 wv + 15, one colour at a time:
-        // D(16 sites x 16 real outputs) = F(16 x 160) W2r^T(160 x 16) in 5 steps of K = 32.
-        // Operand layout of v_mfma_f32_16x16x32_bf16: lane l supplies row (A) or
-        // column (B) l % 16 and the 8 K values 8 (l / 16) .. 8 (l / 16) + 7; it
-        // receives D rows 4 (l / 16) .. 4 (l / 16) + 3 of column l % 16.
-        const int lane = t & 63, wv = t >> 6;
-        const int m = lane & 15, kb = lane >> 4;
-        const __bf16 *Bw = reinterpret_cast<const __bf16 *>(w->B);
+        bf16x8 av[3][5];   // [colour][step]
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) av[b][4][e] = static_cast<__bf16>(0.f);
+            av[b][4][0] = static_cast<__bf16>(fs[0][b].x);
+            av[b][4][1] = static_cast<__bf16>(fs[0][b].y);
+            av[b][4][2] = static_cast<__bf16>(fs[1][b].x);
+            av[b][4][3] = static_cast<__bf16>(fs[1][b].y);
+        }
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {   // hop d = 2kq + hh fills steps 2hh, 2hh+1
+            const int d = 2 * kq + hh;
+            float2 v[kNetC][3];
+            su3<float> u;
+            float sg = 0.f;
+            if (valid) {
+                const int j = hop_setup<NROW>(g, a.links, 0, i, x, d, u, sg);
+                load24(phi1, g.Vh, j, v);
+            }
+#pragma unroll
+            for (int cp = 0; cp < kNetC; ++cp) {
+                float2 h[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+                if (valid) transport(u, sg, d < 4, v[cp], h);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    av[b][2 * hh + (cp >> 2)][2 * (cp & 3)] = static_cast<__bf16>(h[b].x);
+                    av[b][2 * hh + (cp >> 2)][2 * (cp & 3) + 1] = static_cast<__bf16>(h[b].y);
+                }
+            }
+        }
+        const bf16x8 *Bw = reinterpret_cast<const bf16x8 *>(w->B);
+        bf16x8 bv[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) bv[c] = Bw[(c * 4 + kq) * 16 + s16];
+        const int ch = s16 >> 1;   // D column n = s16: channel n / 2, real (n even) or imaginary part
+        const float2 wo = w->wout[ch];
+#pragma unroll
         for (int b = 0; b < 3; ++b) {
             f32x4 d4 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int ks = 0; ks < kNetKR / 32; ++ks) {
-                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&F[(b * kL2Sites + 16 * wv + m) * kNetKR + 32 * ks + 8 * kb]);
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&Bw[m * kNetKR + 32 * ks + 8 * kb]);
-                d4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, d4, 0, 0, 0);
-            }
-            // column n = m: channel n / 2, real (n even) or imaginary part; project onto wout
-            const int c = m >> 1;
-            const float2 wo = w->wout[c];
+            for (int c = 0; c < 5; ++c) d4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[b][c], bv[c], d4, 0, 0, 0);
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
                 const float v = d4[jj];
-                float pre = (m & 1) ? -wo.y * v : wo.x * v;
-                float pim = (m & 1) ? wo.x * v : wo.y * v;
+                float pre = (s16 & 1) ? -wo.y * v : wo.x * v;
+                float pim = (s16 & 1) ? wo.x * v : wo.y * v;
 #pragma unroll
                 for (int off = 8; off >= 1; off >>= 1) {
                     pre += __shfl_xor(pre, off, 16);
                     pim += __shfl_xor(pim, off, 16);
                 }
-                const int site = blockIdx.x * kL2Sites + 16 * wv + 4 * kb + jj;
+                const int site = site0 + 4 * kq + jj;
                 if (site < g.Vh) {
-                    if (m == 0) out[(size_t)b * g.Vh + site] = make_float2(pre, pim);
-                    if (phi2) reinterpret_cast<float *>(&phi2[(size_t)site * 24 + c * 3 + b])[m & 1] = v;
+                    if (s16 == 0) out[(size_t)b * g.Vh + site] = make_float2(pre, pim);
+                    if (phi2) reinterpret_cast<float *>(&phi2[(size_t)(ch * 3 + b) * g.Vh + site])[s16 & 1] = v;
                 }
             }
         }
     } else {
-        // sum the 4 threads of each site (adjacent lanes of one wave)
+        float2 acc[kNetC][3];   // this lane's share of phi2
+#pragma unroll
+        for (int c = 0; c < kNetC; ++c)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                acc[c][b] = caddf(cmulf(w->W2[c][2 * kq], fs[0][b]), cmulf(w->W2[c][2 * kq + 1], fs[1][b]));
+            }
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const int d = 2 * kq + hh;
+            float2 v[kNetC][3];
+            su3<float> u;
+            float sg = 0.f;
+            if (valid) {
+                const int j = hop_setup<NROW>(g, a.links, 0, i, x, d, u, sg);
+                load24(phi1, g.Vh, j, v);
+            }
+            for (int cp = 0; cp < kNetC; ++cp) {
+                float2 h[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+                if (valid) transport(u, sg, d < 4, v[cp], h);
+                const int k = 8 + 8 * d + cp;
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+#pragma unroll
+                    for (int c = 0; c < kNetC; ++c) acc[c][b] = caddf(acc[c][b], cmulf(w->W2[c][k], h[b]));
+            }
+        }
+        // sum the four lane groups of each site (lanes s16, s16+16, s16+32, s16+48)
 #pragma unroll
         for (int c = 0; c < kNetC; ++c)
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
                 float2 v = acc[c][b];
-                v.x += __shfl_xor(v.x, 1);
-                v.y += __shfl_xor(v.y, 1);
-                v.x += __shfl_xor(v.x, 2);
-                v.y += __shfl_xor(v.y, 2);
+                v.x += __shfl_xor(v.x, 16);
+                v.y += __shfl_xor(v.y, 16);
+                v.x += __shfl_xor(v.x, 32);
+                v.y += __shfl_xor(v.y, 32);
                 acc[c][b] = v;
             }
-        if (valid && q == 0) {
+        if (valid && kq == 0) {
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                float2 p = make_float2(0.f, 0.f);
+                float2 pv = make_float2(0.f, 0.f);
 #pragma unroll
-                for (int c = 0; c < kNetC; ++c) p = caddf(p, cmulf(w->wout[c], acc[c][b]));
-                out[(size_t)b * g.Vh + i] = p;
+                for (int c = 0; c < kNetC; ++c) pv = caddf(pv, cmulf(w->wout[c], acc[c][b]));
+                out[(size_t)b * g.Vh + i] = pv;
             }
-            if (phi2) store24(phi2, i, acc);
+            if (phi2) store24(phi2, g.Vh, i, acc);
         }
     }
 }
@@ -359,7 +391,7 @@ __global__ void __launch_bounds__(kNetBlock) k_net_bwd_even(NetArgs a, const flo
         float s = 0.f;
         if (valid) {
             const int j = hop_setup<NROW>(g, a.links, 0, i, x, d, u, s);
-            load24(phi1, j, v);
+            load24(phi1, g.Vh, j, v);
         }
         for (int cp = 0; cp < kNetC; ++cp) {
             float2 h[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
@@ -373,7 +405,7 @@ __global__ void __launch_bounds__(kNetBlock) k_net_bwd_even(NetArgs a, const flo
             rv[b] = valid ? r[(size_t)b * g.Vh + i] : make_float2(0.f, 0.f);
             gv[b] = valid ? gg[(size_t)b * g.Vh + i] : make_float2(0.f, 0.f);
         }
-        if (valid) load24(phi2, i, p2);
+        if (valid) load24(phi2, g.Vh, i, p2);
         for (int c = 0; c < kNetC; ++c) {
             float2 gw = make_float2(0.f, 0.f);
             for (int b = 0; b < 3; ++b) {
@@ -384,7 +416,7 @@ __global__ void __launch_bounds__(kNetBlock) k_net_bwd_even(NetArgs a, const flo
             }
             red_wout[sl][c] = gw;
         }
-        if (valid) store24(g2o, i, g2);
+        if (valid) store24(g2o, g.Vh, i, g2);
         for (int cp = 0; cp < kNetC; ++cp) {
             float2 gs = make_float2(0.f, 0.f);
             for (int b = 0; b < 3; ++b) {
@@ -440,7 +472,7 @@ __global__ void __launch_bounds__(kNetBlock) k_net_bwd_odd(NetArgs a, const floa
             float s;
             const int j = hop_setup<NROW>(g, a.links, 1, i, x, db, u, s);
             float2 gv[kNetC][3];
-            load24(g2, j, gv);
+            load24(g2, g.Vh, j, gv);
             for (int cp = 0; cp < kNetC; ++cp) {
                 float2 gf[3];
                 for (int b = 0; b < 3; ++b) {
