@@ -162,23 +162,26 @@ def learned_experiment(args, n_test_fields):
         src = lat.pack(torch.from_numpy(b).cuda())
         learn.compare(lat, net, mass, src, tol=tol)          # warm-up
         res = learn.compare(lat, net, mass, src, tol=tol)
-        for name in ("plain", "net"):
+        for name in res:
             if res[name]["status"] != 0 or res[name]["resid_true"] > tol:
                 raise RuntimeError(f"learned evaluation failed: {name} {res[name]}")
-        log(f"held-out field {seed}: plain {res['plain']['iters']} it {res['plain']['seconds']:.4f} s, "
-            f"net {res['net']['iters']} it {res['net']['seconds']:.4f} s")
-        evals.append(dict(field_seed=seed, **{f"{n}_{k2}": v for n in ("plain", "net")
+        log(f"held-out field {seed}: " + ", ".join(
+            f"{n} {res[n]['iters']} it {res[n]['seconds']:.4f} s" for n in res))
+        evals.append(dict(field_seed=seed, **{f"{n}_{k2}": v for n in res
                                                for k2, v in res[n].items() if k2 != "status"}))
         del lat
-    it_gain = float(np.mean([e["plain_iters"] / e["net_iters"] for e in evals]))
-    tts_gain = float(np.mean([e["plain_seconds"] / e["net_seconds"] for e in evals]))
+    gains = {}
+    for mode in ("bf16", "folded"):
+        gains[mode] = dict(
+            iteration_gain=round(float(np.mean([e["plain_iters"] / e[f"{mode}_iters"] for e in evals])), 3),
+            tts_gain=round(float(np.mean([e["plain_seconds"] / e[f"{mode}_seconds"] for e in evals])), 3))
     return dict(train=dict(dims=list(c["train_dims"]), fields=nf, pairs_per_field=npairs, pairs=args.pairs,
                            steps=args.train_steps, batch=args.batch, lr=args.lr, mode="bf16",
                            seconds=round(t_train, 2), data_seconds=round(t_data, 2),
                            loss_first=round(losses[0], 5), loss_last=round(float(np.mean(losses[-20:])), 5)),
                 test=dict(dims=list(c["test_dims"]), mass=mass, shift=0.0, tol=tol, links=f"{args.fmt}-real",
                           fields=evals),
-                iteration_gain=round(it_gain, 3), tts_gain=round(tts_gain, 3))
+                gains=gains)
 
 
 def main():

@@ -228,10 +228,16 @@ stag_status stag_batch_last_config(int *block, int *rpt);
  * r and outputs are STAG_F32 library vectors of the lattice; the network
  * reads the lattice's single precision links.
  * mode 0: layer-2 channel mixing in BF16 on the matrix cores with FP32
- *         accumulation (the solver uses this mode);
- * mode 1: the same mixing in FP32 on the vector ALU (a check of mode 0).
- * The backward pass is FP32 in both modes; gradients are summed in a fixed
- * order (deterministic). */
+ *         accumulation;
+ * mode 1: the same mixing in FP32 on the vector ALU (a check of mode 0);
+ * mode 2: the folded form.  The network is linear and the hops act on
+ *         colour only, so with v_k = sum_c wout[c] W2[c][k] it equals
+ *           P r = s r + sum_d T_d psi_d,  psi_d = sum_d' A[d][d'] T_d' r (odd sites),
+ *           s = sum_c v_c w1s[c],  A[d][d'] = sum_c v_{8+8d+c} w1h[c][d'];
+ *         evaluated in FP32, layer 2 then gathers one colour vector per hop
+ *         instead of eight.  Forward only (stag_net_apply, stag_fcg_solve).
+ * The backward pass is FP32 in modes 0 and 1; gradients are summed in a
+ * fixed order (deterministic). */
 typedef struct stag_net stag_net;
 
 /* Create a network on the current device with every parameter zero. */
@@ -249,7 +255,7 @@ stag_status stag_net_apply(stag_net *net, stag_lattice *lat, const void *r, void
 
 /* Gradient of L = Re sum_x <g(x), P(r)(x)> with respect to the parameters,
  * written to the HOST array grad[1312] as dL/dRe, dL/dIm of each theta_j.
- * r, g: STAG_F32 library vectors.  Synchronous. */
+ * r, g: STAG_F32 library vectors; mode 0 or 1.  Synchronous. */
 stag_status stag_net_grad(stag_net *net, stag_lattice *lat, const void *r, const void *g, double *grad,
                           int mode, void *stream);
 
@@ -263,15 +269,19 @@ stag_status stag_net_train_step(stag_net *net, stag_lattice *lat, const void *b,
 
 /* Flexible CG with P as preconditioner (Polak-Ribiere beta) for
  * (M + shift) x = src from the x passed in (STAG_F64 library vectors; sol
- * is read and overwritten).  net == NULL runs plain double precision CG.
- * The residual is re-computed in double precision from x whenever the
- * iterated one reaches tol ||src|| (the judge), and the solver falls back
- * to plain double precision CG, warm-started, when <r, P r> <= 0, a
- * curvature is not positive or finite, or the residual stalls for 50
- * iterations (stats->fallback_used = 1).  stats->iters counts both parts;
- * stats->resid_true[0] is the final relative true residual.  Synchronous. */
+ * is read and overwritten).  The network is evaluated in `mode` (0, 1 or 2)
+ * on a single precision copy of the residual; everything else is double
+ * precision.  net == NULL runs plain double precision CG.  The residual is
+ * re-computed in double precision from x whenever the iterated one reaches
+ * tol ||src|| (the judge); the iteration stops if it meets tol, else it
+ * restarts from it.  The solver falls back to plain double precision CG,
+ * warm-started, when <r, P r> <= 0, a curvature is not positive or finite,
+ * or the residual stalls for 50 iterations (stats->fallback_used = 1).
+ * stats->iters counts both parts; stats->resid_true[0] is the final
+ * relative true residual.  Synchronous. */
 stag_status stag_fcg_solve(stag_lattice *lat, double mass, double shift, const void *src, void *sol,
-                           stag_net *net, double tol, int max_iter, stag_cg_stats *stats, void *stream);
+                           stag_net *net, int mode, double tol, int max_iter, stag_cg_stats *stats,
+                           void *stream);
 
 /* Bandwidth probe used by the benchmark to measure the achievable HBM rate
  * in the same run.  kind 0: read `bytes` from src (dst receives nothing in

@@ -16,7 +16,7 @@ import os
 
 import torch
 
-from ._abi import (F32, F64, MIXED, LINK12, LINK18, MIX_BF16, MIX_FP32, NET_NPARAM, CgStats, StagError,
+from ._abi import (F32, F64, MIXED, LINK12, LINK18, MIX_BF16, MIX_FOLDED, MIX_FP32, NET_NPARAM, CgStats, StagError,
                    System, batch_flags, load_library, status_name)
 
 __all__ = ["Lattice", "CgStats", "StagError", "F64", "F32", "MIXED", "LINK18", "LINK12",
@@ -153,18 +153,19 @@ class Lattice:
                                int(max_iter), _PREC[prec], ctypes.byref(st), _stream()), "stag_cg")
         return x, rc, st.to_dict(1)
 
-    def fcg_solve(self, mass, shift, src: torch.Tensor, x: torch.Tensor, net=None, tol=1e-10,
+    def fcg_solve(self, mass, shift, src: torch.Tensor, x: torch.Tensor, net=None, mode="bf16", tol=1e-10,
                   max_iter=100000):
         """Flexible CG for (M + shift) x = src preconditioned by `net` (a Net, or
-        None for plain double precision CG), from the given x (overwritten)."""
+        None for plain double precision CG) evaluated in `mode` ("bf16",
+        "fp32" or "folded"), from the given x (overwritten)."""
         st = CgStats()
         rc = _check(_L.stag_fcg_solve(self._h, float(mass), float(shift), _ptr(src), _ptr(x),
-                                      net._h if net is not None else None, float(tol), int(max_iter),
-                                      ctypes.byref(st), _stream()), "stag_fcg_solve")
+                                      net._h if net is not None else None, _MIX.get(mode, mode), float(tol),
+                                      int(max_iter), ctypes.byref(st), _stream()), "stag_fcg_solve")
         return x, rc, st.to_dict(1)
 
 
-_MIX = {"bf16": MIX_BF16, "fp32": MIX_FP32, MIX_BF16: MIX_BF16, MIX_FP32: MIX_FP32}
+_MIX = {"bf16": MIX_BF16, "fp32": MIX_FP32, "folded": MIX_FOLDED}
 
 
 class Net:

@@ -11,7 +11,7 @@ F64, F32, MIXED = 0, 1, 2
 LINK18, LINK12 = 0, 1
 MAX_SHIFTS = 64
 NET_NPARAM = 656
-MIX_BF16, MIX_FP32 = 0, 1
+MIX_BF16, MIX_FP32, MIX_FOLDED = 0, 1, 2
 
 _NAMES = {0: "STAG_OK", 1: "STAG_ENOCONV", 2: "STAG_EBREAKDOWN", -1: "STAG_EINVAL",
           -2: "STAG_ENOMEM", -3: "STAG_EHIP"}
@@ -95,7 +95,7 @@ SIGNATURES = {
     "stag_net_apply": (_i, [_v, _v, _v, _v, _i, _v]),
     "stag_net_grad": (_i, [_v, _v, _v, _v, ctypes.POINTER(_d), _i, _v]),
     "stag_net_train_step": (_i, [_v, _v, _v, _v, _i, _d, _i, ctypes.POINTER(_d), _v]),
-    "stag_fcg_solve": (_i, [_v, _d, _d, _v, _v, _v, _d, _i, ctypes.POINTER(CgStats), _v]),
+    "stag_fcg_solve": (_i, [_v, _d, _d, _v, _v, _v, _i, _d, _i, ctypes.POINTER(CgStats), _v]),
     "stag_hbm_probe": (_i, [_v, _v, ctypes.c_int64, _i, _v]),
     "stag_status_string": (ctypes.c_char_p, [_i]),
     "stag_last_error": (ctypes.c_char_p, []),

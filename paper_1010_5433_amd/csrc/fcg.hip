@@ -108,13 +108,14 @@ __global__ void __launch_bounds__(kFcgBlock) k_fcg_alpha(FcgState *st, const dou
     }
 }
 
-// |r|^2, convergence, stagnation; beta (Polak-Ribiere) and the new <r, z>
+// |r|^2, convergence, stagnation; beta (Polak-Ribiere) and the new <r, z>.
+// r_{k+1} - r_k = -alpha_k q_k, so <z_{k+1}, r_{k+1} - r_k> = -alpha_k <z_{k+1}, q_k>.
 __global__ void __launch_bounds__(kFcgBlock) k_fcg_beta(FcgState *st, const double *part_rr, int n_rr,
                                                      const double *part_a, const double *part_b, int n_ab) {
     __shared__ double red[kFcgBlock / kWave];
     if (st->run != FCG_RUNNING) return;
     const double rr = fixed_sum(part_rr, n_rr, red);
-    const double za = fixed_sum(part_a, n_ab, red);
+    const double za = -st->alpha * fixed_sum(part_a, n_ab, red);
     const double rz = fixed_sum(part_b, n_ab, red);
     if (threadIdx.x != 0) return;
     st->iter += 1;
@@ -146,10 +147,9 @@ __global__ void __launch_bounds__(kFcgBlock) k_fcg_beta(FcgState *st, const doub
     st->rz = rz;
 }
 
-// x += alpha p; r_old = r; r -= alpha q; r32 = (float) r; partial |r|^2
-__global__ void __launch_bounds__(kFcgBlock) k_fcg_step(const FcgState *st, double2 *x, double2 *r, double2 *rold,
-                                                     float2 *r32, const double2 *p, const double2 *q, int64_t n,
-                                                     double *part) {
+// x += alpha p; r -= alpha q; r32 = (float) r; partial |r|^2
+__global__ void __launch_bounds__(kFcgBlock) k_fcg_step(const FcgState *st, double2 *x, double2 *r, float2 *r32,
+                                                     const double2 *p, const double2 *q, int64_t n, double *part) {
     __shared__ double red[kFcgBlock / kWave];
     if (st->run != FCG_RUNNING) return;
     const double alpha = st->alpha;
@@ -157,7 +157,6 @@ __global__ void __launch_bounds__(kFcgBlock) k_fcg_step(const FcgState *st, doub
     for (int64_t j = (int64_t)blockIdx.x * kFcgBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kFcgBlock) {
         const double2 pv = p[j], qv = q[j];
         double2 xv = x[j], rv = r[j];
-        rold[j] = rv;
         xv.x += alpha * pv.x;
         xv.y += alpha * pv.y;
         rv.x -= alpha * qv.x;
@@ -171,29 +170,31 @@ __global__ void __launch_bounds__(kFcgBlock) k_fcg_step(const FcgState *st, doub
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// r32 = (float) r; r_old = 0 (start and restart)
+// r32 = (float) r (start and restart)
 __global__ void __launch_bounds__(kFcgBlock) k_fcg_demote(const FcgState *st, const double2 *r, float2 *r32,
-                                                       double2 *rold, int64_t n) {
+                                                       int64_t n) {
     if (st->run != FCG_RUNNING) return;
-    for (int64_t j = (int64_t)blockIdx.x * kFcgBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kFcgBlock) {
+    for (int64_t j = (int64_t)blockIdx.x * kFcgBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kFcgBlock)
         r32[j] = make_float2(float(r[j].x), float(r[j].y));
-        rold[j] = make_double2(0.0, 0.0);
-    }
 }
 
-// z = (double) z32; partials of <z, r - r_old> and <r, z>; p = z when `first`
-__global__ void __launch_bounds__(kFcgBlock) k_fcg_z(const FcgState *st, const float2 *z32, double2 *z, double2 *p,
-                                                  int first, const double2 *r, const double2 *rold, int64_t n,
-                                                  double *part_a, double *part_b) {
+// z = P r arrives in single precision: partials of <z, q> and <r, z> (q = A p
+// of the step that produced r); p = z when `first`
+__global__ void __launch_bounds__(kFcgBlock) k_fcg_z(const FcgState *st, const float2 *z32, double2 *p, int first,
+                                                  const double2 *r, const double2 *q, int64_t n, double *part_a,
+                                                  double *part_b) {
     __shared__ double red[kFcgBlock / kWave];
     if (st->run != FCG_RUNNING) return;
     double a = 0.0, b = 0.0;
     for (int64_t j = (int64_t)blockIdx.x * kFcgBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kFcgBlock) {
         const double2 zv = make_double2(double(z32[j].x), double(z32[j].y));
-        z[j] = zv;
-        if (first) p[j] = zv;
-        const double2 rv = r[j], ro = rold[j];
-        a += zv.x * (rv.x - ro.x) + zv.y * (rv.y - ro.y);
+        if (first) {
+            p[j] = zv;
+        } else {
+            const double2 qv = q[j];
+            a += zv.x * qv.x + zv.y * qv.y;
+        }
+        const double2 rv = r[j];
         b += zv.x * rv.x + zv.y * rv.y;
     }
     const double sa = block_sum(a, red);
@@ -205,14 +206,14 @@ __global__ void __launch_bounds__(kFcgBlock) k_fcg_z(const FcgState *st, const f
 }
 
 // p = z + beta p
-__global__ void __launch_bounds__(kFcgBlock) k_fcg_dir(const FcgState *st, double2 *p, const double2 *z, int64_t n) {
+__global__ void __launch_bounds__(kFcgBlock) k_fcg_dir(const FcgState *st, double2 *p, const float2 *z32, int64_t n) {
     if (st->run != FCG_RUNNING) return;
     const double beta = st->beta;
     for (int64_t j = (int64_t)blockIdx.x * kFcgBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kFcgBlock) {
-        const double2 zv = z[j];
+        const float2 zv = z32[j];
         double2 pv = p[j];
-        pv.x = zv.x + beta * pv.x;
-        pv.y = zv.y + beta * pv.y;
+        pv.x = double(zv.x) + beta * pv.x;
+        pv.y = double(zv.y) + beta * pv.y;
         p[j] = pv;
     }
 }
@@ -234,7 +235,7 @@ static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 static constexpr int kFcgChunk = 8;   // iterations enqueued between reads of the run word
 
 stag_status fcg_solve(stag_lattice *lat, double mass, double shift, const void *src, void *sol, stag_net *net,
-                      double tol, int max_iter, stag_cg_stats *stats, hipStream_t s) {
+                      int mode, double tol, int max_iter, stag_cg_stats *stats, hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
     stag_cg_stats st;
     std::memset(&st, 0, sizeof(st));
@@ -249,7 +250,7 @@ stag_status fcg_solve(stag_lattice *lat, double mass, double shift, const void *
     const int grid = (int)std::min<int64_t>((ne + kFcgBlock - 1) / kFcgBlock, 2048);
     const int nparts = std::max(ds_grid, grid);
     void *W = nullptr;
-    const size_t bytes = 6 * al(vb) + 2 * al(sizeof(float2) * ne) + 4 * al(sizeof(double) * nparts) +
+    const size_t bytes = 4 * al(vb) + 2 * al(sizeof(float2) * ne) + 4 * al(sizeof(double) * nparts) +
                          al(sizeof(FcgState)) + 256;
     STAG_TRY(ws_get(lat, WS_E2, bytes, &W));
     char *cur = static_cast<char *>(W);
@@ -259,8 +260,7 @@ stag_status fcg_solve(stag_lattice *lat, double mass, double shift, const void *
         return q;
     };
     double2 *x = static_cast<double2 *>(sol), *b = static_cast<double2 *>(const_cast<void *>(src));
-    double2 *r = reinterpret_cast<double2 *>(take(vb)), *rold = reinterpret_cast<double2 *>(take(vb));
-    double2 *z = reinterpret_cast<double2 *>(take(vb)), *p = reinterpret_cast<double2 *>(take(vb));
+    double2 *r = reinterpret_cast<double2 *>(take(vb)), *p = reinterpret_cast<double2 *>(take(vb));
     double2 *q = reinterpret_cast<double2 *>(take(vb)), *t = reinterpret_cast<double2 *>(take(vb));
     float2 *r32 = reinterpret_cast<float2 *>(take(sizeof(float2) * ne));
     float2 *z32 = reinterpret_cast<float2 *>(take(sizeof(float2) * ne));
@@ -301,13 +301,13 @@ stag_status fcg_solve(stag_lattice *lat, double mass, double shift, const void *
     // z = P(r) from r (double), p = z, <r, z>
     auto start_direction = [&]() -> hipError_t {
         hipLaunchKernelGGL(k_fcg_demote, dim3(grid), dim3(kFcgBlock), 0, s, (const FcgState *)dst, (const double2 *)r,
-                           r32, rold, ne);
+                           r32, ne);
         NetArgs a = net_args(net, lat, r32, z32, nb, false);
         a.skip = skip;
-        hipError_t err = net_launch_forward(a, 1, kMixBF16, s);
+        hipError_t err = net_launch_forward(a, 1, mode, s);
         if (err != hipSuccess) return err;
-        hipLaunchKernelGGL(k_fcg_z, dim3(grid), dim3(kFcgBlock), 0, s, (const FcgState *)dst, (const float2 *)z32, z, p,
-                           1, (const double2 *)r, (const double2 *)rold, ne, pa, pb);
+        hipLaunchKernelGGL(k_fcg_z, dim3(grid), dim3(kFcgBlock), 0, s, (const FcgState *)dst, (const float2 *)z32, p, 1,
+                           (const double2 *)r, (const double2 *)q, ne, pa, pb);
         hipLaunchKernelGGL(k_fcg_start, dim3(1), dim3(kFcgBlock), 0, s, dst, (const double *)pb, grid);
         return hipGetLastError();
     };
@@ -327,17 +327,17 @@ stag_status fcg_solve(stag_lattice *lat, double mass, double shift, const void *
         err = launch_dslash(true, lat->nrow, DS_NORMAL_DOT, e, s);
         if (err != hipSuccess) return err;
         hipLaunchKernelGGL(k_fcg_alpha, dim3(1), dim3(kFcgBlock), 0, s, dst, (const double *)pq, ds_grid);
-        hipLaunchKernelGGL(k_fcg_step, dim3(grid), dim3(kFcgBlock), 0, s, (const FcgState *)dst, x, r, rold, r32,
+        hipLaunchKernelGGL(k_fcg_step, dim3(grid), dim3(kFcgBlock), 0, s, (const FcgState *)dst, x, r, r32,
                            (const double2 *)p, (const double2 *)q, ne, prr);
         NetArgs a = net_args(net, lat, r32, z32, nb, false);
         a.skip = skip;
-        err = net_launch_forward(a, 1, kMixBF16, s);
+        err = net_launch_forward(a, 1, mode, s);
         if (err != hipSuccess) return err;
-        hipLaunchKernelGGL(k_fcg_z, dim3(grid), dim3(kFcgBlock), 0, s, (const FcgState *)dst, (const float2 *)z32, z, p,
-                           0, (const double2 *)r, (const double2 *)rold, ne, pa, pb);
+        hipLaunchKernelGGL(k_fcg_z, dim3(grid), dim3(kFcgBlock), 0, s, (const FcgState *)dst, (const float2 *)z32, p, 0,
+                           (const double2 *)r, (const double2 *)q, ne, pa, pb);
         hipLaunchKernelGGL(k_fcg_beta, dim3(1), dim3(kFcgBlock), 0, s, dst, (const double *)prr, grid,
                            (const double *)pa, (const double *)pb, grid);
-        hipLaunchKernelGGL(k_fcg_dir, dim3(grid), dim3(kFcgBlock), 0, s, (const FcgState *)dst, p, (const double2 *)z,
+        hipLaunchKernelGGL(k_fcg_dir, dim3(grid), dim3(kFcgBlock), 0, s, (const FcgState *)dst, p, (const float2 *)z32,
                            ne);
         return hipGetLastError();
     };

@@ -13,7 +13,9 @@ constexpr int kNetC = 8;                 // channels
 constexpr int kNetK = 72;                // layer-2 inputs per channel: self (8) + 8 hops x 8 channels
 constexpr int kNetW1S = 0, kNetW1H = 8, kNetW2 = 72, kNetWout = 648, kNetNParam = 656;
 
-enum NetMix { kMixBF16 = 0, kMixFP32 = 1 };
+// Evaluation modes: the layer-2 channel mixing in BF16 on the matrix cores,
+// the same in FP32 on the vector ALU, or the folded two-hop form (FP32).
+enum NetMix { kMixBF16 = 0, kMixFP32 = 1, kMixFolded = 2 };
 
 // Weights in the forms the kernels read.
 struct NetDev {
@@ -21,6 +23,10 @@ struct NetDev {
     float2 w1h[kNetC][8];          // [c][d]
     float2 W2[kNetC][kNetK];       // [c][k]
     float2 wout[kNetC];
+    // folded form of the (linear) network: P r = fsig r + sum_d T_d psi_d with
+    // psi_d = sum_d' fA[d][d'] T_d' r on odd sites
+    float2 fsig;
+    float2 fA[8][8];
     alignas(16) __hip_bfloat16 B[5 * 4 * 16 * 8];   // real form of W2 in matrix-core operand order
                                                      // [step][lane group][column][8 K values]
 };

@@ -107,8 +107,44 @@ __device__ __forceinline__ int mfma_feature(int kq, int p) {
 }
 
 // ---------------------------------------------------------------- weights
+// The network is linear and the hops act on colour only, so channel mixing
+// commutes with transport.  With v_k = sum_c wout[c] W2[c][k]:
+//   P r (x) = s r(x) + sum_d (T_d psi_d)(x),  s = sum_c' v_c' w1s[c'],
+//   psi_d(y) = sum_d' A[d][d'] (T_d' r)(y),   A[d][d'] = sum_c' v_{8+8d+c'} w1h[c'][d'],
+// an exact rewrite that gathers one colour vector per hop in layer 2.
 __global__ void __launch_bounds__(kNetBlock) k_net_prep(const float2 *theta, NetDev *w) {
+    __shared__ double vr[kNetK], vi[kNetK];
     const int t = threadIdx.x;
+    for (int k = t; k < kNetK; k += kNetBlock) {
+        double sr = 0.0, si = 0.0;
+        for (int c = 0; c < kNetC; ++c) {
+            const float2 wo = theta[kNetWout + c], W = theta[kNetW2 + c * kNetK + k];
+            sr += double(wo.x) * W.x - double(wo.y) * W.y;
+            si += double(wo.x) * W.y + double(wo.y) * W.x;
+        }
+        vr[k] = sr;
+        vi[k] = si;
+    }
+    __syncthreads();
+    if (t < 64) {
+        const int d = t >> 3, dp = t & 7;
+        double sr = 0.0, si = 0.0;
+        for (int cp = 0; cp < kNetC; ++cp) {
+            const float2 h = theta[kNetW1H + 8 * cp + dp];
+            const int k = 8 + 8 * d + cp;
+            sr += vr[k] * h.x - vi[k] * h.y;
+            si += vr[k] * h.y + vi[k] * h.x;
+        }
+        w->fA[d][dp] = make_float2(float(sr), float(si));
+    } else if (t == 64) {
+        double sr = 0.0, si = 0.0;
+        for (int cp = 0; cp < kNetC; ++cp) {
+            const float2 h = theta[kNetW1S + cp];
+            sr += vr[cp] * h.x - vi[cp] * h.y;
+            si += vr[cp] * h.y + vi[cp] * h.x;
+        }
+        w->fsig = make_float2(float(sr), float(si));
+    }
     for (int j = t; j < kNetC; j += kNetBlock) w->w1s[j] = theta[kNetW1S + j];
     for (int j = t; j < kNetC * 8; j += kNetBlock) w->w1h[j / 8][j % 8] = theta[kNetW1H + j];
     for (int j = t; j < kNetC * kNetK; j += kNetBlock) w->W2[j / kNetK][j % kNetK] = theta[kNetW2 + j];
@@ -162,6 +198,77 @@ __global__ void __launch_bounds__(kNetBlock) k_net_l1(NetArgs a) {
         }
     }
     store24(phi1, g.Vh, i, acc);
+}
+
+// ---------------------------------------------------------------- folded form
+// odd sites: psi_d = sum_d' A[d][d'] T_d' r, stored as 24 planes [d][colour][V/2]
+template <int NROW>
+__global__ void __launch_bounds__(kNetBlock) k_net_f1(NetArgs a) {
+    __shared__ float2 sA[64];   // the 8 x 8 mixing, read by every lane at the same address
+    if (a.skip && *a.skip) return;
+    if (threadIdx.x < 64) sA[threadIdx.x] = a.w->fA[threadIdx.x >> 3][threadIdx.x & 7];
+    __syncthreads();
+    const Geom &g = a.g;
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * kNetBlock + threadIdx.x;
+    if (i >= g.Vh) return;
+    const size_t so = blockIdx.y;
+    const float2 *r = a.r + so * a.vstride;
+    float2 *psi = a.phi1 + so * (size_t)g.Vh * 24;
+    int x[4];
+    site_coords(g, 1, i, x);
+    float2 h[8][3];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        su3<float> u;
+        float sg;
+        const int j = hop_setup<NROW>(g, a.links, 1, i, x, d, u, sg);
+        float2 v[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) v[b] = r[(size_t)b * g.Vh + j];
+        transport(u, sg, d < 4, v, h[d]);
+    }
+#pragma unroll
+    for (int d = 0; d < 8; ++d)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int dp = 0; dp < 8; ++dp) acc = caddf(acc, cmulf(sA[8 * d + dp], h[dp][b]));
+            psi[(size_t)(d * 3 + b) * g.Vh + i] = acc;
+        }
+}
+
+// even sites: P r = s r + sum_d T_d psi_d (one colour vector per hop)
+template <int NROW>
+__global__ void __launch_bounds__(kNetBlock) k_net_f2(NetArgs a) {
+    if (a.skip && *a.skip) return;
+    const Geom &g = a.g;
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * kNetBlock + threadIdx.x;
+    if (i >= g.Vh) return;
+    const size_t so = blockIdx.y;
+    const float2 *r = a.r + so * a.vstride;
+    const float2 *psi = a.phi1 + so * (size_t)g.Vh * 24;
+    float2 *out = a.out + so * a.vstride;
+    int x[4];
+    site_coords(g, 0, i, x);
+    const float2 sig = a.w->fsig;
+    float2 acc[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) acc[b] = cmulf(sig, r[(size_t)b * g.Vh + i]);
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        su3<float> u;
+        float sg;
+        const int j = hop_setup<NROW>(g, a.links, 0, i, x, d, u, sg);
+        float2 v[3], h[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) v[b] = psi[(size_t)(d * 3 + b) * g.Vh + j];
+        transport(u, sg, d < 4, v, h);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) acc[b] = caddf(acc[b], h[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) out[(size_t)b * g.Vh + i] = acc[b];
 }
 
 // ---------------------------------------------------------------- forward layer 2 (even sites)
@@ -561,6 +668,16 @@ hipError_t net_launch_prep(const float2 *theta, NetDev *w, hipStream_t s) {
 
 hipError_t net_launch_forward(const NetArgs &a, int n_samples, int mix, hipStream_t s) {
     const dim3 g1((a.g.Vh + kNetBlock - 1) / kNetBlock, n_samples), g2((a.g.Vh + kL2Sites - 1) / kL2Sites, n_samples);
+    if (mix == kMixFolded) {
+        if (a.nrow == 2) {
+            hipLaunchKernelGGL(k_net_f1<2>, g1, dim3(kNetBlock), 0, s, a);
+            hipLaunchKernelGGL(k_net_f2<2>, g1, dim3(kNetBlock), 0, s, a);
+        } else {
+            hipLaunchKernelGGL(k_net_f1<3>, g1, dim3(kNetBlock), 0, s, a);
+            hipLaunchKernelGGL(k_net_f2<3>, g1, dim3(kNetBlock), 0, s, a);
+        }
+        return hipGetLastError();
+    }
     if (a.nrow == 2) {
         hipLaunchKernelGGL(k_net_l1<2>, g1, dim3(kNetBlock), 0, s, a);
         if (mix == kMixBF16) hipLaunchKernelGGL((k_net_l2<2, kMixBF16>), g2, dim3(kNetBlock), 0, s, a);

@@ -29,7 +29,7 @@ int net_part_o();
 int net_loss_blocks(const Geom &g);
 
 stag_status fcg_solve(stag_lattice *lat, double mass, double shift, const void *src, void *sol, stag_net *net,
-                      double tol, int max_iter, stag_cg_stats *stats, hipStream_t s);
+                      int mode, double tol, int max_iter, stag_cg_stats *stats, hipStream_t s);
 
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -154,7 +154,8 @@ stag_status stag_net_get_params(const stag_net *net, double *theta) {
 static stag_status check_net_lat(const stag_net *net, const stag_lattice *lat, int mode) {
     if (!net || !lat) return invalid("null handle");
     if (!lat->nrow) return invalid("links not set");
-    if (mode != kMixBF16 && mode != kMixFP32) return invalid("mode must be 0 (BF16 matrix cores) or 1 (FP32)");
+    if (mode != kMixBF16 && mode != kMixFP32 && mode != kMixFolded)
+        return invalid("mode must be 0 (BF16 matrix cores), 1 (FP32) or 2 (folded)");
     return STAG_OK;
 }
 
@@ -173,6 +174,7 @@ stag_status stag_net_apply(stag_net *net, stag_lattice *lat, const void *r, void
 stag_status stag_net_grad(stag_net *net, stag_lattice *lat, const void *r, const void *g, double *grad, int mode,
                           void *stream) {
     STAG_TRY(check_net_lat(net, lat, mode));
+    if (mode == kMixFolded) return invalid("gradients need the layered form (mode 0 or 1)");
     if (!r || !g || !grad) return invalid("null argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
     NetBufs b;
@@ -194,6 +196,7 @@ stag_status stag_net_grad(stag_net *net, stag_lattice *lat, const void *r, const
 stag_status stag_net_train_step(stag_net *net, stag_lattice *lat, const void *b, const void *x, int n, double lr,
                                 int mode, double *loss, void *stream) {
     STAG_TRY(check_net_lat(net, lat, mode));
+    if (mode == kMixFolded) return invalid("training needs the layered form (mode 0 or 1)");
     if (!b || !x || n < 1 || n > 1024) return invalid("bad batch");
     if (!(lr > 0) || !std::isfinite(lr)) return invalid("lr must be > 0");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -215,11 +218,13 @@ stag_status stag_net_train_step(stag_net *net, stag_lattice *lat, const void *b,
 }
 
 stag_status stag_fcg_solve(stag_lattice *lat, double mass, double shift, const void *src, void *sol, stag_net *net,
-                           double tol, int max_iter, stag_cg_stats *stats, void *stream) {
+                           int mode, double tol, int max_iter, stag_cg_stats *stats, void *stream) {
     if (!lat || !lat->nrow) return invalid("lattice with links required");
     if (!src || !sol || src == sol) return invalid("bad vector");
     if (!(mass > 0) || !(shift >= 0) || !(tol > 0) || max_iter < 1) return invalid("bad solver parameter");
-    return fcg_solve(lat, mass, shift, src, sol, net, tol, max_iter, stats, static_cast<hipStream_t>(stream));
+    if (net && mode != kMixBF16 && mode != kMixFP32 && mode != kMixFolded)
+        return invalid("mode must be 0 (BF16 matrix cores), 1 (FP32) or 2 (folded)");
+    return fcg_solve(lat, mass, shift, src, sol, net, mode, tol, max_iter, stats, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

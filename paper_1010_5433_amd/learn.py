@@ -87,15 +87,17 @@ def train(net: Net, data, steps: int, batch: int, lr: float, mode="bf16", seed: 
     return losses
 
 
-def compare(lat: Lattice, net: Net, mass: float, src: torch.Tensor, shift=0.0, tol=1e-10, max_iter=100000):
-    """Plain double precision CG against flexible CG with the network, both
-    from x = 0 on the same source: iterations, time and true residuals."""
+def compare(lat: Lattice, net: Net, mass: float, src: torch.Tensor, shift=0.0, tol=1e-10, max_iter=100000,
+            modes=("bf16", "folded")):
+    """Plain double precision CG against flexible CG with the network in
+    each of `modes`, all from x = 0 on the same source: iterations, time and
+    true residuals."""
     out = {}
-    for name, n in (("plain", None), ("net", net)):
+    for name, n, mode in [("plain", None, "bf16")] + [(m, net, m) for m in modes]:
         x = torch.zeros_like(src)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, rc, st = lat.fcg_solve(mass, shift, src, x, net=n, tol=tol, max_iter=max_iter)
+        _, rc, st = lat.fcg_solve(mass, shift, src, x, net=n, mode=mode, tol=tol, max_iter=max_iter)
         torch.cuda.synchronize()
         out[name] = dict(status=rc, iters=st["iters"], seconds=time.perf_counter() - t0,
                          resid_true=st["resid_true"][0], fallback=st["fallback_used"])

@@ -10,6 +10,8 @@ Tolerances:
     bfloat16 weights; sums of ~10^2 such terms give ~3e-3 norm-relative,
     bound 1e-2.  In the gradient only the output-weight block uses the
     BF16 layer-2 values; the other blocks stay at the FP32 bound.
+  * Folded mode: an exact rewrite of the same linear map evaluated in FP32
+    (fewer operations than the layered form): bound 1e-5.
   * Flexible CG: the FP64 true residual of the result <= tol (1e-10),
     checked with the oracle's operator.
 """
@@ -70,6 +72,20 @@ def test_net_forward_fp32_vs_oracle(orc, dims, kind, fmt):
     got = unpack(lat, net.apply(lat, pack(lat, r, "f32"), mode="fp32"))
     want = orc.net_forward(dims, U, th, r)
     assert rel(got, want) <= 1e-5
+
+
+@pytest.mark.parametrize("dims,kind,fmt", CASES)
+def test_net_forward_folded_vs_oracle(orc, dims, kind, fmt):
+    """The folded two-hop form of the linear network equals the layered
+    network (oracle) to FP32 rounding."""
+    import paper_1010_5433_amd as stag
+    log(f"net forward folded {dims} {kind} fmt={fmt}")
+    U, lat = _setup(dims, kind, fmt)
+    th = rand_theta(13)
+    r = syn.gaussian_source(dims, 14)
+    net = stag.Net(th)
+    got = unpack(lat, net.apply(lat, pack(lat, r, "f32"), mode="folded"))
+    assert rel(got, orc.net_forward(dims, U, th, r)) <= 1e-5
 
 
 @pytest.mark.parametrize("dims,kind,fmt", CASES)
@@ -152,10 +168,10 @@ def test_net_gauge_equivariant_on_gpu():
     net = stag.Net(rand_theta(10))
     lat, latg = lattice_with_links(dims, U, "18"), lattice_with_links(dims, Ug, "18")
     rg = np.einsum("nij,nj->ni", omega[ev], r)
-    for mode in ("fp32", "bf16"):
+    for mode in ("fp32", "bf16", "folded"):
         lhs = unpack(latg, net.apply(latg, pack(latg, rg, "f32"), mode=mode))
         rhs = np.einsum("nij,nj->ni", omega[ev], unpack(lat, net.apply(lat, pack(lat, r, "f32"), mode=mode)))
-        assert rel(lhs, rhs) <= (1e-5 if mode == "fp32" else 2e-2)
+        assert rel(lhs, rhs) <= (2e-2 if mode == "bf16" else 1e-5)
 
 
 def test_net_params_roundtrip_and_validation():
@@ -171,6 +187,8 @@ def test_net_params_roundtrip_and_validation():
         net.apply(lat, r32, out=r32)           # in place is rejected
     with pytest.raises(stag.StagError):
         net.apply(lat, r32, mode=7)
+    with pytest.raises(stag.StagError):
+        net.grad(lat, r32, r32, mode="folded")     # gradients need the layered form
 
 
 def test_train_step_reduces_loss():
@@ -225,13 +243,16 @@ def test_fcg_polynomial_preconditioner_gains(orc):
     net = stag.Net(poly_theta(a + bb - m * m, 1.0, scale=1.0 / bb))
     b = syn.gaussian_source(dims, 32)
     src = pack(lat, b)
-    x0, x1 = torch.zeros_like(src), torch.zeros_like(src)
+    x0 = torch.zeros_like(src)
     _, rc0, st0 = lat.fcg_solve(m, 0.0, src, x0, net=None, tol=1e-10)
-    _, rc1, st1 = lat.fcg_solve(m, 0.0, src, x1, net=net, tol=1e-10)
-    log(f"plain {st0['iters']} iterations, polynomial-preconditioned {st1['iters']} (lambda_max {lmax:.3f})")
-    assert rc1 == 0 and st1["fallback_used"] == 0
-    assert orc.true_residual(dims, U, m, 0.0, b, unpack(lat, x1)) <= 1e-10
-    assert st1["iters"] <= 0.7 * st0["iters"]
+    for mode in ("bf16", "fp32", "folded"):
+        x1 = torch.zeros_like(src)
+        _, rc1, st1 = lat.fcg_solve(m, 0.0, src, x1, net=net, mode=mode, tol=1e-10)
+        log(f"plain {st0['iters']} iterations, polynomial-preconditioned ({mode}) {st1['iters']} "
+            f"(lambda_max {lmax:.3f})")
+        assert rc1 == 0 and st1["fallback_used"] == 0
+        assert orc.true_residual(dims, U, m, 0.0, b, unpack(lat, x1)) <= 1e-10
+        assert st1["iters"] <= 0.7 * st0["iters"]
 
 
 def test_fcg_fallback_on_indefinite_preconditioner(orc):
@@ -270,7 +291,8 @@ def test_trained_network_gains_over_plain_cg(orc):
     b = syn.gaussian_source(dims, 650)
     res = learn.compare(latt, net, m, pack(latt, b))
     log(f"held-out: {res}")
-    assert res["net"]["status"] == 0 and res["net"]["fallback"] == 0
-    assert res["net"]["resid_true"] <= 1e-10
-    assert res["net"]["iters"] <= 0.8 * res["plain"]["iters"]
+    for mode in ("bf16", "folded"):
+        assert res[mode]["status"] == 0 and res[mode]["fallback"] == 0
+        assert res[mode]["resid_true"] <= 1e-10
+        assert res[mode]["iters"] <= 0.8 * res["plain"]["iters"]
     assert losses[-1] < losses[0]
