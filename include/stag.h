@@ -151,9 +151,11 @@ stag_status stag_normal_op(stag_lattice *lat, double mass, double shift, const v
  *                       reductions and recursion (reaches only the single
  *                       precision floor, Section 6).
  *   prec = STAG_MIXED : single precision iterations, double precision
- *                       reliable updates of the base residual every 100
- *                       iterations, then a mixed CG refinement of every shift
- *                       whose true residual exceeds tol.
+ *                       reliable updates of the base residual (b - A x
+ *                       recomputed whenever |r| fell tenfold since the last
+ *                       one; checked every 8 iterations), then a mixed CG
+ *                       refinement of every shift whose true residual
+ *                       exceeds tol.
  * Requires mass > 0, shifts >= 0, tol > 0, 1 <= n_shifts <= 64, links set.
  * ||src|| = 0 gives zero solutions and 0 iterations.  Returns STAG_ENOCONV
  * after max_iter iterations (stats filled), STAG_EBREAKDOWN on a

@@ -75,8 +75,9 @@ struct BDslashCfg {
     int rpt;     // right-hand sides per thread: 1, 2, 4 or 8
 };
 
-// sel < 0 selects each system's base shift.  skip_done: systems whose solve
-// ended are skipped.  write: BR_EO_RESID also stores rhi.
+// sel < 0 selects each system's base shift.  skip_done 1: systems whose solve
+// ended are skipped; 2: systems with no reliable update due are skipped.
+// write: BR_EO_RESID also stores rhi.
 hipError_t launch_bdslash(bool dbl, int nrow, BDslashCfg cfg, BView v, int role, int sel, int skip_done, int write,
                           hipStream_t s);
 
@@ -87,9 +88,9 @@ enum BVecOp {
     BV_NORM_SRC = 2,   // partial |b|^2
     BV_R_UPDATE = 3,   // r -= alpha ap, partial |r|^2
     BV_SHIFT_UPDATE = 4,
-    BV_FLUSH = 5,      // xhi += x, x = 0 (single precision), skipped once done
+    BV_FLUSH = 5,      // xhi += x, x = 0 (single precision), when a reliable update is due
     BV_FLUSH_FINAL = 6,// same, always
-    BV_DEMOTE = 7      // r = (float) rhi, skipped once done
+    BV_DEMOTE = 7      // r = (float) rhi, when a reliable update is due
 };
 hipError_t launch_bvec(bool dbl, BView v, int op, int max_blocks, hipStream_t s);
 

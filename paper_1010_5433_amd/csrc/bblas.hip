@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(kBBlock) kb_vec(BView v, int op) {
             }
         }
     } else if (op == BV_FLUSH || op == BV_FLUSH_FINAL) {
-        if (op == BV_FLUSH && st->done) return;
+        if (op == BV_FLUSH && st->rel_skip) return;
         for (int e = 0; e < 4; ++e) {
             const int64_t j = j0 + e * kWave;
             if (j >= n) break;
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(kBBlock) kb_vec(BView v, int op) {
             }
         }
     } else if (op == BV_DEMOTE) {
-        if (st->done) return;
+        if (st->rel_skip) return;
         T2<R> *r = static_cast<T2<R> *>(s.r);
         for (int e = 0; e < 4; ++e) {
             const int64_t j = j0 + e * kWave;
@@ -162,7 +162,8 @@ __global__ void __launch_bounds__(kBTailBlock) kb_tail(BView v, int kind, int se
         if (threadIdx.x == 0) st->upd_valid = 0;  // retire the previous update
         if (st->done) return;
     }
-    if ((kind == BT_BETA || kind == BT_RELIABLE) && st->done) return;
+    if (kind == BT_BETA && st->done) return;
+    if (kind == BT_RELIABLE && st->rel_skip) return;
     const bool use_ds = kind == BT_ALPHA || kind == BT_RELIABLE || kind == BT_TRUE_RESID || (kind == BT_INIT && s.x_init);
     const double *part = use_ds ? s.part_ds : s.part_bl;
     const int np = use_ds ? s.nchunk_ds : s.nchunk_bl;
@@ -184,6 +185,7 @@ __global__ void __launch_bounds__(kBTailBlock) kb_tail(BView v, int kind, int se
     } else if (kind == BT_RELIABLE) {
         if (threadIdx.x == 0) {
             st->rho = total;
+            st->rho_rel = total;
             st->n_reliable += 1;
         }
     } else if (kind == BT_TRUE_RESID) {

@@ -7,9 +7,9 @@
 //    every candidate on the actual batch the first time a batch layout is
 //    seen; the choice is cached per layout in the process and, when the
 //    environment variable STAG_AUTOTUNE_CACHE names a file, on disk.
-//  * Ten iterations (with a double precision reliable update at every 100th
-//    iteration in mixed precision) are captured once in a hipGraph and
-//    replayed; after each replay a 4-byte "all systems done" flag is copied
+//  * Ten iterations (in mixed precision followed by a double precision
+//    reliable update for every system whose residual fell tenfold since its
+//    last one) are captured once in a hipGraph and replayed; after each replay a 4-byte "all systems done" flag is copied
 //    to pinned host memory and read one replay behind, so the queue never
 //    drains.  Kernels of systems that already finished return at once.
 #include <hip/hip_runtime.h>
@@ -204,6 +204,7 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
         st.base = s.base;
         st.tol = opt.tol;
         st.max_iter = opt.max_iter;
+        st.rel_delta2 = (!dbl && opt.reliable_every > 0) ? 0.01 : 0.0;
         for (int i = 0; i < sp.n; ++i) st.shift_rel[i] = sp.shifts[i] - sp.shifts[s.base];
         max_n = std::max(max_n, sp.n);
         max_blocks = std::max(max_blocks, (s.nchunk_bl + kBBlock / kWave - 1) / (kBBlock / kWave));
@@ -315,8 +316,8 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
         }
         if (reliable && e == hipSuccess) {
             e = launch_bvec(dbl, v, BV_FLUSH, max_blocks, cs);
-            if (e == hipSuccess) e = launch_bdslash(dbl, nrow, cfg, v, BR_OE_X, -1, 1, 0, cs);
-            if (e == hipSuccess) e = launch_bdslash(dbl, nrow, cfg, v, BR_EO_RESID, -1, 1, 1, cs);
+            if (e == hipSuccess) e = launch_bdslash(dbl, nrow, cfg, v, BR_OE_X, -1, 2, 0, cs);
+            if (e == hipSuccess) e = launch_bdslash(dbl, nrow, cfg, v, BR_EO_RESID, -1, 2, 1, cs);
             if (e == hipSuccess) e = launch_btail(v, BT_RELIABLE, 0, cs);
             if (e == hipSuccess) e = launch_bvec(dbl, v, BV_DEMOTE, max_blocks, cs);
         }
@@ -354,7 +355,7 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
     }
     for (int chunk = 0; rc == STAG_OK; ++chunk) {
         const int it_end = (chunk + 1) * K;
-        const bool rel = use_rel && it_end % opt.reliable_every == 0;
+        const bool rel = use_rel;   // every replay checks whether a reliable update is due
         hipError_t e = opt.use_graph ? hipGraphLaunch(ge[rel ? 1 : 0], cs) : enqueue(rel);
         const int slot = chunk & 1;
         if (e == hipSuccess) e = hipMemcpyAsync(const_cast<int *>(flags + slot), d_flag, sizeof(int), hipMemcpyDeviceToHost, cs);

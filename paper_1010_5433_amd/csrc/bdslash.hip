@@ -31,7 +31,8 @@ __global__ void __launch_bounds__(256) kb_dslash(BView v, int sel, int skip_done
         if (r < tile.nsys) {
             const BSys *s = v.sys + tile.sys[r];
             const int k = sel < 0 ? s->base : sel;
-            bool l = !(skip_done && s->st->done);
+            // skip_done 1: systems whose solve ended; 2: systems with no reliable update due
+            bool l = !(skip_done == 1 ? s->st->done : skip_done == 2 ? s->st->rel_skip : 0);
             if (ROLE == BR_OE_X || ROLE == BR_EO_RESID) l = l && k < s->n;
             if (l) {
                 live[r] = true;

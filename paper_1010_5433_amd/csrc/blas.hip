@@ -133,8 +133,8 @@ __global__ void __launch_bounds__(kBlasBlock) k_shift_update(const MsState *st, 
 }
 
 __global__ void __launch_bounds__(kBlasBlock) k_x_flush(const MsState *st, ShiftPtrs hi, ShiftPtrs lo, int n_shift,
-                                                     int64_t n, int skip_on_done) {
-    if (skip_on_done && st->done) return;
+                                                     int64_t n, int gated) {
+    if (gated && st->rel_skip) return;
     for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
         for (int i = 0; i < n_shift; ++i) {
             double2 *h = static_cast<double2 *>(hi.x[i]);
@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(kBlasBlock) k_x_flush(const MsState *st, Shift
 }
 
 __global__ void __launch_bounds__(kBlasBlock) k_demote(const MsState *st, const double2 *src, float2 *dst, int64_t n) {
-    if (st->done) return;
+    if (st->rel_skip) return;
     for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
         const double2 v = src[j];
         dst[j] = make_float2(float(v.x), float(v.y));
@@ -190,7 +190,8 @@ __global__ void __launch_bounds__(kTailBlock) k_reduce_tail(MsState *st, const d
         if (threadIdx.x == 0) st->upd_valid = 0;
         return;
     }
-    if ((kind == TAIL_BETA || kind == TAIL_RELIABLE) && st->done) return;
+    if (kind == TAIL_BETA && st->done) return;
+    if (kind == TAIL_RELIABLE && st->rel_skip) return;
     double t = 0.0;
     for (int k = threadIdx.x; k < nparts; k += kTailBlock) t += partial[k];
     const double total = block_sum(t, red);
@@ -202,6 +203,7 @@ __global__ void __launch_bounds__(kTailBlock) k_reduce_tail(MsState *st, const d
     } else if (kind == TAIL_RELIABLE) {
         if (threadIdx.x == 0) {
             st->rho = total;
+            st->rho_rel = total;
             st->n_reliable += 1;
         }
     } else if (kind == TAIL_TRUE_RESID) {
@@ -250,9 +252,9 @@ hipError_t launch_shift_update(bool dbl, MsState *st, const void *r, ShiftPtrs p
     return hipGetLastError();
 }
 
-hipError_t launch_x_flush(MsState *st, ShiftPtrs hi, ShiftPtrs lo, int n_shift, int64_t n, bool skip_on_done,
+hipError_t launch_x_flush(MsState *st, ShiftPtrs hi, ShiftPtrs lo, int n_shift, int64_t n, bool gated,
                           hipStream_t s) {
-    hipLaunchKernelGGL(k_x_flush, dim3(blas_grid(n)), dim3(kBlasBlock), 0, s, st, hi, lo, n_shift, n, skip_on_done ? 1 : 0);
+    hipLaunchKernelGGL(k_x_flush, dim3(blas_grid(n)), dim3(kBlasBlock), 0, s, st, hi, lo, n_shift, n, gated ? 1 : 0);
     return hipGetLastError();
 }
 

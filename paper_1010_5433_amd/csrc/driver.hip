@@ -13,10 +13,11 @@
 // single precision with double reductions and recursion, accumulating
 // solutions in single precision and flushing them into the double
 // solutions.  STAG_MIXED adds reliable updates: every `reliable_every`
-// iterations the base residual is recomputed as b - A x in double
+// iterations the device checks whether |r| fell tenfold since the last
+// update; if so the base residual is recomputed as b - A x in double
 // precision (the residual-replacement idea the paper discusses, applied to
-// the base system of the shifted family) and the single precision residual
-// is replaced by it.
+// the base system of the shifted family) and replaces the single precision
+// residual.
 #include <chrono>
 #include <cstring>
 #include <vector>
@@ -49,6 +50,8 @@ struct ShiftedResult {
 };
 
 static constexpr int kChunk = 8;   // iterations enqueued between flag reads
+static constexpr double kReliableDelta = 0.1;   // reliable update after |r| fell 10x
+static constexpr int kReliableCheck = 8;        // iterations between reliable-update checks
 
 stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult *res, hipStream_t s) {
     const int n = sp.n;
@@ -98,6 +101,7 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
     hs.base = base;
     hs.tol = sp.tol;
     hs.max_iter = sp.max_iter;
+    hs.rel_delta2 = sp.reliable_every > 0 ? kReliableDelta * kReliableDelta : 0.0;
     for (int i = 0; i < n; ++i) hs.shift_rel[i] = sp.shifts[i] - sigma0;
     STAG_HIP(hipMemcpyAsync(st, &hs, sizeof(hs), hipMemcpyHostToDevice, s));
 
@@ -164,7 +168,7 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
         STAG_HIP(launch_shift_update(dbl, st, R, it_ptrs, n, ne, bl_grid, s));
         if (sp.reliable_every > 0 && (k + 1) % sp.reliable_every == 0) {
             STAG_HIP(launch_x_flush(st, hi_ptrs, lo_ptrs, n, ne, true, s));
-            STAG_HIP(true_residual(sp.x_hi[base], sigma0, RHI, part0, &st->done));
+            STAG_HIP(true_residual(sp.x_hi[base], sigma0, RHI, part0, &st->rel_skip));
             STAG_HIP(launch_reduce_tail(st, part0, ds_grid, TAIL_RELIABLE, 0, s));
             STAG_HIP(launch_demote(st, static_cast<const double2 *>(RHI), static_cast<float2 *>(R), ne, s));
         }
@@ -249,7 +253,7 @@ static stag_status cg_refine(stag_lattice *lat, double mass, double shift, const
     sp.x_init = true;
     sp.tol = tol;
     sp.dbl_iter = !mixed;
-    sp.reliable_every = mixed ? 100 : 0;
+    sp.reliable_every = mixed ? kReliableCheck : 0;
     *iters = 0;
     *n_rel = 0;
     ShiftedResult r;
@@ -286,7 +290,7 @@ stag_status multishift_cg(stag_lattice *lat, double mass, const double *shifts, 
     sp.tol = tol;
     sp.max_iter = max_iter;
     sp.dbl_iter = prec == STAG_F64;
-    sp.reliable_every = prec == STAG_MIXED ? 100 : 0;
+    sp.reliable_every = prec == STAG_MIXED ? kReliableCheck : 0;
     ShiftedResult r;
     STAG_TRY(run_shifted(lat, sp, &r, s));
     stag_status rc = status_of(r.status);

@@ -39,6 +39,8 @@ __device__ __forceinline__ void ms_init_step(MsState *st, double rho, double b2)
         st->upd_valid = 0;
         st->upd_p = 0;
         st->n_reliable = 0;
+        st->rho_rel = rho;
+        st->rel_skip = 1;
         st->done = conv ? 1 : 0;
         st->status = conv ? MS_CONVERGED : MS_RUNNING;
     }
@@ -115,6 +117,15 @@ __device__ __forceinline__ void ms_beta_step(MsState *st, double rho_new) {
             st->done = 1;
             st->status = MS_NOCONV;
         }
+        // A reliable update replaces the iterated residual by b - A x.  It is
+        // due once |r| fell by the factor sqrt(rel_delta2) since the last
+        // one: then the single precision drift of the iterated residual is
+        // still small against |r| itself, and the replaced residual stays
+        // consistent with the search direction.  (A fixed schedule lets |r|
+        // drop below the single precision floor between updates; the
+        // replaced residual then no longer fits the direction and the
+        // recursion diverges.)
+        st->rel_skip = (st->rel_delta2 > 0.0 && !st->done && rho_new < st->rel_delta2 * st->rho_rel) ? 0 : 1;
     }
 }
 

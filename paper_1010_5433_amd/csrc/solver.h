@@ -19,6 +19,8 @@ struct MsState {
     double alpha, alpha_prev, beta, beta_prev;
     double bnorm2;       // ||b||^2 of the reference right-hand side
     double tol;          // relative tolerance
+    double rho_rel;      // |r|^2 right after the last reliable update (or the start)
+    double rel_delta2;   // reliable update once |r|^2 < rel_delta2 * rho_rel (0: never)
     double scratch[4];   // reduced values handed to the host
     int n, base;
     int iter, max_iter;
@@ -27,7 +29,8 @@ struct MsState {
     int upd_valid;       // the shift-update kernel applies this iteration
     int upd_p;           // the base direction is updated this iteration
     int n_reliable;
-    int pad[3];
+    int rel_skip;        // 1: the reliable-update kernels of this iteration are no-ops
+    int pad[2];
     double shift_rel[kMaxShifts];   // s_i = sigma_i - sigma_base
     double zeta[kMaxShifts], zeta_prev[kMaxShifts], zeta_next[kMaxShifts];
     double a[kMaxShifts], b[kMaxShifts];

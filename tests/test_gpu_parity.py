@@ -247,6 +247,26 @@ def test_multishift_f32_floor_and_mixed_refinement(orc):
         assert orc.true_residual(dims, U, 0.02, s, b, xs[i]) <= 1e-10
 
 
+@pytest.mark.parametrize("dims,mass,seed", [((6, 4, 2, 4), 0.1, 4), ((8, 8, 8, 8), 0.2, 5)])
+def test_mixed_reliable_updates_below_single_floor(orc, dims, mass, seed):
+    """A well-conditioned system whose residual falls far below the single
+    precision floor within a few dozen iterations: the reliable updates keep
+    the base shift consistent (no divergence, base at 1e-10 without
+    refinement) and refinement brings the other shifts to tol."""
+    log(f"mixed reliable updates {dims} m={mass}")
+    U = links_np(dims, "smooth", 0.5, seed)
+    b = syn.gaussian_source(dims, 20)
+    shifts = list(syn.logspace_shifts(1e-3, 1.0, 4))
+    lat = lattice_with_links(dims, U)
+    xs, rc, st = _solve(lat, mass, shifts, b, prec="mixed")
+    log(f"  iters {st['iters']} reliable {st['n_reliable']} refine {st['refine_iters']}")
+    assert rc == 0
+    assert st["n_reliable"] >= 3
+    assert st["resid_unrefined"][0] <= 3e-10          # the base shift (smallest), before refinement
+    for i, s in enumerate(shifts):
+        assert orc.true_residual(dims, U, mass, s, b, xs[i]) <= 1e-10
+
+
 def test_single_cg_from_guess(orc):
     import torch
     log("single cg")
