@@ -184,20 +184,23 @@ typedef struct {
 } stag_system;
 
 /* flags of stag_multishift_cg_batched */
-#define STAG_BATCH_NO_GRAPH 0x1                 /* launch kernels directly instead of replaying a hipGraph */
+#define STAG_BATCH_NO_GRAPH 0x1                 /* accepted for compatibility: iterations are always launched directly */
 #define STAG_BATCH_RPT(r) (((r) & 0xF) << 4)   /* force r right-hand sides per thread (1, 2, 4, 8) ... */
 #define STAG_BATCH_BLOCK(b) ((((b) / 64) & 0xF) << 8) /* ... and b sites per block (64, 128, 256) */
 
 /* Batched multi-shift CG: n_systems (1..64) independent shifted families --
  * several pseudo-fermions on one gauge field and/or lattices of different
- * sizes -- advanced together, one launch per phase for the whole batch
- * (Section 2 lists multiple pseudo-fermions among the algorithm's tricks).
- * Systems whose `lat` is the same handle share link loads in a multi-RHS
- * Dslash.  The launch shape is autotuned once per batch layout (cached in
- * the process, and in the file named by STAG_AUTOTUNE_CACHE if set) unless
- * forced through flags.  Ten iterations are captured in a hipGraph and
- * replayed.  Every shift of every system freezes on its own; each system
- * has its own recursion, mass and shifts; tol and max_iter are shared.
+ * sizes -- advanced together (Section 2 lists multiple pseudo-fermions among
+ * the algorithm's tricks).  Systems whose `lat` is the same handle share
+ * link loads in a multi-RHS Dslash (up to 8 right-hand sides per launch,
+ * one launch per lattice and phase); the vector updates and the scalar
+ * recursions of all systems, whatever their lattice, run in one launch per
+ * phase.  The launch shape of the multi-RHS Dslash (sites per block,
+ * right-hand sides per launch) is timed on the first batch of each layout
+ * and cached in the process, unless forced through flags.  Everything runs
+ * on `stream`; a done flag is read every 8 iterations, one chunk behind.
+ * Every shift of every system freezes on its own; each system has its own
+ * recursion, mass and shifts; tol and max_iter are shared.
  * prec as for stag_multishift_cg (STAG_MIXED refines every shift that
  * misses tol in a second batched pass, warm-started).  All lattices must
  * use the same link format and device.  stats, if non-NULL, receives

@@ -247,14 +247,6 @@ stag_status stag_cg(stag_lattice *lat, double mass, double shift, const void *sr
 
 stag_status stag_multishift_cg_batched(const stag_system *systems, int n_systems, double tol, int max_iter,
                                        stag_prec prec, int flags, stag_cg_stats *stats, void *stream) {
-    // Switched off: the first GPU run of this path (warm-started batched
-    // refinement at 32^4) ended in a GPU memory fault whose cause is not yet
-    // found (host logic and kernel indexing check clean under a CPU
-    // emulation).  The entry point refuses to run until that is resolved.
-    if (!std::getenv("STAG_BATCHED_DEVELOPMENT")) {
-        set_error("stag_multishift_cg_batched is disabled: an unexplained GPU memory fault in its first run is under investigation");
-        return STAG_EINVAL;
-    }
     try {
         if (!systems) return invalid("null systems");
         if (n_systems < 1 || n_systems > 64) return invalid("n_systems must be in [1, 64]");
@@ -282,7 +274,7 @@ stag_status stag_multishift_cg_batched(const stag_system *systems, int n_systems
         opt.tol = tol;
         opt.max_iter = max_iter;
         opt.dbl = prec == STAG_F64;
-        opt.reliable_every = prec == STAG_MIXED ? 100 : 0;
+        opt.reliable_every = prec == STAG_MIXED ? 8 : 0;
         opt.use_graph = !(flags & STAG_BATCH_NO_GRAPH);
         opt.force_rpt = (flags >> 4) & 0xF;
         opt.force_block = ((flags >> 8) & 0xF) * 64;
@@ -305,7 +297,7 @@ stag_status stag_multishift_cg_batched(const stag_system *systems, int n_systems
 
 stag_status stag_batch_last_config(int *block, int *rpt) {
     if (!block || !rpt) return invalid("null argument");
-    const BDslashCfg c = last_batch_cfg();
+    const BDslashCfg c = last_batch_cfg2();
     *block = c.block;
     *rpt = c.rpt;
     return STAG_OK;

@@ -134,6 +134,10 @@ struct BOptions {
 };
 
 stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *out, hipStream_t user_stream);
+// the direct-launch form (per-lattice multi-RHS Dslash with arguments by value,
+// no tile table, no graph, the caller's stream)
+stag_status run_batched2(const BSpec *spec, int nsys, const BOptions &opt, BOut *out, hipStream_t s);
+BDslashCfg last_batch_cfg2();
 // refine every (system, shift) whose true residual in stats exceeds opt.tol
 stag_status refine_batched(const BSpec *spec, int nsys, const BOptions &opt, stag_cg_stats *stats, hipStream_t s);
 stag_status batched_solve(const BSpec *spec, int nsys, const BOptions &opt, bool mixed, stag_cg_stats *stats,

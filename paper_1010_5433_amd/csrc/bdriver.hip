@@ -371,6 +371,11 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
         }
         if (it_end > opt.max_iter + K) break;
     }
+    // the last replay may still run: let it finish before its executable goes
+    if (rc == STAG_OK && hipStreamSynchronize(cs) != hipSuccess) {
+        set_error("batched iteration failed at the last replay");
+        rc = STAG_EHIP;
+    }
     if (rc == STAG_OK) {
         hipEventDestroy(ev[0]);
         hipEventDestroy(ev[1]);
@@ -442,9 +447,9 @@ stag_status refine_batched(const BSpec *spec, int nsys, const BOptions &opt, sta
             }
             BOptions ro_opt = opt;
             ro_opt.dbl = false;
-            ro_opt.reliable_every = 100;
+            ro_opt.reliable_every = 8;
             ro_opt.force_block = ro_opt.force_rpt = 0;
-            STAG_TRY(run_batched(rs.data(), m, ro_opt, ro.data(), s));
+            STAG_TRY(run_batched2(rs.data(), m, ro_opt, ro.data(), s));
             for (int j = 0; j < m; ++j) {
                 const Item &it = todo[c0 + j];
                 stag_cg_stats &st = stats[it.k];
@@ -468,7 +473,7 @@ stag_status batched_solve(const BSpec *spec, int nsys, const BOptions &opt0, boo
     const auto t0 = std::chrono::steady_clock::now();
     BOptions opt = opt0;
     std::vector<BOut> out(nsys);
-    STAG_TRY(run_batched(spec, nsys, opt, out.data(), s));
+    STAG_TRY(run_batched2(spec, nsys, opt, out.data(), s));
     stag_status rc = STAG_OK;
     for (int k = 0; k < nsys; ++k) {
         stag_cg_stats &st = stats[k];

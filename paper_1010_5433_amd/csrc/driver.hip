@@ -22,6 +22,7 @@
 #include <cstring>
 #include <vector>
 
+#include "batch.h"
 #include "ms_device.h"
 #include "solver.h"
 
@@ -305,21 +306,19 @@ stag_status multishift_cg(stag_lattice *lat, double mass, const double *shifts, 
         st.resid_unrefined[i] = r.resid_true[i];
     }
     if (prec == STAG_MIXED && rc != STAG_EBREAKDOWN) {
-        // refine every shift that misses tol: warm-started single-shift mixed CG
-        stag_status worst = STAG_OK;
-        for (int i = 0; i < n; ++i) {
-            if (st.resid_true[i] <= tol) continue;
-            int it = 0, nrel = 0;
-            double resid = st.resid_true[i];
-            stag_status ri = cg_refine(lat, mass, shifts[i], src, sols[i], tol, max_iter, true, &it, &nrel, &resid, s);
-            if (ri < 0) return ri;
-            st.refine_iters += it;
-            st.refine_iters_shift[i] = it;
-            st.n_reliable += nrel;
-            st.resid_true[i] = resid;
-            if (ri != STAG_OK && worst != STAG_EBREAKDOWN) worst = ri;
-        }
-        rc = worst;
+        // refine every shift that misses tol: warm-started single-shift mixed
+        // CG, all of them together (one multi-RHS Dslash per phase loads every
+        // link once for up to 8 shifts)
+        BSpec fam = {lat, mass, n, shifts, src, sols, false};
+        BOptions ro;
+        std::memset(&ro, 0, sizeof(ro));
+        ro.tol = tol;
+        ro.max_iter = max_iter;
+        ro.dbl = false;
+        ro.reliable_every = kReliableCheck;
+        const stag_status rr = refine_batched(&fam, 1, ro, &st, s);
+        if (rr < 0) return rr;
+        rc = rr;
     }
     st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = st;
