@@ -113,6 +113,55 @@ def cpu_baseline(dims, U, b, mass, shifts, gpu_iters, sample_iters):
                        f"{gpu_iters} iterations; {per_iter * 1e3:.1f} ms per iteration")
 
 
+def batched_experiment(args):
+    """The batched workload (8 pseudo-fermions x 16 shifts on 24^3x6 plus
+    single sources on 8^4, 12^4 and 16^3x8) in one batched call against the
+    same systems solved one after another, in double and in mixed precision."""
+    import torch
+
+    import paper_1010_5433_amd as stag
+    import stag_synth as syn
+
+    c = syn.config("c4_batched")
+    tol = c["tol"]
+    systems = []
+    for y in c["systems"]:
+        U = syn.smooth_links(y["dims"], 0.5, y["links"][2])
+        lat = stag.Lattice(y["dims"])
+        lat.set_links(torch.from_numpy(U).cuda(), args.fmt)
+        shifts = [float(v) for v in syn.logspace_shifts(*y["shifts"])]
+        for ss in y["source_seeds"]:
+            b = syn.gaussian_source(y["dims"], ss)
+            systems.append(dict(lat=lat, mass=y["mass"], shifts=shifts, src=lat.pack(torch.from_numpy(b).cuda())))
+    out = dict(systems=len(systems), shifts=sum(len(s["shifts"]) for s in systems),
+               lattices=[list(y["dims"]) for y in c["systems"]])
+    for prec in ("f64", "mixed"):
+        stag.multishift_cg_batched(systems, tol=tol, prec=prec)      # warm-up: launch-shape timing
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sols, rc, st = stag.multishift_cg_batched(systems, tol=tol, prec=prec)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter() - t0
+        if rc != 0 or max(max(s["resid_true"]) for s in st) > tol:
+            raise RuntimeError(f"batched solve failed: rc={rc}")
+        block, rpt = stag.batch_last_config()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for y in systems:
+            _, rc1, st1 = y["lat"].multishift_cg(y["mass"], y["shifts"], y["src"], tol=tol, prec=prec)
+            if rc1 != 0 or max(st1["resid_true"]) > tol:
+                raise RuntimeError(f"unbatched solve failed: rc={rc1}")
+        torch.cuda.synchronize()
+        t_u = time.perf_counter() - t0
+        log(f"batched {prec}: {t_b:.4f} s in one call vs {t_u:.4f} s one system after another "
+            f"(first lattice's launch shape: block {block}, {rpt} right-hand sides per launch)")
+        out[prec] = dict(batched_s=round(t_b, 4), sequential_s=round(t_u, 4), speedup=round(t_u / t_b, 3),
+                         iters=[s["iters"] for s in st], refine_iters=[s["refine_iters"] for s in st],
+                         max_resid_true=max(max(s["resid_true"]) for s in st),
+                         launch_shape_first_lattice=dict(block=block, rhs_per_launch=rpt))
+    return out
+
+
 def learned_experiment(args, n_test_fields):
     """Train the gauge-equivariant preconditioner on 16^4 fields and judge it
     in flexible CG on held-out 32^4 fields against plain FP64 CG."""
@@ -198,6 +247,8 @@ def main():
     ap.add_argument("--only-dslash", type=int, default=0,
                     help="profiling aid: run N half-Dslash launches of the bench's precision and exit")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner experiment")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-solver experiment")
+    ap.add_argument("--batched-only", action="store_true", help="run only the batched-solver experiment")
     ap.add_argument("--learned-only", action="store_true",
                     help="run only the learned-preconditioner experiment (all held-out fields)")
     ap.add_argument("--train-steps", type=int, default=1500)
@@ -221,6 +272,10 @@ def main():
     import paper_1010_5433_amd as stag
     import stag_synth as syn
 
+    if args.batched_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"batched": batched_experiment(args)}), flush=True)
+        return
     if args.learned_only:
         torch.cuda.set_device(0)
         print(json.dumps({"learned": learned_experiment(args, args.test_fields)}), flush=True)
@@ -332,6 +387,8 @@ def main():
         dsl[f"{p}_{args.fmt}"] = dict(us=round(s * 1e6, 2), GBs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
     log(f"dslash: {dsl}")
 
+    if not args.no_batched:
+        extra["batched"] = batched_experiment(args)
     if not args.no_learned:
         extra["learned"] = learned_experiment(args, 1)
 

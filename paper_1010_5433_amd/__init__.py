@@ -239,7 +239,8 @@ def multishift_cg_batched(systems, tol=1e-10, max_iter=100000, prec="f64", no_gr
     """Batched multi-shift CG.  systems: list of dicts with keys lat (Lattice),
     mass, shifts, src (library vector) and optionally sols.  Systems on the
     same Lattice share link loads.  Returns (list of sols, status, list of
-    stats dicts).  rpt/block force a launch shape (0: autotune)."""
+    stats dicts).  rpt/block force a launch shape (0: autotune); no_graph is
+    accepted and changes nothing (iterations are launched directly)."""
     n = len(systems)
     keep = []
     arr = (System * n)()

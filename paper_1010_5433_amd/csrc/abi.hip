@@ -104,7 +104,6 @@ stag_status stag_lattice_destroy(stag_lattice *lat) {
     hipFree(lat->links32);
     for (int k = 0; k < WS_NSLOTS; ++k) hipFree(lat->ws[k]);
     hipHostFree(lat->host_flags);
-    if (lat->capture_stream) hipStreamDestroy(lat->capture_stream);
     delete lat;
     return STAG_OK;
 }
@@ -275,7 +274,6 @@ stag_status stag_multishift_cg_batched(const stag_system *systems, int n_systems
         opt.max_iter = max_iter;
         opt.dbl = prec == STAG_F64;
         opt.reliable_every = prec == STAG_MIXED ? 8 : 0;
-        opt.use_graph = !(flags & STAG_BATCH_NO_GRAPH);
         opt.force_rpt = (flags >> 4) & 0xF;
         opt.force_block = ((flags >> 8) & 0xF) * 64;
         if (opt.force_rpt || opt.force_block) {
@@ -297,7 +295,7 @@ stag_status stag_multishift_cg_batched(const stag_system *systems, int n_systems
 
 stag_status stag_batch_last_config(int *block, int *rpt) {
     if (!block || !rpt) return invalid("null argument");
-    const BDslashCfg c = last_batch_cfg2();
+    const BDslashCfg c = last_batch_cfg();
     *block = c.block;
     *rpt = c.rpt;
     return STAG_OK;

@@ -1,7 +1,8 @@
 // Batched shifted CG: many systems (pseudo-fermions x shifts, and lattices
-// of different sizes) advanced together, one launch per phase for the whole
-// batch.  Systems that share a gauge field are processed by a multi-RHS
-// Dslash that loads every link once for up to 8 right-hand sides.
+// of different sizes) advanced together.  Systems that share a gauge field
+// are processed by a multi-RHS Dslash that loads every link once for up to
+// 8 right-hand sides (one launch per lattice and phase); the vector updates
+// and recursions of all systems run in one launch per phase.
 //
 // Reductions are grouped per 64 consecutive sites (Dslash) or per 256
 // consecutive vector entries (vector kernels) -- one wave each -- and the
@@ -46,26 +47,10 @@ struct BSys {
     double2 *xhi[kMaxShifts];
 };
 
-struct BTile {
-    int lat;
-    int site0;             // first site of the tile (multiple of 64)
-    int nsys;              // systems handled by the tile (<= RPT of the launch)
-    int sys[kMaxRpt];
-};
-
-// What a batched Dslash launch computes for each live system of a tile.
-enum BRole {
-    BR_OE_P = 0,      // t = D_oe p_base
-    BR_EO_AP = 1,     // ap = (m^2 + sigma_base) p_base - D_eo t, partial <p_base, ap>
-    BR_OE_X = 2,      // t64 = D_oe x_sel (double)
-    BR_EO_RESID = 3   // rhi = b - (m^2 + sigma_sel) x_sel + D_eo t64 (double), partial |rhi|^2
-};
-
+// Tables read by the vector and recursion kernels of a batch.
 struct BView {
     const BLat *lats;
     const BSys *sys;
-    const BTile *tiles;
-    int ntiles;
     int nsys;
 };
 
@@ -74,12 +59,6 @@ struct BDslashCfg {
     int block;   // sites per block: 64, 128 or 256
     int rpt;     // right-hand sides per thread: 1, 2, 4 or 8
 };
-
-// sel < 0 selects each system's base shift.  skip_done 1: systems whose solve
-// ended are skipped; 2: systems with no reliable update due are skipped.
-// write: BR_EO_RESID also stores rhi.
-hipError_t launch_bdslash(bool dbl, int nrow, BDslashCfg cfg, BView v, int role, int sel, int skip_done, int write,
-                          hipStream_t s);
 
 // Vector kernels over every system (grid.y = system).
 enum BVecOp {
@@ -95,13 +74,11 @@ enum BVecOp {
 hipError_t launch_bvec(bool dbl, BView v, int op, int max_blocks, hipStream_t s);
 
 enum BTail {
-    BT_INIT = 0,       // rho from part_ds (x_init) or part_bl; |b|^2 from part_bl
-    BT_ALPHA = 1,
-    BT_BETA = 2,
-    BT_RELIABLE = 3,
-    BT_TRUE_RESID = 4  // shift sel
+    BT_INIT = 0,       // zero start: rho = |b|^2 from part_bl
+    BT_ALPHA = 1,      // <p, A p> from part_ds
+    BT_BETA = 2        // |r|^2 from part_bl
 };
-hipError_t launch_btail(BView v, int kind, int sel, hipStream_t s);
+hipError_t launch_btail(BView v, int kind, hipStream_t s);
 hipError_t launch_ball_done(BView v, int *flag, hipStream_t s);
 
 // ---------------------------------------------------------------- host side
@@ -128,16 +105,12 @@ struct BOptions {
     int max_iter;
     bool dbl;
     int reliable_every;     // 0: none
-    bool use_graph;
     int force_block;        // 0: autotune
     int force_rpt;
 };
 
-stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *out, hipStream_t user_stream);
-// the direct-launch form (per-lattice multi-RHS Dslash with arguments by value,
-// no tile table, no graph, the caller's stream)
-stag_status run_batched2(const BSpec *spec, int nsys, const BOptions &opt, BOut *out, hipStream_t s);
-BDslashCfg last_batch_cfg2();
+// per-lattice multi-RHS Dslash with arguments by value; everything on stream s
+stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *out, hipStream_t s);
 // refine every (system, shift) whose true residual in stats exceeds opt.tol
 stag_status refine_batched(const BSpec *spec, int nsys, const BOptions &opt, stag_cg_stats *stats, hipStream_t s);
 stag_status batched_solve(const BSpec *spec, int nsys, const BOptions &opt, bool mixed, stag_cg_stats *stats,

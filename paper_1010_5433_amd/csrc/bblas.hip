@@ -152,9 +152,10 @@ hipError_t launch_bvec(bool dbl, BView v, int op, int max_blocks, hipStream_t s)
     return hipGetLastError();
 }
 
-// One workgroup per system.
+// One workgroup per system: sum the partials in a fixed order, then apply
+// the step of the shifted recursion.
 constexpr int kBTailBlock = 256;
-__global__ void __launch_bounds__(kBTailBlock) kb_tail(BView v, int kind, int sel) {
+__global__ void __launch_bounds__(kBTailBlock) kb_tail(BView v, int kind) {
     __shared__ double red[kBTailBlock / kWave];
     const BSys &s = v.sys[blockIdx.x];
     MsState *st = s.st;
@@ -163,41 +164,20 @@ __global__ void __launch_bounds__(kBTailBlock) kb_tail(BView v, int kind, int se
         if (st->done) return;
     }
     if (kind == BT_BETA && st->done) return;
-    if (kind == BT_RELIABLE && st->rel_skip) return;
-    const bool use_ds = kind == BT_ALPHA || kind == BT_RELIABLE || kind == BT_TRUE_RESID || (kind == BT_INIT && s.x_init);
+    const bool use_ds = kind == BT_ALPHA;
     const double *part = use_ds ? s.part_ds : s.part_bl;
     const int np = use_ds ? s.nchunk_ds : s.nchunk_bl;
     double t = 0.0;
     for (int k = threadIdx.x; k < np; k += kBTailBlock) t += part[k];
     const double total = block_sum(t, red);
-    if (kind == BT_INIT) {
-        double b2 = total;
-        if (s.x_init) {
-            double tb = 0.0;
-            for (int k = threadIdx.x; k < s.nchunk_bl; k += kBTailBlock) tb += s.part_bl[k];
-            b2 = block_sum(tb, red);
-        }
-        ms_init_step(st, total, b2);
-    } else if (kind == BT_ALPHA) {
-        ms_alpha_step(st, total);
-    } else if (kind == BT_BETA) {
-        ms_beta_step(st, total);
-    } else if (kind == BT_RELIABLE) {
-        if (threadIdx.x == 0) {
-            st->rho = total;
-            st->rho_rel = total;
-            st->n_reliable += 1;
-        }
-    } else if (kind == BT_TRUE_RESID) {
-        const int k = sel < 0 ? s.base : sel;
-        if (threadIdx.x == 0 && k < s.n)
-            st->resid_true[k] = st->bnorm2 > 0.0 ? sqrt(total / st->bnorm2) : sqrt(total);
-    }
+    if (kind == BT_INIT) ms_init_step(st, total, total);   // zero start: r = b
+    else if (kind == BT_ALPHA) ms_alpha_step(st, total);
+    else ms_beta_step(st, total);
 }
 
-hipError_t launch_btail(BView v, int kind, int sel, hipStream_t s) {
+hipError_t launch_btail(BView v, int kind, hipStream_t s) {
     if (v.nsys <= 0) return hipSuccess;
-    hipLaunchKernelGGL(kb_tail, dim3(v.nsys), dim3(kBTailBlock), 0, s, v, kind, sel);
+    hipLaunchKernelGGL(kb_tail, dim3(v.nsys), dim3(kBTailBlock), 0, s, v, kind);
     return hipGetLastError();
 }
 

@@ -1,54 +1,66 @@
-// Multi-RHS batched half-Dslash.
+// Batched shifted CG: the multi-RHS half-Dslash and the iteration driver.
 //
-// A launch walks a tile table.  A tile is (lattice, 64..256 consecutive
-// output sites, up to RPT systems on that lattice).  Each lane handles one
-// site: it loads the 4 forward and 4 backward links once and applies them
-// to the neighbour vectors of every live system of the tile, so the link
-// traffic -- 92% of a single-RHS Dslash in double precision -- is divided by
-// the number of right-hand sides.  Tiles of different lattices (different
-// extents) share the launch: every tile reads its own geometry.
+// Many systems (pseudo-fermions x shifts, and lattices of different sizes)
+// advance together.  Per iteration:
+//  * the two half-Dslash launches run per lattice, one lane per site, each
+//    lane loading its 8 links once for up to 8 right-hand sides (the systems
+//    of that lattice); the per-system pointers and scalars travel in the
+//    kernel arguments;
+//  * the vector updates and the scalar recursions run once for all systems
+//    (grid.y = system, or one workgroup per system), whatever their lattice;
+//  * the double precision residual work (reliable updates, true residuals,
+//    warm starts) is rare and uses the single-system kernels.
+// Everything is enqueued on the caller's stream in chunks of iterations; a
+// 4-byte "all systems done" flag is read one chunk behind.  The launch shape
+// of the multi-RHS Dslash (sites per block, right-hand sides per launch) is
+// timed on the first batch of each layout and cached.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
 #include "batch.h"
 #include "links.h"
+#include "ms_device.h"
 
 namespace stag {
 
+// Arguments of one multi-RHS half-Dslash launch on one lattice.
+struct BDArgs {
+    Geom g;
+    const void *links;
+    int nrhs;
+    int pad;
+    const void *in[kMaxRpt];     // OE: p_base; EO: t
+    void *out[kMaxRpt];          // OE: t; EO: ap
+    const void *aux[kMaxRpt];    // EO: p_base
+    double c[kMaxRpt];           // EO: m^2 + sigma_base
+    double *part[kMaxRpt];       // EO: one partial of <p, ap> per 64 consecutive sites
+    int nchunk[kMaxRpt];         // partials of each system (ceil(V/2 / 64))
+    const int *done[kMaxRpt];    // a system whose solve ended is skipped
+};
+
+enum BDRole { BD_OE = 0, BD_EO = 1 };
+
 template <typename R, int NROW, int RPT, int ROLE>
-__global__ void __launch_bounds__(256) kb_dslash(BView v, int sel, int skip_done, int write) {
-    const BTile tile = v.tiles[xcd_tile(blockIdx.x, gridDim.x)];
-    const BLat lat = v.lats[tile.lat];
-    const int vh = lat.g.Vh;
-    const BSys *sp[RPT];
-    const void *in[RPT];
-    int sh[RPT];
+__global__ void __launch_bounds__(256) kb_dslash(BDArgs a) {
+    const int vh = a.g.Vh;
     bool live[RPT];
     bool any = false;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        live[r] = false;
-        sp[r] = nullptr;
-        in[r] = nullptr;
-        sh[r] = 0;
-        if (r < tile.nsys) {
-            const BSys *s = v.sys + tile.sys[r];
-            const int k = sel < 0 ? s->base : sel;
-            // skip_done 1: systems whose solve ended; 2: systems with no reliable update due
-            bool l = !(skip_done == 1 ? s->st->done : skip_done == 2 ? s->st->rel_skip : 0);
-            if (ROLE == BR_OE_X || ROLE == BR_EO_RESID) l = l && k < s->n;
-            if (l) {
-                live[r] = true;
-                sp[r] = s;
-                sh[r] = k;
-                in[r] = ROLE == BR_OE_P ? s->p[s->base] : ROLE == BR_EO_AP ? s->t
-                      : ROLE == BR_OE_X ? (const void *)s->xhi[k] : (const void *)s->t64;
-                any = true;
-            }
-        }
+        live[r] = r < a.nrhs && !*a.done[r];
+        any = any || live[r];
     }
     if (!any) return;
-
-    const int p = (ROLE == BR_OE_P || ROLE == BR_OE_X) ? 1 : 0;
-    const void *links = (ROLE == BR_OE_X || ROLE == BR_EO_RESID) ? lat.links64 : lat.links;
-    const int i = tile.site0 + threadIdx.x;
+    const int p = ROLE == BD_OE ? 1 : 0;
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     vec3<R> acc[RPT];
     double part[RPT];
 #pragma unroll
@@ -59,119 +71,417 @@ __global__ void __launch_bounds__(256) kb_dslash(BView v, int sel, int skip_done
     }
     if (i < vh) {
         int x[4];
-        site_coords(lat.g, p, i, x);
+        site_coords(a.g, p, i, x);
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
-            const int jf = site_nbr(lat.g, i, x, mu, +1);
-            const int jb = site_nbr(lat.g, i, x, mu, -1);
-            const su3<R> uf = LinkLayout<R, NROW>::load(links, vh, p * 4 + mu, i);
-            const R sf = R(fwd_sign(lat.g, x, mu));
+            const int jf = site_nbr(a.g, i, x, mu, +1);
+            const int jb = site_nbr(a.g, i, x, mu, -1);
+            const su3<R> uf = LinkLayout<R, NROW>::load(a.links, vh, p * 4 + mu, i);
+            const R sf = R(fwd_sign(a.g, x, mu));
 #pragma unroll
             for (int r = 0; r < RPT; ++r)
-                if (live[r]) acc_mul(acc[r], sf, uf, load_vec<R>(in[r], vh, jf));
-            const su3<R> ub = LinkLayout<R, NROW>::load(links, vh, (1 - p) * 4 + mu, jb);
-            const R sb = R(-bwd_sign(lat.g, x, mu));
+                if (live[r]) acc_mul(acc[r], sf, uf, load_vec<R>(a.in[r], vh, jf));
+            const su3<R> ub = LinkLayout<R, NROW>::load(a.links, vh, (1 - p) * 4 + mu, jb);
+            const R sb = R(-bwd_sign(a.g, x, mu));
 #pragma unroll
             for (int r = 0; r < RPT; ++r)
-                if (live[r]) acc_mul_dag(acc[r], sb, ub, load_vec<R>(in[r], vh, jb));
+                if (live[r]) acc_mul_dag(acc[r], sb, ub, load_vec<R>(a.in[r], vh, jb));
         }
         const R half = R(0.5);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             if (!live[r]) continue;
-            const BSys *s = sp[r];
-            if (ROLE == BR_OE_P || ROLE == BR_OE_X) {
-                vec3<R> o;
+            vec3<R> o;
+            if (ROLE == BD_OE) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) o.c[c] = half * acc[r].c[c];
-                store_vec<R>(ROLE == BR_OE_P ? s->t : (void *)s->t64, vh, i, o);
-            } else if (ROLE == BR_EO_AP) {
-                const vec3<R> pv = load_vec<R>(s->p[s->base], vh, i);
-                const R c = R(s->m2 + s->shifts[s->base]);
-                vec3<R> o;
+            } else {
+                const vec3<R> pv = load_vec<R>(a.aux[r], vh, i);
+                const R cc = R(a.c[r]);
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    o.c[k] = c * pv.c[k] - half * acc[r].c[k];
+                    o.c[k] = cc * pv.c[k] - half * acc[r].c[k];
                     part[r] += double(pv.c[k].re) * double(o.c[k].re) + double(pv.c[k].im) * double(o.c[k].im);
                 }
-                store_vec<R>(s->ap, vh, i, o);
-            } else {  // BR_EO_RESID (double)
-                const vec3<R> xv = load_vec<R>(s->xhi[sh[r]], vh, i);
-                const vec3<R> bv = load_vec<R>(s->src, vh, i);
-                const R c = R(s->m2 + s->shifts[sh[r]]);
-                vec3<R> o;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    o.c[k] = bv.c[k] - (c * xv.c[k] - half * acc[r].c[k]);
-                    part[r] += double(o.c[k].re) * double(o.c[k].re) + double(o.c[k].im) * double(o.c[k].im);
-                }
-                if (write) store_vec<R>(s->rhi, vh, i, o);
             }
+            store_vec<R>(a.out[r], vh, i, o);
         }
     }
-    if (ROLE == BR_EO_AP || ROLE == BR_EO_RESID) {
-        // one partial per 64 consecutive sites, independent of the block size
-        const int chunk = (tile.site0 >> 6) + (int)(threadIdx.x >> 6);
+    if (ROLE == BD_EO) {
+        // one partial per 64 consecutive sites, whatever the block size
+        const int chunk = (i - (threadIdx.x & (kWave - 1))) >> 6;
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             if (!live[r]) continue;
             const double w = wave_sum(part[r]);
-            if ((threadIdx.x & 63) == 0 && chunk < sp[r]->nchunk_ds) sp[r]->part_ds[chunk] = w;
+            if ((threadIdx.x & (kWave - 1)) == 0 && chunk < a.nchunk[r]) a.part[r][chunk] = w;
         }
     }
 }
 
 template <typename R, int NROW, int RPT>
-static hipError_t launch_role(int role, int block, BView v, int sel, int skip, int write, hipStream_t s) {
-    const dim3 grid(v.ntiles), blk(block);
-    switch (role) {
-        case BR_OE_P: hipLaunchKernelGGL((kb_dslash<R, NROW, RPT, BR_OE_P>), grid, blk, 0, s, v, sel, skip, write); break;
-        case BR_EO_AP: hipLaunchKernelGGL((kb_dslash<R, NROW, RPT, BR_EO_AP>), grid, blk, 0, s, v, sel, skip, write); break;
-        default: return hipErrorInvalidValue;
-    }
+static hipError_t bd_launch_rpt(int role, int block, const BDArgs &a, hipStream_t s) {
+    const dim3 grid((a.g.Vh + block - 1) / block), blk(block);
+    if (role == BD_OE) hipLaunchKernelGGL((kb_dslash<R, NROW, RPT, BD_OE>), grid, blk, 0, s, a);
+    else hipLaunchKernelGGL((kb_dslash<R, NROW, RPT, BD_EO>), grid, blk, 0, s, a);
     return hipGetLastError();
 }
 
-template <int NROW, int RPT>
-static hipError_t launch_role64(int role, int block, BView v, int sel, int skip, int write, hipStream_t s) {
-    const dim3 grid(v.ntiles), blk(block);
-    switch (role) {
-        case BR_OE_P: hipLaunchKernelGGL((kb_dslash<double, NROW, RPT, BR_OE_P>), grid, blk, 0, s, v, sel, skip, write); break;
-        case BR_EO_AP: hipLaunchKernelGGL((kb_dslash<double, NROW, RPT, BR_EO_AP>), grid, blk, 0, s, v, sel, skip, write); break;
-        case BR_OE_X: hipLaunchKernelGGL((kb_dslash<double, NROW, RPT, BR_OE_X>), grid, blk, 0, s, v, sel, skip, write); break;
-        case BR_EO_RESID: hipLaunchKernelGGL((kb_dslash<double, NROW, RPT, BR_EO_RESID>), grid, blk, 0, s, v, sel, skip, write); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <int NROW>
-static hipError_t launch_nrow(bool dbl, BDslashCfg cfg, BView v, int role, int sel, int skip, int write, hipStream_t s) {
-    // the double precision residual roles always run on the double links
-    if (dbl || role == BR_OE_X || role == BR_EO_RESID) {
-        switch (cfg.rpt) {
-            case 1: return launch_role64<NROW, 1>(role, cfg.block, v, sel, skip, write, s);
-            case 2: return launch_role64<NROW, 2>(role, cfg.block, v, sel, skip, write, s);
-            case 4: return launch_role64<NROW, 4>(role, cfg.block, v, sel, skip, write, s);
-            case 8: return launch_role64<NROW, 8>(role, cfg.block, v, sel, skip, write, s);
-        }
-    } else {
-        switch (cfg.rpt) {
-            case 1: return launch_role<float, NROW, 1>(role, cfg.block, v, sel, skip, write, s);
-            case 2: return launch_role<float, NROW, 2>(role, cfg.block, v, sel, skip, write, s);
-            case 4: return launch_role<float, NROW, 4>(role, cfg.block, v, sel, skip, write, s);
-            case 8: return launch_role<float, NROW, 8>(role, cfg.block, v, sel, skip, write, s);
-        }
+template <typename R, int NROW>
+static hipError_t bd_launch_nrow(int role, BDslashCfg cfg, const BDArgs &a, hipStream_t s) {
+    switch (cfg.rpt) {
+        case 1: return bd_launch_rpt<R, NROW, 1>(role, cfg.block, a, s);
+        case 2: return bd_launch_rpt<R, NROW, 2>(role, cfg.block, a, s);
+        case 4: return bd_launch_rpt<R, NROW, 4>(role, cfg.block, a, s);
+        case 8: return bd_launch_rpt<R, NROW, 8>(role, cfg.block, a, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_bdslash(bool dbl, int nrow, BDslashCfg cfg, BView v, int role, int sel, int skip_done, int write,
-                          hipStream_t s) {
-    if (v.ntiles <= 0) return hipSuccess;
+static hipError_t bd_launch(bool dbl, int nrow, int role, BDslashCfg cfg, const BDArgs &a, hipStream_t s) {
+    if (a.nrhs < 1 || a.nrhs > cfg.rpt || a.nrhs > kMaxRpt) return hipErrorInvalidValue;
     if (cfg.block != 64 && cfg.block != 128 && cfg.block != 256) return hipErrorInvalidValue;
-    return nrow == 2 ? launch_nrow<2>(dbl, cfg, v, role, sel, skip_done, write, s)
-                     : launch_nrow<3>(dbl, cfg, v, role, sel, skip_done, write, s);
+    if (dbl) return nrow == 2 ? bd_launch_nrow<double, 2>(role, cfg, a, s) : bd_launch_nrow<double, 3>(role, cfg, a, s);
+    return nrow == 2 ? bd_launch_nrow<float, 2>(role, cfg, a, s) : bd_launch_nrow<float, 3>(role, cfg, a, s);
+}
+
+// ---------------------------------------------------------------- launch-shape cache
+
+static std::mutex g_tune_mu;
+static std::map<std::string, BDslashCfg> g_tune;
+static thread_local BDslashCfg g_last_cfg = {0, 0};
+
+BDslashCfg last_batch_cfg() { return g_last_cfg; }
+
+static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *out, hipStream_t s) {
+    if (nsys < 1 || nsys > kMaxBatch) return invalid("a batch holds 1..64 systems");
+    const bool dbl = opt.dbl;
+    const bool any_init = std::any_of(spec, spec + nsys, [](const BSpec &p) { return p.x_init; });
+    const bool all_init = std::all_of(spec, spec + nsys, [](const BSpec &p) { return p.x_init; });
+    if (any_init && !all_init) return invalid("a batch is either all zero-start or all warm-start");
+    for (int k = 0; k < nsys; ++k)
+        if (spec[k].x_init && spec[k].n != 1) return invalid("a warm-started system has exactly one shift");
+
+    // ---- lattices and their systems
+    std::vector<stag_lattice *> lats;
+    std::vector<std::vector<int>> members;
+    std::vector<int> sys_lat(nsys);
+    for (int k = 0; k < nsys; ++k) {
+        int li = -1;
+        for (size_t l = 0; l < lats.size(); ++l)
+            if (lats[l] == spec[k].lat) li = (int)l;
+        if (li < 0) {
+            lats.push_back(spec[k].lat);
+            members.emplace_back();
+            li = (int)lats.size() - 1;
+        }
+        members[li].push_back(k);
+        sys_lat[k] = li;
+    }
+    const int nlat = (int)lats.size();
+    const int nrow = lats[0]->nrow;
+    for (int l = 1; l < nlat; ++l)
+        if (lats[l]->nrow != nrow) return invalid("all lattices of a batch must use the same link format");
+
+    // ---- work arena (carved from the first lattice's handle)
+    int max_ds = 1;
+    for (int l = 0; l < nlat; ++l) max_ds = std::max(max_ds, dslash_grid(lats[l]->g, kDslashBlock));
+    size_t bytes = al256(sizeof(BLat) * nlat) + al256(sizeof(BSys) * nsys) + al256(sizeof(MsState) * nsys) + 256;
+    for (int k = 0; k < nsys; ++k) {
+        const int64_t vh = spec[k].lat->Vh;
+        const size_t vb = (size_t)(dbl ? 48 : 24) * vh, v64 = (size_t)48 * vh;
+        const int nds = (int)((vh + 63) / 64), nbl = (int)((3 * vh + kBChunk - 1) / kBChunk);
+        size_t b = al256(sizeof(double) * nds) + al256(sizeof(double) * nbl) + al256(sizeof(double) * max_ds);
+        b += 3 * al256(vb) + 2 * al256(v64) + spec[k].n * al256(vb);
+        if (!dbl) b += spec[k].n * al256(vb);
+        bytes += b;
+    }
+    void *arena = nullptr;
+    STAG_TRY(ws_get(lats[0], WS_BATCH, bytes, &arena));
+    char *cur = static_cast<char *>(arena);
+    auto take = [&](size_t n) {
+        char *p = cur;
+        cur += al256(n);
+        return p;
+    };
+    BLat *d_lat = reinterpret_cast<BLat *>(take(sizeof(BLat) * nlat));
+    BSys *d_sys = reinterpret_cast<BSys *>(take(sizeof(BSys) * nsys));
+    MsState *d_st = reinterpret_cast<MsState *>(take(sizeof(MsState) * nsys));
+    int *d_flag = reinterpret_cast<int *>(take(256));
+
+    std::vector<BLat> h_lat(nlat);
+    for (int l = 0; l < nlat; ++l) {
+        std::memset(&h_lat[l], 0, sizeof(BLat));
+        h_lat[l].g = lats[l]->g;
+        h_lat[l].nrow = nrow;
+        h_lat[l].links = dbl ? lats[l]->links64 : lats[l]->links32;
+        h_lat[l].links64 = lats[l]->links64;
+    }
+    std::vector<BSys> h_sys(nsys);
+    std::vector<MsState> h_st(nsys);
+    std::vector<double *> pres(nsys);   // per-system partials of the single-system residual kernels
+    int max_n = 0, max_blocks = 1;
+    for (int k = 0; k < nsys; ++k) {
+        const BSpec &sp = spec[k];
+        BSys &y = h_sys[k];
+        std::memset(&y, 0, sizeof(BSys));
+        const int64_t vh = sp.lat->Vh;
+        const size_t vb = (size_t)(dbl ? 48 : 24) * vh, v64 = (size_t)48 * vh;
+        y.lat = sys_lat[k];
+        y.n = sp.n;
+        y.base = 0;
+        for (int i = 1; i < sp.n; ++i)
+            if (sp.shifts[i] < sp.shifts[y.base]) y.base = i;
+        y.nchunk_ds = (int)((vh + 63) / 64);
+        y.nchunk_bl = (int)((3 * vh + kBChunk - 1) / kBChunk);
+        y.x_init = sp.x_init ? 1 : 0;
+        y.m2 = sp.mass * sp.mass;
+        for (int i = 0; i < sp.n; ++i) y.shifts[i] = sp.shifts[i];
+        y.st = d_st + k;
+        y.part_ds = reinterpret_cast<double *>(take(sizeof(double) * y.nchunk_ds));
+        y.part_bl = reinterpret_cast<double *>(take(sizeof(double) * y.nchunk_bl));
+        pres[k] = reinterpret_cast<double *>(take(sizeof(double) * max_ds));
+        y.src = static_cast<const double2 *>(sp.src);
+        y.r = take(vb);
+        y.ap = take(vb);
+        y.t = take(vb);
+        y.t64 = reinterpret_cast<double2 *>(take(v64));
+        y.rhi = reinterpret_cast<double2 *>(take(v64));
+        for (int i = 0; i < sp.n; ++i) {
+            y.p[i] = take(vb);
+            y.xhi[i] = static_cast<double2 *>(sp.sols[i]);
+            y.x[i] = dbl ? sp.sols[i] : take(vb);
+        }
+        MsState &st = h_st[k];
+        std::memset(&st, 0, sizeof(MsState));
+        st.n = sp.n;
+        st.base = y.base;
+        st.tol = opt.tol;
+        st.max_iter = opt.max_iter;
+        st.rel_delta2 = (!dbl && opt.reliable_every > 0) ? 0.01 : 0.0;
+        for (int i = 0; i < sp.n; ++i) st.shift_rel[i] = sp.shifts[i] - sp.shifts[y.base];
+        max_n = std::max(max_n, sp.n);
+        max_blocks = std::max(max_blocks, (y.nchunk_bl + kBBlock / kWave - 1) / (kBBlock / kWave));
+    }
+    STAG_HIP(hipMemcpyAsync(d_lat, h_lat.data(), sizeof(BLat) * nlat, hipMemcpyHostToDevice, s));
+    STAG_HIP(hipMemcpyAsync(d_sys, h_sys.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice, s));
+    STAG_HIP(hipMemcpyAsync(d_st, h_st.data(), sizeof(MsState) * nsys, hipMemcpyHostToDevice, s));
+    // the host copies must stay valid until the copies ran
+    STAG_HIP(hipStreamSynchronize(s));
+
+    BView v;
+    std::memset(&v, 0, sizeof(v));
+    v.lats = d_lat;
+    v.sys = d_sys;
+    v.nsys = nsys;
+
+    // b - (M + shift_i) x_i of system k in double precision, single-system kernels
+    auto residual = [&](int k, int i, void *rout, const int *skip) -> hipError_t {
+        stag_lattice *lat = spec[k].lat;
+        DslashArgs d;
+        std::memset(&d, 0, sizeof(d));
+        d.g = lat->g;
+        d.links = lat->links64;
+        d.skip = skip;
+        d.out_parity = 1;
+        d.in = h_sys[k].xhi[i];
+        d.out = h_sys[k].t64;
+        hipError_t e = launch_dslash(true, nrow, DS_PLAIN, d, s);
+        if (e != hipSuccess) return e;
+        d.out_parity = 0;
+        d.in = h_sys[k].t64;
+        d.out = rout;
+        d.aux = h_sys[k].xhi[i];
+        d.rhs = spec[k].src;
+        d.c = h_sys[k].m2 + spec[k].shifts[i];
+        d.partial = pres[k];
+        return launch_dslash(true, nrow, DS_RESID, d, s);
+    };
+
+    // ---- start
+    if (all_init) {
+        for (int k = 0; k < nsys; ++k) STAG_HIP(residual(k, 0, h_sys[k].rhi, nullptr));
+        STAG_HIP(launch_bvec(dbl, v, BV_RESTART, max_blocks, s));
+        STAG_HIP(launch_bvec(dbl, v, BV_NORM_SRC, max_blocks, s));
+        for (int k = 0; k < nsys; ++k)
+            STAG_HIP(launch_scalar_init(d_st + k, pres[k], dslash_grid(spec[k].lat->g, kDslashBlock),
+                                        h_sys[k].part_bl, h_sys[k].nchunk_bl, s));
+    } else {
+        STAG_HIP(launch_bvec(dbl, v, BV_START, max_blocks, s));
+        STAG_HIP(launch_bvec(dbl, v, BV_NORM_SRC, max_blocks, s));
+        STAG_HIP(launch_btail(v, BT_INIT, s));
+    }
+
+    // ---- multi-RHS Dslash arguments: per lattice, groups of at most 8 systems
+    auto make_args = [&](int l, const std::vector<int> &grp, int role) {
+        BDArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.g = lats[l]->g;
+        a.links = h_lat[l].links;
+        a.nrhs = (int)grp.size();
+        for (size_t r = 0; r < grp.size(); ++r) {
+            const int k = grp[r];
+            const BSys &y = h_sys[k];
+            a.done[r] = &d_st[k].done;
+            a.nchunk[r] = y.nchunk_ds;
+            if (role == BD_OE) {
+                a.in[r] = y.p[y.base];
+                a.out[r] = y.t;
+            } else {
+                a.in[r] = y.t;
+                a.out[r] = y.ap;
+                a.aux[r] = y.p[y.base];
+                a.c[r] = y.m2 + y.shifts[y.base];
+                a.part[r] = y.part_ds;
+            }
+        }
+        return a;
+    };
+    auto groups_of = [&](int l, int rpt) {
+        std::vector<std::vector<int>> gs;
+        const std::vector<int> &m = members[l];
+        for (size_t k0 = 0; k0 < m.size(); k0 += rpt)
+            gs.emplace_back(m.begin() + k0, m.begin() + std::min(m.size(), k0 + (size_t)rpt));
+        return gs;
+    };
+
+    // ---- launch shape per lattice: cached, else timed on this batch (t = D_oe p)
+    std::vector<BDslashCfg> cfg(nlat);
+    for (int l = 0; l < nlat; ++l) {
+        const stag_lattice *lat = lats[l];
+        std::ostringstream key;
+        key << (dbl ? "f64" : "f32") << " nrow" << nrow << " " << lat->dims[0] << "x" << lat->dims[1] << "x"
+            << lat->dims[2] << "x" << lat->dims[3] << ":" << members[l].size();
+        BDslashCfg c = {0, 0};
+        if (opt.force_block && opt.force_rpt) {
+            c = {opt.force_block, opt.force_rpt};
+        } else {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune.find(key.str());
+            if (it != g_tune.end()) c = it->second;
+        }
+        if (!c.block) {
+            hipEvent_t e0, e1;
+            STAG_HIP(hipEventCreate(&e0));
+            STAG_HIP(hipEventCreate(&e1));
+            float best = 1e30f;
+            const size_t ns = members[l].size();
+            for (int rpt : {1, 2, 4, 8}) {
+                if (rpt > 1 && (size_t)rpt / 2 >= ns) continue;
+                for (int blk : {64, 128, 256}) {
+                    const BDslashCfg cc = {blk, rpt};
+                    const auto gs = groups_of(l, rpt);
+                    for (int w = 0; w < 7; ++w) {
+                        if (w == 2) STAG_HIP(hipEventRecord(e0, s));
+                        for (const auto &grp : gs) STAG_HIP(bd_launch(dbl, nrow, BD_OE, cc, make_args(l, grp, BD_OE), s));
+                    }
+                    STAG_HIP(hipEventRecord(e1, s));
+                    STAG_HIP(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    STAG_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best) {
+                        best = ms;
+                        c = cc;
+                    }
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune[key.str()] = c;
+        }
+        cfg[l] = c;
+    }
+    g_last_cfg = cfg[0];
+    std::vector<std::vector<std::pair<BDArgs, BDArgs>>> args(nlat);
+    for (int l = 0; l < nlat; ++l)
+        for (const auto &grp : groups_of(l, cfg[l].rpt))
+            args[l].push_back({make_args(l, grp, BD_OE), make_args(l, grp, BD_EO)});
+
+    // ---- iterations
+    const bool use_rel = !dbl && opt.reliable_every > 0;
+    const int check = use_rel ? opt.reliable_every : 0;
+    auto iteration = [&](int it) -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int l = 0; l < nlat && e == hipSuccess; ++l)
+            for (const auto &pa : args[l]) {
+                e = bd_launch(dbl, nrow, BD_OE, cfg[l], pa.first, s);
+                if (e != hipSuccess) return e;
+                e = bd_launch(dbl, nrow, BD_EO, cfg[l], pa.second, s);
+                if (e != hipSuccess) return e;
+            }
+        if (e == hipSuccess) e = launch_btail(v, BT_ALPHA, s);
+        if (e == hipSuccess) e = launch_bvec(dbl, v, BV_R_UPDATE, max_blocks, s);
+        if (e == hipSuccess) e = launch_btail(v, BT_BETA, s);
+        if (e == hipSuccess) e = launch_bvec(dbl, v, BV_SHIFT_UPDATE, max_blocks, s);
+        if (e == hipSuccess && check > 0 && (it + 1) % check == 0) {
+            // reliable update of every system whose residual fell tenfold since its last one
+            e = launch_bvec(dbl, v, BV_FLUSH, max_blocks, s);
+            for (int k = 0; k < nsys && e == hipSuccess; ++k) {
+                e = residual(k, h_sys[k].base, h_sys[k].rhi, &d_st[k].rel_skip);
+                if (e == hipSuccess)
+                    e = launch_reduce_tail(d_st + k, pres[k], dslash_grid(spec[k].lat->g, kDslashBlock), TAIL_RELIABLE,
+                                           0, s);
+            }
+            if (e == hipSuccess) e = launch_bvec(dbl, v, BV_DEMOTE, max_blocks, s);
+        }
+        return e;
+    };
+    volatile int *flags = lats[0]->host_flags;
+    flags[0] = flags[1] = 0;
+    hipEvent_t ev[2];
+    STAG_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    STAG_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    constexpr int K = 8;
+    stag_status rc = STAG_OK;
+    for (int chunk = 0;; ++chunk) {
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < K && e == hipSuccess; ++k) e = iteration(chunk * K + k);
+        if (e == hipSuccess) e = launch_ball_done(v, d_flag, s);
+        const int slot = chunk & 1;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(const_cast<int *>(flags + slot), d_flag, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(ev[slot], s);
+        if (e == hipSuccess && chunk > 0) {
+            e = hipEventSynchronize(ev[slot ^ 1]);
+            if (e == hipSuccess && flags[slot ^ 1]) break;
+        }
+        if (e != hipSuccess) {
+            set_error(std::string("batched iteration failed: ") + hipGetErrorString(e));
+            rc = STAG_EHIP;
+            break;
+        }
+        if ((chunk + 1) * K > opt.max_iter + K) break;
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (rc != STAG_OK) return rc;
+
+    // ---- finish: flush single precision accumulators, double precision true residuals
+    if (!dbl) STAG_HIP(launch_bvec(dbl, v, BV_FLUSH_FINAL, max_blocks, s));
+    for (int k = 0; k < nsys; ++k)
+        for (int i = 0; i < spec[k].n; ++i) {
+            STAG_HIP(residual(k, i, nullptr, nullptr));
+            STAG_HIP(launch_reduce_tail(d_st + k, pres[k], dslash_grid(spec[k].lat->g, kDslashBlock), TAIL_TRUE_RESID,
+                                        i, s));
+        }
+    STAG_HIP(hipMemcpyAsync(h_st.data(), d_st, sizeof(MsState) * nsys, hipMemcpyDeviceToHost, s));
+    STAG_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < nsys; ++k) {
+        const MsState &st = h_st[k];
+        BOut &o = out[k];
+        o.status = st.status;
+        o.iters = st.iter;
+        o.n_reliable = st.n_reliable;
+        for (int i = 0; i < st.n; ++i) {
+            o.iters_shift[i] = st.active[i] ? st.iter : st.iters_shift[i];
+            o.resid_iter[i] = st.resid_iter[i];
+            o.resid_true[i] = st.resid_true[i];
+        }
+    }
+    return STAG_OK;
 }
 
 }  // namespace stag

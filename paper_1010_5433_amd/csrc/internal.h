@@ -96,7 +96,6 @@ struct stag_lattice {
     void *ws[WS_NSLOTS];
     size_t ws_bytes[WS_NSLOTS];
     int *host_flags;     // pinned host mirror of solver flags
-    hipStream_t capture_stream;  // library stream for graph capture (created on first use)
 };
 
 namespace stag {
