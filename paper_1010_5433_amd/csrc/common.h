@@ -106,6 +106,19 @@ template <typename R> __device__ __forceinline__ vec3<R> load_vec(const void *ba
     for (int c = 0; c < 3; ++c) v.c[c] = ld2<R>(p + c * vh, i);
     return v;
 }
+// Nontemporal store of a colour vector: for an output that the next kernel
+// reads through its neighbour gathers, not through this kernel's caches.
+template <typename R> __device__ __forceinline__ void store_vec_nt(void *base, int64_t vh, int64_t i, const vec3<R> &v) {
+    using T2 = typename vtype<R>::t2;
+    T2 *b = static_cast<T2 *>(base);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T2 w;
+        w.x = v.c[c].re;
+        w.y = v.c[c].im;
+        st_nt(&b[c * vh + i], w);
+    }
+}
 template <typename R> __device__ __forceinline__ void store_vec(void *base, int64_t vh, int64_t i, const vec3<R> &v) {
     typename vtype<R>::t2 *p = static_cast<typename vtype<R>::t2 *>(base);
 #pragma unroll
