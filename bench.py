@@ -35,11 +35,15 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+FMT_NROW = {"18": 3, "12": 2, "8": 1}
+
+
 def dslash_bytes_per_site(dbl: bool, nrow: int, mode: str = "plain") -> int:
     """Minimum unique HBM traffic of one half-Dslash per output site: all 8
     links once, the input vector once (neighbours re-read from cache), the
-    output once; the normal-operator epilogue also reads p."""
-    bl = (16 if dbl else 8) * 3 * nrow
+    output once; the normal-operator epilogue also reads p.  Links take
+    9, 6 or 4 complex words (18-, 12- or 8-real storage)."""
+    bl = (16 if dbl else 8) * (4 if nrow == 1 else 3 * nrow)
     bv = 48 if dbl else 24
     return 8 * bl + (3 if mode == "epilogue" else 2) * bv
 
@@ -206,7 +210,7 @@ def learned_experiment(args, n_test_fields):
     for k, seed in enumerate(c["test_link_seeds"][:n_test_fields]):
         U = syn.smooth_links(c["test_dims"], c["eps"], seed)
         lat = stag.Lattice(c["test_dims"])
-        lat.set_links(torch.from_numpy(U).cuda(), args.fmt)
+        lat.set_links(torch.from_numpy(U).cuda(), "12")   # the network kernels are tuned for 12-real links
         b = syn.gaussian_source(c["test_dims"], c["test_source_seed"] + k)
         src = lat.pack(torch.from_numpy(b).cuda())
         learn.compare(lat, net, mass, src, tol=tol)          # warm-up
@@ -228,7 +232,7 @@ def learned_experiment(args, n_test_fields):
                            steps=args.train_steps, batch=args.batch, lr=args.lr, mode="bf16",
                            seconds=round(t_train, 2), data_seconds=round(t_data, 2),
                            loss_first=round(losses[0], 5), loss_last=round(float(np.mean(losses[-20:])), 5)),
-                test=dict(dims=list(c["test_dims"]), mass=mass, shift=0.0, tol=tol, links=f"{args.fmt}-real",
+                test=dict(dims=list(c["test_dims"]), mass=mass, shift=0.0, tol=tol, links="12-real",
                           fields=evals),
                 gains=gains)
 
@@ -239,7 +243,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="f64", choices=["mixed", "f64", "f32"])
-    ap.add_argument("--fmt", default="12", choices=["18", "12"])
+    ap.add_argument("--fmt", default="8", choices=["18", "12", "8"])
     ap.add_argument("--cpu-sample-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64-reference", action="store_true")
@@ -369,7 +373,7 @@ def main():
 
     # ---- roofline of the dominant kernel: the half-Dslash in the step's precision
     dbl = it_prec == "f64"
-    nrow = 3 if args.fmt == "18" else 2
+    nrow = FMT_NROW[args.fmt]
     sec = time_dslash(lat, it_prec)
     algo = dslash_bytes_per_site(dbl, nrow) * lat.Vh
     achieved = algo / sec / 1e9
@@ -378,13 +382,18 @@ def main():
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 kernel=kname, bytes_per_launch=algo, avg_launch_us=round(sec * 1e6, 2))
-    # the other precision/format pairs, for the record
+    # every precision and link format, for the record (same field, repacked)
     dsl = {}
-    for p in ("f64", "f32"):
-        d = p == "f64"
-        s = time_dslash(lat, p)
-        gbs = dslash_bytes_per_site(d, nrow) * lat.Vh / s / 1e9
-        dsl[f"{p}_{args.fmt}"] = dict(us=round(s * 1e6, 2), GBs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+    for fmt in ("8", "12", "18"):
+        if fmt != args.fmt:
+            lat.set_links(torch.from_numpy(U).cuda(), fmt)
+        for p in ("f64", "f32"):
+            d = p == "f64"
+            s = time_dslash(lat, p)
+            gbs = dslash_bytes_per_site(d, FMT_NROW[fmt]) * lat.Vh / s / 1e9
+            dsl[f"{p}_{fmt}"] = dict(us=round(s * 1e6, 2), GBs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4),
+                                     traffic=read_traffic(f"k_dslash<{'double' if d else 'float'},{FMT_NROW[fmt]},PLAIN>"))
+    lat.set_links(torch.from_numpy(U).cuda(), args.fmt)
     log(f"dslash: {dsl}")
 
     if not args.no_batched:

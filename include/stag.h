@@ -67,8 +67,11 @@ typedef enum {
 
 typedef enum {
     STAG_LINK18 = 0, /* all 9 complex entries of each link */
-    STAG_LINK12 = 1  /* first two rows; third rebuilt as conj(row0 x row1)
+    STAG_LINK12 = 1, /* first two rows; third rebuilt as conj(row0 x row1)
                         (Section 5, 12-real representation); needs SU(3) links */
+    STAG_LINK8 = 2   /* not in the paper: U01, U02, U10 and the phases of U00
+                        and U20; the rest rebuilt from unitarity and det U = 1.
+                        Needs SU(3) links with U01, U02 not both zero */
 } stag_link_fmt;
 
 #define STAG_MAX_SHIFTS 64
@@ -104,8 +107,12 @@ int64_t stag_half_volume(const stag_lattice *lat);
 /* Pack a gauge field into the handle.  links: device, canonical complex128
  * (4,V,3,3).  Both a double and a single precision copy are stored in the
  * even/odd structure-of-arrays layout (element-major, site index fastest;
- * Section 5 and its Figure 2), keeping all 9 entries or the first two rows
- * (fmt).  Links must be SU(3) for STAG_LINK12.  Replaces earlier links. */
+ * Section 5 and its Figure 2), keeping all 9 entries, the first two rows or
+ * 8 reals (fmt).  Links must be SU(3) for STAG_LINK12 and STAG_LINK8.  For
+ * STAG_LINK8 the call rebuilds the double precision field on the device and
+ * returns STAG_EINVAL (links left unset) if any entry is off by more than
+ * 1e-12, which catches links that have no 8-real form; it then waits for
+ * the stream.  Replaces earlier links. */
 stag_status stag_links_set(stag_lattice *lat, const void *links, stag_link_fmt fmt, void *stream);
 
 /* Test hook: write the geometry tables computed by the same device index

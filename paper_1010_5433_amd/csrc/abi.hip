@@ -2,6 +2,7 @@
 // management, and dispatch to the kernels and solver drivers.  No C++
 // exception crosses this boundary.
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -98,24 +99,28 @@ stag_status stag_lattice_create(const int dims[4], int antiperiodic_t, stag_latt
 
 stag_status stag_lattice_destroy(stag_lattice *lat) {
     if (!lat) return STAG_OK;
-    hipSetDevice(lat->device);
-    hipDeviceSynchronize();
-    hipFree(lat->links64);
-    hipFree(lat->links32);
-    for (int k = 0; k < WS_NSLOTS; ++k) hipFree(lat->ws[k]);
-    hipHostFree(lat->host_flags);
+    (void)hipSetDevice(lat->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(lat->links64);
+    (void)hipFree(lat->links32);
+    for (int k = 0; k < WS_NSLOTS; ++k) (void)hipFree(lat->ws[k]);
+    (void)hipHostFree(lat->host_flags);
     delete lat;
     return STAG_OK;
 }
 
 int64_t stag_half_volume(const stag_lattice *lat) { return lat ? lat->Vh : 0; }
 
+// Largest entry error accepted when a field is stored in 8 reals (double
+// precision rebuild; smoothed and Haar fields stay below 3e-14).
+static constexpr double kLink8MaxError = 1e-12;
+
 stag_status stag_links_set(stag_lattice *lat, const void *links, stag_link_fmt fmt, void *stream) {
     STAG_TRY(check_lattice(lat, false));
     if (!links) return invalid("null links");
-    if (fmt != STAG_LINK18 && fmt != STAG_LINK12) return invalid("unknown link format");
+    if (fmt != STAG_LINK18 && fmt != STAG_LINK12 && fmt != STAG_LINK8) return invalid("unknown link format");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int nrow = fmt == STAG_LINK12 ? 2 : 3;
+    const int nrow = fmt == STAG_LINK8 ? 1 : fmt == STAG_LINK12 ? 2 : 3;
     STAG_HIP(hipStreamSynchronize(s));
     if (lat->links64) STAG_HIP(hipFree(lat->links64));
     if (lat->links32) STAG_HIP(hipFree(lat->links32));
@@ -125,6 +130,25 @@ stag_status stag_links_set(stag_lattice *lat, const void *links, stag_link_fmt f
     STAG_HIP(hipMalloc(&lat->links32, link_field_bytes(false, nrow, lat->Vh)));
     STAG_HIP(launch_pack_links(lat->g, links, lat->links64, true, nrow, s));
     STAG_HIP(launch_pack_links(lat->g, links, lat->links32, false, nrow, s));
+    if (nrow == 1) {
+        // the 8-real form needs u01, u02 not both zero: check the rebuilt field
+        const int nb = check_links_blocks(lat->g);
+        void *part = nullptr;
+        STAG_TRY(ws_get(lat, WS_PART, sizeof(double) * nb, &part));
+        STAG_HIP(launch_check_links(lat->g, links, lat->links64, nrow, static_cast<double *>(part), s));
+        std::vector<double> h(nb);
+        STAG_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+        STAG_HIP(hipStreamSynchronize(s));
+        double worst = 0.0;
+        for (double v : h) worst = (v > worst || v != v) ? v : worst;
+        if (!(worst <= kLink8MaxError)) {
+            char buf[32];
+            std::snprintf(buf, sizeof(buf), "%.3g", worst);
+            set_error(std::string("links not representable in 8 reals (rebuilt entries off by ") + buf +
+                      "; a link with u01 = u02 = 0, e.g. the unit matrix, has no 8-real form)");
+            return STAG_EINVAL;
+        }
+    }
     lat->nrow = nrow;
     return STAG_OK;
 }

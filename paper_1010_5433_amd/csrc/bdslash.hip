@@ -72,8 +72,7 @@ __global__ void __launch_bounds__(256) kb_dslash(BDArgs a) {
     if (i < vh) {
         int x[4];
         site_coords(a.g, p, i, x);
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
+        auto hop = [&](int mu) {
             const int jf = site_nbr(a.g, i, x, mu, +1);
             const int jb = site_nbr(a.g, i, x, mu, -1);
             const su3<R> uf = LinkLayout<R, NROW>::load(a.links, vh, p * 4 + mu, i);
@@ -86,6 +85,13 @@ __global__ void __launch_bounds__(256) kb_dslash(BDArgs a) {
 #pragma unroll
             for (int r = 0; r < RPT; ++r)
                 if (live[r]) acc_mul_dag(acc[r], sb, ub, load_vec<R>(a.in[r], vh, jb));
+        };
+        if (NROW == 1) {   // 8-real links: one direction at a time (registers)
+#pragma unroll 1
+            for (int mu = 0; mu < 4; ++mu) hop(mu);
+        } else {
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu) hop(mu);
         }
         const R half = R(0.5);
 #pragma unroll
@@ -141,7 +147,11 @@ static hipError_t bd_launch_nrow(int role, BDslashCfg cfg, const BDArgs &a, hipS
 static hipError_t bd_launch(bool dbl, int nrow, int role, BDslashCfg cfg, const BDArgs &a, hipStream_t s) {
     if (a.nrhs < 1 || a.nrhs > cfg.rpt || a.nrhs > kMaxRpt) return hipErrorInvalidValue;
     if (cfg.block != 64 && cfg.block != 128 && cfg.block != 256) return hipErrorInvalidValue;
-    if (dbl) return nrow == 2 ? bd_launch_nrow<double, 2>(role, cfg, a, s) : bd_launch_nrow<double, 3>(role, cfg, a, s);
+    if (dbl) {
+        if (nrow == 1) return bd_launch_nrow<double, 1>(role, cfg, a, s);
+        return nrow == 2 ? bd_launch_nrow<double, 2>(role, cfg, a, s) : bd_launch_nrow<double, 3>(role, cfg, a, s);
+    }
+    if (nrow == 1) return bd_launch_nrow<float, 1>(role, cfg, a, s);
     return nrow == 2 ? bd_launch_nrow<float, 2>(role, cfg, a, s) : bd_launch_nrow<float, 3>(role, cfg, a, s);
 }
 

@@ -28,8 +28,7 @@ __global__ void __launch_bounds__(kDslashBlock) k_dslash(DslashArgs a) {
         vec3<R> acc;
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc.c[c] = {R(0), R(0)};
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
+        auto hop = [&](int mu) {
             const int jf = site_nbr(a.g, i, x, mu, +1);
             const int jb = site_nbr(a.g, i, x, mu, -1);
             const su3<R> uf = LinkLayout<R, NROW>::load(a.links, vh, p * 4 + mu, i);
@@ -38,6 +37,15 @@ __global__ void __launch_bounds__(kDslashBlock) k_dslash(DslashArgs a) {
             const vec3<R> vb = load_vec<R>(a.in, vh, jb);
             acc_mul(acc, R(fwd_sign(a.g, x, mu)), uf, vf);
             acc_mul_dag(acc, R(-bwd_sign(a.g, x, mu)), ub, vb);
+        };
+        if (NROW == 1) {
+            // the 8-real rebuild is long: one direction at a time keeps the
+            // registers (and so the waves in flight) of the stored forms
+#pragma unroll 1
+            for (int mu = 0; mu < 4; ++mu) hop(mu);
+        } else {
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu) hop(mu);
         }
         const R half = R(0.5);
         if (MODE == DS_PLAIN) {
@@ -95,7 +103,11 @@ static hipError_t launch_mode(int mode, const DslashArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_dslash(bool dbl, int nrow, int mode, const DslashArgs &a, hipStream_t s) {
-    if (dbl) return nrow == 2 ? launch_mode<double, 2>(mode, a, s) : launch_mode<double, 3>(mode, a, s);
+    if (dbl) {
+        if (nrow == 1) return launch_mode<double, 1>(mode, a, s);
+        return nrow == 2 ? launch_mode<double, 2>(mode, a, s) : launch_mode<double, 3>(mode, a, s);
+    }
+    if (nrow == 1) return launch_mode<float, 1>(mode, a, s);
     return nrow == 2 ? launch_mode<float, 2>(mode, a, s) : launch_mode<float, 3>(mode, a, s);
 }
 

@@ -61,6 +61,10 @@ int dslash_grid(const Geom &g, int block);
 hipError_t launch_dslash(bool dbl, int nrow, int mode, const DslashArgs &a, hipStream_t s);
 
 hipError_t launch_pack_links(const Geom &g, const void *canon, void *dst, bool dbl, int nrow, hipStream_t s);
+// largest entry-wise |rebuilt - canonical| of a packed double precision field, one partial per block
+int check_links_blocks(const Geom &g);
+hipError_t launch_check_links(const Geom &g, const void *canon, const void *packed64, int nrow, double *partial,
+                              hipStream_t s);
 hipError_t launch_pack_vec(const Geom &g, const void *canon, void *dst, bool dbl, hipStream_t s);
 hipError_t launch_unpack_vec(const Geom &g, const void *src, void *canon, bool dbl, hipStream_t s);
 hipError_t launch_tables(const Geom &g, int32_t *nbr, int32_t *coord, int32_t *sign, hipStream_t s);

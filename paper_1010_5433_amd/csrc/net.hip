@@ -669,7 +669,10 @@ hipError_t net_launch_prep(const float2 *theta, NetDev *w, hipStream_t s) {
 hipError_t net_launch_forward(const NetArgs &a, int n_samples, int mix, hipStream_t s) {
     const dim3 g1((a.g.Vh + kNetBlock - 1) / kNetBlock, n_samples), g2((a.g.Vh + kL2Sites - 1) / kL2Sites, n_samples);
     if (mix == kMixFolded) {
-        if (a.nrow == 2) {
+        if (a.nrow == 1) {
+            hipLaunchKernelGGL(k_net_f1<1>, g1, dim3(kNetBlock), 0, s, a);
+            hipLaunchKernelGGL(k_net_f2<1>, g1, dim3(kNetBlock), 0, s, a);
+        } else if (a.nrow == 2) {
             hipLaunchKernelGGL(k_net_f1<2>, g1, dim3(kNetBlock), 0, s, a);
             hipLaunchKernelGGL(k_net_f2<2>, g1, dim3(kNetBlock), 0, s, a);
         } else {
@@ -678,7 +681,11 @@ hipError_t net_launch_forward(const NetArgs &a, int n_samples, int mix, hipStrea
         }
         return hipGetLastError();
     }
-    if (a.nrow == 2) {
+    if (a.nrow == 1) {
+        hipLaunchKernelGGL(k_net_l1<1>, g1, dim3(kNetBlock), 0, s, a);
+        if (mix == kMixBF16) hipLaunchKernelGGL((k_net_l2<1, kMixBF16>), g2, dim3(kNetBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_net_l2<1, kMixFP32>), g2, dim3(kNetBlock), 0, s, a);
+    } else if (a.nrow == 2) {
         hipLaunchKernelGGL(k_net_l1<2>, g1, dim3(kNetBlock), 0, s, a);
         if (mix == kMixBF16) hipLaunchKernelGGL((k_net_l2<2, kMixBF16>), g2, dim3(kNetBlock), 0, s, a);
         else hipLaunchKernelGGL((k_net_l2<2, kMixFP32>), g2, dim3(kNetBlock), 0, s, a);
@@ -698,7 +705,10 @@ int net_part_o() { return kPartO; }
 hipError_t net_launch_backward(const NetArgs &a, int n_samples, const float2 *gin, float2 *g2, float2 *partE,
                                float2 *partO, double2 *grad, hipStream_t s) {
     const dim3 ge(net_blocks_even_bwd(a.g), n_samples), go(net_blocks_odd_bwd(a.g), n_samples);
-    if (a.nrow == 2) {
+    if (a.nrow == 1) {
+        hipLaunchKernelGGL(k_net_bwd_even<1>, ge, dim3(kNetBlock), 0, s, a, gin, g2, partE);
+        hipLaunchKernelGGL(k_net_bwd_odd<1>, go, dim3(kNetBlock), 0, s, a, (const float2 *)g2, partO);
+    } else if (a.nrow == 2) {
         hipLaunchKernelGGL(k_net_bwd_even<2>, ge, dim3(kNetBlock), 0, s, a, gin, g2, partE);
         hipLaunchKernelGGL(k_net_bwd_odd<2>, go, dim3(kNetBlock), 0, s, a, (const float2 *)g2, partO);
     } else {

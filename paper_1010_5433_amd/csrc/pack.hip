@@ -32,6 +32,47 @@ __global__ void __launch_bounds__(kPackBlock) k_pack_links(Geom g, const double2
     LinkLayout<R, NROW>::store(dst, g.Vh, p * 4 + mu, lex >> 1, u);
 }
 
+// Largest entry-wise difference between the canonical links and the links
+// rebuilt from a packed double precision field (one partial per block).
+template <int NROW>
+__global__ void __launch_bounds__(kPackBlock) k_check_links(Geom g, const double2 *canon, const void *packed,
+                                                          double *partial) {
+    const int64_t vol = 2 * (int64_t)g.Vh;
+    const int64_t k = (int64_t)blockIdx.x * kPackBlock + threadIdx.x;
+    double err = 0.0;
+    if (k < 4 * vol) {
+        const int mu = (int)(k / vol);
+        const int64_t lex = k - mu * vol;
+        int64_t r = lex;
+        int x[4];
+        for (int nu = 0; nu < 4; ++nu) {
+            x[nu] = (int)(r % g.L[nu]);
+            r /= g.L[nu];
+        }
+        const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+        const su3<double> u = LinkLayout<double, NROW>::load(packed, g.Vh, p * 4 + mu, lex >> 1);
+        const double2 *src = canon + k * 9;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            const double2 v = src[e];
+            const double d = fmax(fabs(u.e[e / 3][e % 3].re - v.x), fabs(u.e[e / 3][e % 3].im - v.y));
+            err = (d > err || d != d) ? d : err;   // a NaN wins
+        }
+    }
+    // block maximum, NaN-propagating, in a fixed order
+    __shared__ double mx[kPackBlock];
+    mx[threadIdx.x] = err;
+    __syncthreads();
+    for (int h = kPackBlock / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            const double a = mx[threadIdx.x], b = mx[threadIdx.x + h];
+            mx[threadIdx.x] = (b > a || b != b) ? b : a;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = mx[0];
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kPackBlock) k_pack_vec(int vh, const double2 *canon, void *dst) {
     const int i = blockIdx.x * kPackBlock + threadIdx.x;
@@ -79,12 +120,26 @@ hipError_t launch_pack_links(const Geom &g, const void *canon, void *dst, bool d
     const int64_t n = 8 * (int64_t)g.Vh;
     const double2 *c = static_cast<const double2 *>(canon);
     if (dbl) {
-        if (nrow == 2) hipLaunchKernelGGL((k_pack_links<double, 2>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
+        if (nrow == 1) hipLaunchKernelGGL((k_pack_links<double, 1>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
+        else if (nrow == 2) hipLaunchKernelGGL((k_pack_links<double, 2>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
         else hipLaunchKernelGGL((k_pack_links<double, 3>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
     } else {
-        if (nrow == 2) hipLaunchKernelGGL((k_pack_links<float, 2>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
+        if (nrow == 1) hipLaunchKernelGGL((k_pack_links<float, 1>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
+        else if (nrow == 2) hipLaunchKernelGGL((k_pack_links<float, 2>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
         else hipLaunchKernelGGL((k_pack_links<float, 3>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
     }
+    return hipGetLastError();
+}
+
+int check_links_blocks(const Geom &g) { return (int)blocks_for(8 * (int64_t)g.Vh); }
+
+hipError_t launch_check_links(const Geom &g, const void *canon, const void *packed64, int nrow, double *partial,
+                              hipStream_t s) {
+    const int64_t n = 8 * (int64_t)g.Vh;
+    const double2 *c = static_cast<const double2 *>(canon);
+    if (nrow == 1) hipLaunchKernelGGL(k_check_links<1>, dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, packed64, partial);
+    else if (nrow == 2) hipLaunchKernelGGL(k_check_links<2>, dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, packed64, partial);
+    else hipLaunchKernelGGL(k_check_links<3>, dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, packed64, partial);
     return hipGetLastError();
 }
 

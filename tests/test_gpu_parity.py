@@ -9,6 +9,8 @@ solver):
     ||gpu - orc|| / ||orc|| <= 1e-14.
   * FP32 half Dslash vs the FP64 oracle: inputs and links rounded to single
     (2^-24 relative each) plus ~8 rounded terms: <= 3e-7 norm-relative.
+  * 8-real links: the rebuild (phases, two square roots, one reciprocal) adds
+    a few ulp per entry; the same bounds hold.
   * solvers: the FP64 true relative residual of every shift, computed by the
     ORACLE's operator on the GPU's solution, <= 1e-10 (the requested tol);
     solutions agree with the oracle's within kappa_i * 2e-10.
@@ -48,7 +50,7 @@ def test_tables_bit_exact(orc, dims, antiperiodic):
 
 
 @pytest.mark.parametrize("dims", SMALL + FULL)
-@pytest.mark.parametrize("fmt", ["18", "12"])
+@pytest.mark.parametrize("fmt", ["18", "12", "8"])
 def test_dslash_f64(orc, dims, fmt):
     log(f"dslash f64 {dims} fmt={fmt}")
     U = links_np(dims, "haar" if np.prod(dims) < 4096 else "smooth", 0.5, 11)
@@ -63,7 +65,7 @@ def test_dslash_f64(orc, dims, fmt):
 
 
 @pytest.mark.parametrize("dims", SMALL + FULL)
-@pytest.mark.parametrize("fmt", ["18", "12"])
+@pytest.mark.parametrize("fmt", ["18", "12", "8"])
 def test_dslash_f32(orc, dims, fmt):
     log(f"dslash f32 {dims} fmt={fmt}")
     U = links_np(dims, "haar" if np.prod(dims) < 4096 else "smooth", 0.5, 11)
@@ -97,7 +99,7 @@ def test_free_field_plane_wave_on_gpu(dims):
 
 
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 8), (32, 32, 32, 8)])
-@pytest.mark.parametrize("fmt", ["18", "12"])
+@pytest.mark.parametrize("fmt", ["18", "12", "8"])
 def test_normal_op(orc, dims, fmt):
     log(f"normal op {dims} fmt={fmt}")
     U = links_np(dims, "smooth", 0.5, 3)
@@ -265,6 +267,36 @@ def test_mixed_reliable_updates_below_single_floor(orc, dims, mass, seed):
     assert st["resid_unrefined"][0] <= 3e-10          # the base shift (smallest), before refinement
     for i, s in enumerate(shifts):
         assert orc.true_residual(dims, U, mass, s, b, xs[i]) <= 1e-10
+
+
+def test_links8_rejects_unit_links():
+    """The 8-real form cannot hold links with U01 = U02 = 0 (the unit matrix
+    of the free field): stag_links_set refuses them and leaves no links."""
+    import paper_1010_5433_amd as stag
+    dims = (4, 4, 4, 4)
+    lat = stag.Lattice(dims)
+    with pytest.raises(stag.StagError):
+        lat.set_links(to_dev(ln.free_links(dims)), "8")
+    with pytest.raises(stag.StagError):     # no links were kept
+        lat.dslash_eo(0, pack(lat, np.ones((lat.Vh, 3), complex)))
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_multishift_config3_8real_links(orc, prec):
+    """The 32^4 solve with 8-real links: every shift at FP64 true residual
+    <= 1e-10 by the oracle's (exact) operator."""
+    c = syn.config("c3_32x32x32x32_smooth")
+    log(f"multishift config 3 (32^4), 8-real links, prec={prec}")
+    U = links_np(c["dims"], "smooth", c["links"][1], c["links"][2])
+    b = syn.gaussian_source(c["dims"], c["source_seed"])
+    shifts = syn.logspace_shifts(*c["shifts"])
+    lat = lattice_with_links(c["dims"], U, "8")
+    xs, rc, st = _solve(lat, c["mass"], shifts, b, prec=prec)
+    log(f"  iters {st['iters']} refine {st['refine_iters']} seconds {st['seconds']:.3f}")
+    assert rc == 0
+    for i in (0, 7, 15):
+        r = orc.true_residual(c["dims"], U, c["mass"], shifts[i], b, xs[i])
+        assert r <= 1e-10, (i, r)
 
 
 def test_single_cg_from_guess(orc):
