@@ -169,6 +169,7 @@ def batched_experiment(args):
 def learned_experiment(args, n_test_fields):
     """Train the gauge-equivariant preconditioner on 16^4 fields and judge it
     in flexible CG on held-out 32^4 fields against plain FP64 CG."""
+    fmt = args.learned_fmt or args.fmt
     import numpy as np
     import torch
 
@@ -210,7 +211,7 @@ def learned_experiment(args, n_test_fields):
     for k, seed in enumerate(c["test_link_seeds"][:n_test_fields]):
         U = syn.smooth_links(c["test_dims"], c["eps"], seed)
         lat = stag.Lattice(c["test_dims"])
-        lat.set_links(torch.from_numpy(U).cuda(), "12")   # the network kernels are tuned for 12-real links
+        lat.set_links(torch.from_numpy(U).cuda(), fmt)
         b = syn.gaussian_source(c["test_dims"], c["test_source_seed"] + k)
         src = lat.pack(torch.from_numpy(b).cuda())
         learn.compare(lat, net, mass, src, tol=tol)          # warm-up
@@ -224,7 +225,7 @@ def learned_experiment(args, n_test_fields):
                                                for k2, v in res[n].items() if k2 != "status"}))
         del lat
     gains = {}
-    for mode in ("bf16", "folded"):
+    for mode in ("bf16", "folded", "folded_bf16"):
         gains[mode] = dict(
             iteration_gain=round(float(np.mean([e["plain_iters"] / e[f"{mode}_iters"] for e in evals])), 3),
             tts_gain=round(float(np.mean([e["plain_seconds"] / e[f"{mode}_seconds"] for e in evals])), 3))
@@ -232,7 +233,7 @@ def learned_experiment(args, n_test_fields):
                            steps=args.train_steps, batch=args.batch, lr=args.lr, mode="bf16",
                            seconds=round(t_train, 2), data_seconds=round(t_data, 2),
                            loss_first=round(losses[0], 5), loss_last=round(float(np.mean(losses[-20:])), 5)),
-                test=dict(dims=list(c["test_dims"]), mass=mass, shift=0.0, tol=tol, links="12-real",
+                test=dict(dims=list(c["test_dims"]), mass=mass, shift=0.0, tol=tol, links=f"{fmt}-real",
                           fields=evals),
                 gains=gains)
 
@@ -263,6 +264,8 @@ def main():
     ap.add_argument("--train-pairs", type=int, default=0)
     ap.add_argument("--pairs", default="mx", choices=["mx", "solve"])
     ap.add_argument("--test-fields", type=int, default=4, help="held-out fields of --learned-only")
+    ap.add_argument("--learned-fmt", default=None, choices=["18", "12", "8"],
+                    help="link storage of the held-out fields of the learned experiment (default: --fmt)")
     args = ap.parse_args()
 
     if args.gpus != 1:

@@ -248,6 +248,12 @@ stag_status stag_batch_last_config(int *block, int *rpt);
  *           s = sum_c v_c w1s[c],  A[d][d'] = sum_c v_{8+8d+c} w1h[c][d'];
  *         evaluated in FP32, layer 2 then gathers one colour vector per hop
  *         instead of eight.  Forward only (stag_net_apply, stag_fcg_solve).
+ * mode 3: the folded form reading a bfloat16 copy of the links (12 reals,
+ *         third row rebuilt; made from the single precision field on first
+ *         use, kept with the lattice until its links are replaced) and
+ *         storing psi_d in bfloat16; arithmetic in FP32.  Entries of P r
+ *         carry relative errors of order 1e-2, which the flexible CG
+ *         absorbs.  Forward only.
  * The backward pass is FP32 in modes 0 and 1; gradients are summed in a
  * fixed order (deterministic). */
 typedef struct stag_net stag_net;
@@ -281,7 +287,7 @@ stag_status stag_net_train_step(stag_net *net, stag_lattice *lat, const void *b,
 
 /* Flexible CG with P as preconditioner (Polak-Ribiere beta) for
  * (M + shift) x = src from the x passed in (STAG_F64 library vectors; sol
- * is read and overwritten).  The network is evaluated in `mode` (0, 1 or 2)
+ * is read and overwritten).  The network is evaluated in `mode` (0 to 3)
  * on a single precision copy of the residual; everything else is double
  * precision.  net == NULL runs plain double precision CG.  The residual is
  * re-computed in double precision from x whenever the iterated one reaches

@@ -16,7 +16,7 @@ import os
 
 import torch
 
-from ._abi import (F32, F64, MIXED, LINK8, LINK12, LINK18, MIX_BF16, MIX_FOLDED, MIX_FP32, NET_NPARAM, CgStats, StagError,
+from ._abi import (F32, F64, MIXED, LINK8, LINK12, LINK18, MIX_BF16, MIX_FOLDED, MIX_FOLDED_BF16, MIX_FP32, NET_NPARAM, CgStats, StagError,
                    System, batch_flags, load_library, status_name)
 
 __all__ = ["Lattice", "CgStats", "StagError", "F64", "F32", "MIXED", "LINK18", "LINK12",
@@ -157,7 +157,7 @@ class Lattice:
                   max_iter=100000):
         """Flexible CG for (M + shift) x = src preconditioned by `net` (a Net, or
         None for plain double precision CG) evaluated in `mode` ("bf16",
-        "fp32" or "folded"), from the given x (overwritten)."""
+        "fp32", "folded" or "folded_bf16"), from the given x (overwritten)."""
         st = CgStats()
         rc = _check(_L.stag_fcg_solve(self._h, float(mass), float(shift), _ptr(src), _ptr(x),
                                       net._h if net is not None else None, _MIX.get(mode, mode), float(tol),
@@ -165,7 +165,7 @@ class Lattice:
         return x, rc, st.to_dict(1)
 
 
-_MIX = {"bf16": MIX_BF16, "fp32": MIX_FP32, "folded": MIX_FOLDED}
+_MIX = {"bf16": MIX_BF16, "fp32": MIX_FP32, "folded": MIX_FOLDED, "folded_bf16": MIX_FOLDED_BF16}
 
 
 class Net:

@@ -11,7 +11,7 @@ F64, F32, MIXED = 0, 1, 2
 LINK18, LINK12, LINK8 = 0, 1, 2
 MAX_SHIFTS = 64
 NET_NPARAM = 656
-MIX_BF16, MIX_FP32, MIX_FOLDED = 0, 1, 2
+MIX_BF16, MIX_FP32, MIX_FOLDED, MIX_FOLDED_BF16 = 0, 1, 2, 3
 
 _NAMES = {0: "STAG_OK", 1: "STAG_ENOCONV", 2: "STAG_EBREAKDOWN", -1: "STAG_EINVAL",
           -2: "STAG_ENOMEM", -3: "STAG_EHIP"}

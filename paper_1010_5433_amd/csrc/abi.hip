@@ -103,6 +103,7 @@ stag_status stag_lattice_destroy(stag_lattice *lat) {
     (void)hipDeviceSynchronize();
     (void)hipFree(lat->links64);
     (void)hipFree(lat->links32);
+    (void)hipFree(lat->links16);
     for (int k = 0; k < WS_NSLOTS; ++k) (void)hipFree(lat->ws[k]);
     (void)hipHostFree(lat->host_flags);
     delete lat;
@@ -124,7 +125,8 @@ stag_status stag_links_set(stag_lattice *lat, const void *links, stag_link_fmt f
     STAG_HIP(hipStreamSynchronize(s));
     if (lat->links64) STAG_HIP(hipFree(lat->links64));
     if (lat->links32) STAG_HIP(hipFree(lat->links32));
-    lat->links64 = lat->links32 = nullptr;
+    if (lat->links16) STAG_HIP(hipFree(lat->links16));
+    lat->links64 = lat->links32 = lat->links16 = nullptr;
     lat->nrow = 0;
     STAG_HIP(hipMalloc(&lat->links64, link_field_bytes(true, nrow, lat->Vh)));
     STAG_HIP(hipMalloc(&lat->links32, link_field_bytes(false, nrow, lat->Vh)));

@@ -244,6 +244,7 @@ stag_status fcg_solve(stag_lattice *lat, double mass, double shift, const void *
         if (stats) *stats = st;
         return STAG_OK;
     }
+    STAG_TRY(net_prepare_links(lat, mode, s));
     const int64_t ne = 3 * lat->Vh;
     const size_t vb = sizeof(double2) * ne;
     const int ds_grid = dslash_grid(lat->g, kDslashBlock);

@@ -61,6 +61,8 @@ int dslash_grid(const Geom &g, int block);
 hipError_t launch_dslash(bool dbl, int nrow, int mode, const DslashArgs &a, hipStream_t s);
 
 hipError_t launch_pack_links(const Geom &g, const void *canon, void *dst, bool dbl, int nrow, hipStream_t s);
+// bfloat16 12-real copy from a packed single precision field of any format
+hipError_t launch_pack_links16(const Geom &g, const void *links32, int nrow, void *dst, hipStream_t s);
 // largest entry-wise |rebuilt - canonical| of a packed double precision field, one partial per block
 int check_links_blocks(const Geom &g);
 hipError_t launch_check_links(const Geom &g, const void *canon, const void *packed64, int nrow, double *partial,
@@ -97,6 +99,7 @@ struct stag_lattice {
     int nrow;            // rows stored per link (3 or 2), 0 before stag_links_set
     void *links64;
     void *links32;
+    void *links16;       // bfloat16 12-real copy for the learned preconditioner (packed on first use)
     void *ws[WS_NSLOTS];
     size_t ws_bytes[WS_NSLOTS];
     int *host_flags;     // pinned host mirror of solver flags

@@ -242,6 +242,44 @@ template <> struct LinkLayout<float, 1> {
     }
 };
 
+// Low-precision copy for the learned preconditioner: 12 reals in bfloat16,
+// 3 planes of 4 bf16 (8 bytes) per site: {u00, u01}, {u02, u10}, {u11, u12};
+// the third row is rebuilt in single precision.
+struct BF16Link {};
+template <> struct LinkLayout<BF16Link, 2> {
+    static constexpr int64_t kBytesPerLink = 24;
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    __device__ static __forceinline__ su3<float> load(const void *base, int64_t vh, int blk, int64_t i) {
+        const bf16x4 *q = reinterpret_cast<const bf16x4 *>(static_cast<const char *>(base) + (int64_t)blk * kBytesPerLink * vh);
+        su3<float> u;
+        bf16x4 v = q[0 * vh + i];
+        u.e[0][0] = {float(v[0]), float(v[1])};
+        u.e[0][1] = {float(v[2]), float(v[3])};
+        v = q[1 * vh + i];
+        u.e[0][2] = {float(v[0]), float(v[1])};
+        u.e[1][0] = {float(v[2]), float(v[3])};
+        v = q[2 * vh + i];
+        u.e[1][1] = {float(v[0]), float(v[1])};
+        u.e[1][2] = {float(v[2]), float(v[3])};
+        su3_rebuild_row2(u);
+        return u;
+    }
+    __device__ static __forceinline__ void store(void *base, int64_t vh, int blk, int64_t i, const su3<float> &u) {
+        bf16x4 *q = reinterpret_cast<bf16x4 *>(static_cast<char *>(base) + (int64_t)blk * kBytesPerLink * vh);
+        auto pk = [](cplx<float> a, cplx<float> b) {
+            bf16x4 v;
+            v[0] = static_cast<__bf16>(a.re);
+            v[1] = static_cast<__bf16>(a.im);
+            v[2] = static_cast<__bf16>(b.re);
+            v[3] = static_cast<__bf16>(b.im);
+            return v;
+        };
+        q[0 * vh + i] = pk(u.e[0][0], u.e[0][1]);
+        q[1 * vh + i] = pk(u.e[0][2], u.e[1][0]);
+        q[2 * vh + i] = pk(u.e[1][1], u.e[1][2]);
+    }
+};
+
 // Bytes of one packed link field (both parities, 4 directions).
 inline int64_t link_field_bytes(bool dbl, int nrow, int64_t vh) {
     int64_t per;

@@ -14,8 +14,12 @@ constexpr int kNetK = 72;                // layer-2 inputs per channel: self (8)
 constexpr int kNetW1S = 0, kNetW1H = 8, kNetW2 = 72, kNetWout = 648, kNetNParam = 656;
 
 // Evaluation modes: the layer-2 channel mixing in BF16 on the matrix cores,
-// the same in FP32 on the vector ALU, or the folded two-hop form (FP32).
-enum NetMix { kMixBF16 = 0, kMixFP32 = 1, kMixFolded = 2 };
+// the same in FP32 on the vector ALU, the folded two-hop form (FP32), or the
+// folded form reading bfloat16 links and storing its intermediate field in
+// bfloat16 (FP32 arithmetic).
+enum NetMix { kMixBF16 = 0, kMixFP32 = 1, kMixFolded = 2, kMixFoldedBF16 = 3 };
+inline bool net_mode_ok(int m) { return m >= kMixBF16 && m <= kMixFoldedBF16; }
+inline bool net_mode_folded(int m) { return m == kMixFolded || m == kMixFoldedBF16; }
 
 // Weights in the forms the kernels read.
 struct NetDev {
@@ -35,6 +39,7 @@ struct NetArgs {
     Geom g;
     const void *links;      // packed single precision links of the lattice
     int nrow;
+    const void *links16;    // bfloat16 12-real copy (folded bfloat16 mode only)
     const NetDev *w;
     const float2 *r;        // input  (samples x [3][V/2]) even sites
     float2 *out;            // output (samples x [3][V/2]) even sites
@@ -60,6 +65,8 @@ stag_status net_work(stag_net *net, const stag_lattice *lat, int n, NetBufs *b);
 NetArgs net_args(const stag_net *net, const stag_lattice *lat, const void *r, float2 *out, const NetBufs &b,
                  bool keep_phi2);
 hipError_t net_launch_prep(const float2 *theta, NetDev *w, hipStream_t s);
+// Makes the bfloat16 link copy that mode kMixFoldedBF16 reads (once per link field).
+stag_status net_prepare_links(stag_lattice *lat, int mode, hipStream_t s);
 hipError_t net_launch_forward(const NetArgs &a, int n_samples, int mix, hipStream_t s);
 }  // namespace stag
 

@@ -60,18 +60,19 @@ __device__ __forceinline__ void transport(const su3<float> &u, float s, bool fwd
     }
 }
 
-// Link, sign and neighbour eo index of hop d taken at site i (coords x) of parity p.
-template <int NROW>
+// Link, sign and neighbour eo index of hop d taken at site i (coords x) of parity p
+// (LT = float: packed single precision links; BF16Link: the bfloat16 copy).
+template <int NROW, typename LT = float>
 __device__ __forceinline__ int hop_setup(const Geom &g, const void *links, int p, int i, const int x[4], int d,
                                          su3<float> &u, float &s) {
     const int mu = d & 3;
     if (d < 4) {
-        u = LinkLayout<float, NROW>::load(links, g.Vh, p * 4 + mu, i);
+        u = LinkLayout<LT, NROW>::load(links, g.Vh, p * 4 + mu, i);
         s = float(fwd_sign(g, x, mu));
         return site_nbr(g, i, x, mu, +1);
     }
     const int j = site_nbr(g, i, x, mu, -1);
-    u = LinkLayout<float, NROW>::load(links, g.Vh, (1 - p) * 4 + mu, j);
+    u = LinkLayout<LT, NROW>::load(links, g.Vh, (1 - p) * 4 + mu, j);
     s = float(bwd_sign(g, x, mu));
     return j;
 }
@@ -202,7 +203,32 @@ __global__ void __launch_bounds__(kNetBlock) k_net_l1(NetArgs a) {
 
 // ---------------------------------------------------------------- folded form
 // odd sites: psi_d = sum_d' A[d][d'] T_d' r, stored as 24 planes [d][colour][V/2]
-template <int NROW>
+// (LOWP: links from the bfloat16 copy, psi stored as bfloat16 pairs, so the
+// planes take 4 instead of 8 bytes per entry; arithmetic stays FP32).
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+template <bool LOWP>
+__device__ __forceinline__ void psi_store(float2 *base, size_t k, float2 v) {
+    if constexpr (LOWP) {
+        bf16x2 w;
+        w[0] = static_cast<__bf16>(v.x);
+        w[1] = static_cast<__bf16>(v.y);
+        reinterpret_cast<bf16x2 *>(base)[k] = w;
+    } else {
+        base[k] = v;
+    }
+}
+template <bool LOWP>
+__device__ __forceinline__ float2 psi_load(const float2 *base, size_t k) {
+    if constexpr (LOWP) {
+        const bf16x2 w = reinterpret_cast<const bf16x2 *>(base)[k];
+        return make_float2(float(w[0]), float(w[1]));
+    } else {
+        return base[k];
+    }
+}
+
+template <int NROW, bool LOWP>
 __global__ void __launch_bounds__(kNetBlock) k_net_f1(NetArgs a) {
     __shared__ float2 sA[64];   // the 8 x 8 mixing, read by every lane at the same address
     if (a.skip && *a.skip) return;
@@ -221,7 +247,8 @@ __global__ void __launch_bounds__(kNetBlock) k_net_f1(NetArgs a) {
     for (int d = 0; d < 8; ++d) {
         su3<float> u;
         float sg;
-        const int j = hop_setup<NROW>(g, a.links, 1, i, x, d, u, sg);
+        const int j = LOWP ? hop_setup<2, BF16Link>(g, a.links16, 1, i, x, d, u, sg)
+                           : hop_setup<NROW>(g, a.links, 1, i, x, d, u, sg);
         float2 v[3];
 #pragma unroll
         for (int b = 0; b < 3; ++b) v[b] = r[(size_t)b * g.Vh + j];
@@ -234,12 +261,12 @@ __global__ void __launch_bounds__(kNetBlock) k_net_f1(NetArgs a) {
             float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
             for (int dp = 0; dp < 8; ++dp) acc = caddf(acc, cmulf(sA[8 * d + dp], h[dp][b]));
-            psi[(size_t)(d * 3 + b) * g.Vh + i] = acc;
+            psi_store<LOWP>(psi, (size_t)(d * 3 + b) * g.Vh + i, acc);
         }
 }
 
 // even sites: P r = s r + sum_d T_d psi_d (one colour vector per hop)
-template <int NROW>
+template <int NROW, bool LOWP>
 __global__ void __launch_bounds__(kNetBlock) k_net_f2(NetArgs a) {
     if (a.skip && *a.skip) return;
     const Geom &g = a.g;
@@ -259,10 +286,11 @@ __global__ void __launch_bounds__(kNetBlock) k_net_f2(NetArgs a) {
     for (int d = 0; d < 8; ++d) {
         su3<float> u;
         float sg;
-        const int j = hop_setup<NROW>(g, a.links, 0, i, x, d, u, sg);
+        const int j = LOWP ? hop_setup<2, BF16Link>(g, a.links16, 0, i, x, d, u, sg)
+                           : hop_setup<NROW>(g, a.links, 0, i, x, d, u, sg);
         float2 v[3], h[3];
 #pragma unroll
-        for (int b = 0; b < 3; ++b) v[b] = psi[(size_t)(d * 3 + b) * g.Vh + j];
+        for (int b = 0; b < 3; ++b) v[b] = psi_load<LOWP>(psi, (size_t)(d * 3 + b) * g.Vh + j);
         transport(u, sg, d < 4, v, h);
 #pragma unroll
         for (int b = 0; b < 3; ++b) acc[b] = caddf(acc[b], h[b]);
@@ -668,16 +696,22 @@ hipError_t net_launch_prep(const float2 *theta, NetDev *w, hipStream_t s) {
 
 hipError_t net_launch_forward(const NetArgs &a, int n_samples, int mix, hipStream_t s) {
     const dim3 g1((a.g.Vh + kNetBlock - 1) / kNetBlock, n_samples), g2((a.g.Vh + kL2Sites - 1) / kL2Sites, n_samples);
+    if (mix == kMixFoldedBF16) {
+        if (!a.links16) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_net_f1<2, true>), g1, dim3(kNetBlock), 0, s, a);
+        hipLaunchKernelGGL((k_net_f2<2, true>), g1, dim3(kNetBlock), 0, s, a);
+        return hipGetLastError();
+    }
     if (mix == kMixFolded) {
         if (a.nrow == 1) {
-            hipLaunchKernelGGL(k_net_f1<1>, g1, dim3(kNetBlock), 0, s, a);
-            hipLaunchKernelGGL(k_net_f2<1>, g1, dim3(kNetBlock), 0, s, a);
+            hipLaunchKernelGGL((k_net_f1<1, false>), g1, dim3(kNetBlock), 0, s, a);
+            hipLaunchKernelGGL((k_net_f2<1, false>), g1, dim3(kNetBlock), 0, s, a);
         } else if (a.nrow == 2) {
-            hipLaunchKernelGGL(k_net_f1<2>, g1, dim3(kNetBlock), 0, s, a);
-            hipLaunchKernelGGL(k_net_f2<2>, g1, dim3(kNetBlock), 0, s, a);
+            hipLaunchKernelGGL((k_net_f1<2, false>), g1, dim3(kNetBlock), 0, s, a);
+            hipLaunchKernelGGL((k_net_f2<2, false>), g1, dim3(kNetBlock), 0, s, a);
         } else {
-            hipLaunchKernelGGL(k_net_f1<3>, g1, dim3(kNetBlock), 0, s, a);
-            hipLaunchKernelGGL(k_net_f2<3>, g1, dim3(kNetBlock), 0, s, a);
+            hipLaunchKernelGGL((k_net_f1<3, false>), g1, dim3(kNetBlock), 0, s, a);
+            hipLaunchKernelGGL((k_net_f2<3, false>), g1, dim3(kNetBlock), 0, s, a);
         }
         return hipGetLastError();
     }

@@ -10,6 +10,7 @@
 
 #include "common.h"
 #include "internal.h"
+#include "links.h"
 #include "net.h"
 #include "solver.h"
 
@@ -78,6 +79,7 @@ NetArgs net_args(const stag_net *net, const stag_lattice *lat, const void *r, fl
     a.g = lat->g;
     a.links = lat->links32;
     a.nrow = lat->nrow;
+    a.links16 = lat->links16;
     a.w = net->w;
     a.r = static_cast<const float2 *>(r);
     a.out = out;
@@ -85,6 +87,18 @@ NetArgs net_args(const stag_net *net, const stag_lattice *lat, const void *r, fl
     a.phi2 = keep_phi2 ? b.phi2 : nullptr;
     a.vstride = 3 * lat->Vh;
     return a;
+}
+
+stag_status net_prepare_links(stag_lattice *lat, int mode, hipStream_t s) {
+    if (mode != kMixFoldedBF16 || lat->links16) return STAG_OK;
+    STAG_HIP(hipMalloc(&lat->links16, (size_t)8 * lat->Vh * LinkLayout<BF16Link, 2>::kBytesPerLink));
+    const hipError_t e = launch_pack_links16(lat->g, lat->links32, lat->nrow, lat->links16, s);
+    if (e != hipSuccess) {
+        (void)hipFree(lat->links16);
+        lat->links16 = nullptr;
+        STAG_HIP(e);
+    }
+    return STAG_OK;
 }
 
 }  // namespace stag
@@ -151,11 +165,12 @@ stag_status stag_net_get_params(const stag_net *net, double *theta) {
     return STAG_OK;
 }
 
+static const char *kModeError = "mode must be 0 (BF16 matrix cores), 1 (FP32), 2 (folded) or 3 (folded, bfloat16 links)";
+
 static stag_status check_net_lat(const stag_net *net, const stag_lattice *lat, int mode) {
     if (!net || !lat) return invalid("null handle");
     if (!lat->nrow) return invalid("links not set");
-    if (mode != kMixBF16 && mode != kMixFP32 && mode != kMixFolded)
-        return invalid("mode must be 0 (BF16 matrix cores), 1 (FP32) or 2 (folded)");
+    if (!net_mode_ok(mode)) return invalid(kModeError);
     return STAG_OK;
 }
 
@@ -165,6 +180,7 @@ stag_status stag_net_apply(stag_net *net, stag_lattice *lat, const void *r, void
     hipStream_t s = static_cast<hipStream_t>(stream);
     NetBufs b;
     STAG_TRY(net_work(net, lat, 1, &b));
+    STAG_TRY(net_prepare_links(lat, mode, s));
     STAG_HIP(net_launch_prep(net->theta, net->w, s));
     NetArgs a = net_args(net, lat, r, static_cast<float2 *>(out), b, false);
     STAG_HIP(net_launch_forward(a, 1, mode, s));
@@ -174,7 +190,7 @@ stag_status stag_net_apply(stag_net *net, stag_lattice *lat, const void *r, void
 stag_status stag_net_grad(stag_net *net, stag_lattice *lat, const void *r, const void *g, double *grad, int mode,
                           void *stream) {
     STAG_TRY(check_net_lat(net, lat, mode));
-    if (mode == kMixFolded) return invalid("gradients need the layered form (mode 0 or 1)");
+    if (net_mode_folded(mode)) return invalid("gradients need the layered form (mode 0 or 1)");
     if (!r || !g || !grad) return invalid("null argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
     NetBufs b;
@@ -196,7 +212,7 @@ stag_status stag_net_grad(stag_net *net, stag_lattice *lat, const void *r, const
 stag_status stag_net_train_step(stag_net *net, stag_lattice *lat, const void *b, const void *x, int n, double lr,
                                 int mode, double *loss, void *stream) {
     STAG_TRY(check_net_lat(net, lat, mode));
-    if (mode == kMixFolded) return invalid("training needs the layered form (mode 0 or 1)");
+    if (net_mode_folded(mode)) return invalid("training needs the layered form (mode 0 or 1)");
     if (!b || !x || n < 1 || n > 1024) return invalid("bad batch");
     if (!(lr > 0) || !std::isfinite(lr)) return invalid("lr must be > 0");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -222,8 +238,7 @@ stag_status stag_fcg_solve(stag_lattice *lat, double mass, double shift, const v
     if (!lat || !lat->nrow) return invalid("lattice with links required");
     if (!src || !sol || src == sol) return invalid("bad vector");
     if (!(mass > 0) || !(shift >= 0) || !(tol > 0) || max_iter < 1) return invalid("bad solver parameter");
-    if (net && mode != kMixBF16 && mode != kMixFP32 && mode != kMixFolded)
-        return invalid("mode must be 0 (BF16 matrix cores), 1 (FP32) or 2 (folded)");
+    if (net && !net_mode_ok(mode)) return invalid(kModeError);
     return fcg_solve(lat, mass, shift, src, sol, net, mode, tol, max_iter, stats, static_cast<hipStream_t>(stream));
 }
 

@@ -73,6 +73,17 @@ __global__ void __launch_bounds__(kPackBlock) k_check_links(Geom g, const double
     if (threadIdx.x == 0) partial[blockIdx.x] = mx[0];
 }
 
+// bfloat16 12-real copy of a packed single precision field (any format).
+template <int NROW>
+__global__ void __launch_bounds__(kPackBlock) k_pack_links16(int vh, const void *src, void *dst) {
+    const int64_t k = (int64_t)blockIdx.x * kPackBlock + threadIdx.x;
+    if (k >= 8 * (int64_t)vh) return;
+    const int blk = (int)(k / vh);
+    const int64_t i = k - (int64_t)blk * vh;
+    const su3<float> u = LinkLayout<float, NROW>::load(src, vh, blk, i);
+    LinkLayout<BF16Link, 2>::store(dst, vh, blk, i, u);
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kPackBlock) k_pack_vec(int vh, const double2 *canon, void *dst) {
     const int i = blockIdx.x * kPackBlock + threadIdx.x;
@@ -128,6 +139,14 @@ hipError_t launch_pack_links(const Geom &g, const void *canon, void *dst, bool d
         else if (nrow == 2) hipLaunchKernelGGL((k_pack_links<float, 2>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
         else hipLaunchKernelGGL((k_pack_links<float, 3>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_links16(const Geom &g, const void *links32, int nrow, void *dst, hipStream_t s) {
+    const int64_t n = 8 * (int64_t)g.Vh;
+    if (nrow == 1) hipLaunchKernelGGL(k_pack_links16<1>, dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g.Vh, links32, dst);
+    else if (nrow == 2) hipLaunchKernelGGL(k_pack_links16<2>, dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g.Vh, links32, dst);
+    else hipLaunchKernelGGL(k_pack_links16<3>, dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g.Vh, links32, dst);
     return hipGetLastError();
 }
 

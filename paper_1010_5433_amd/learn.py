@@ -88,7 +88,7 @@ def train(net: Net, data, steps: int, batch: int, lr: float, mode="bf16", seed: 
 
 
 def compare(lat: Lattice, net: Net, mass: float, src: torch.Tensor, shift=0.0, tol=1e-10, max_iter=100000,
-            modes=("bf16", "folded")):
+            modes=("bf16", "folded", "folded_bf16")):
     """Plain double precision CG against flexible CG with the network in
     each of `modes`, all from x = 0 on the same source: iterations, time and
     true residuals."""

@@ -12,6 +12,10 @@ Tolerances:
     BF16 layer-2 values; the other blocks stay at the FP32 bound.
   * Folded mode: an exact rewrite of the same linear map evaluated in FP32
     (fewer operations than the layered form): bound 1e-5.
+  * Folded mode with bfloat16 links and intermediate field: every link entry
+    and every psi entry is rounded once to bfloat16 (2^-9 relative), the
+    third link row is rebuilt from two rounded rows, and each output sums
+    two hops of such terms: ~3e-3 norm-relative, bound 1e-2.
   * Flexible CG: the FP64 true residual of the result <= tol (1e-10),
     checked with the oracle's operator.
 """
@@ -86,6 +90,41 @@ def test_net_forward_folded_vs_oracle(orc, dims, kind, fmt):
     net = stag.Net(th)
     got = unpack(lat, net.apply(lat, pack(lat, r, "f32"), mode="folded"))
     assert rel(got, orc.net_forward(dims, U, th, r)) <= 1e-5
+
+
+@pytest.mark.parametrize("dims,kind,fmt", CASES + [((4, 4, 2, 6), "smooth", "8")])
+def test_net_forward_folded_bf16_vs_oracle(orc, dims, kind, fmt):
+    """Folded form on bfloat16 links with a bfloat16 intermediate field
+    against the layered network (oracle); errors spread over all sites."""
+    import paper_1010_5433_amd as stag
+    log(f"net forward folded_bf16 {dims} {kind} fmt={fmt}")
+    U, lat = _setup(dims, kind, fmt)
+    th = rand_theta(15)
+    r = syn.gaussian_source(dims, 16)
+    net = stag.Net(th)
+    got = unpack(lat, net.apply(lat, pack(lat, r, "f32"), mode="folded_bf16"))
+    want = orc.net_forward(dims, U, th, r)
+    e = rel(got, want)
+    log(f"  folded_bf16 rel {e:.2e}")
+    assert 1e-5 < e <= 1e-2          # rounded (not the FP32 path) and close
+    per_site = np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1).mean()
+    assert per_site.max() <= 5e-2
+
+
+def test_net_folded_bf16_follows_new_links(orc):
+    """The bfloat16 link copy is made on first use; replacing the links
+    must replace it too."""
+    import paper_1010_5433_amd as stag
+    dims = (4, 4, 4, 4)
+    U1, lat = _setup(dims, "smooth", "12", seed=41)
+    U2 = links_np(dims, "haar", 0.5, 42)
+    th = rand_theta(17)
+    r = syn.gaussian_source(dims, 18)
+    net = stag.Net(th)
+    r32 = pack(lat, r, "f32")
+    assert rel(unpack(lat, net.apply(lat, r32, mode="folded_bf16")), orc.net_forward(dims, U1, th, r)) <= 1e-2
+    lat.set_links(to_dev(U2), "18")
+    assert rel(unpack(lat, net.apply(lat, r32, mode="folded_bf16")), orc.net_forward(dims, U2, th, r)) <= 1e-2
 
 
 @pytest.mark.parametrize("dims,kind,fmt", CASES)
@@ -168,10 +207,10 @@ def test_net_gauge_equivariant_on_gpu():
     net = stag.Net(rand_theta(10))
     lat, latg = lattice_with_links(dims, U, "18"), lattice_with_links(dims, Ug, "18")
     rg = np.einsum("nij,nj->ni", omega[ev], r)
-    for mode in ("fp32", "bf16", "folded"):
+    for mode in ("fp32", "bf16", "folded", "folded_bf16"):
         lhs = unpack(latg, net.apply(latg, pack(latg, rg, "f32"), mode=mode))
         rhs = np.einsum("nij,nj->ni", omega[ev], unpack(lat, net.apply(lat, pack(lat, r, "f32"), mode=mode)))
-        assert rel(lhs, rhs) <= (2e-2 if mode == "bf16" else 1e-5)
+        assert rel(lhs, rhs) <= (2e-2 if "bf16" in mode else 1e-5)
 
 
 def test_net_params_roundtrip_and_validation():
@@ -189,6 +228,8 @@ def test_net_params_roundtrip_and_validation():
         net.apply(lat, r32, mode=7)
     with pytest.raises(stag.StagError):
         net.grad(lat, r32, r32, mode="folded")     # gradients need the layered form
+    with pytest.raises(stag.StagError):
+        net.grad(lat, r32, r32, mode="folded_bf16")
 
 
 def test_train_step_reduces_loss():
@@ -245,7 +286,7 @@ def test_fcg_polynomial_preconditioner_gains(orc):
     src = pack(lat, b)
     x0 = torch.zeros_like(src)
     _, rc0, st0 = lat.fcg_solve(m, 0.0, src, x0, net=None, tol=1e-10)
-    for mode in ("bf16", "fp32", "folded"):
+    for mode in ("bf16", "fp32", "folded", "folded_bf16"):
         x1 = torch.zeros_like(src)
         _, rc1, st1 = lat.fcg_solve(m, 0.0, src, x1, net=net, mode=mode, tol=1e-10)
         log(f"plain {st0['iters']} iterations, polynomial-preconditioned ({mode}) {st1['iters']} "
@@ -291,7 +332,7 @@ def test_trained_network_gains_over_plain_cg(orc):
     b = syn.gaussian_source(dims, 650)
     res = learn.compare(latt, net, m, pack(latt, b))
     log(f"held-out: {res}")
-    for mode in ("bf16", "folded"):
+    for mode in ("bf16", "folded", "folded_bf16"):
         assert res[mode]["status"] == 0 and res[mode]["fallback"] == 0
         assert res[mode]["resid_true"] <= 1e-10
         assert res[mode]["iters"] <= 0.8 * res["plain"]["iters"]
