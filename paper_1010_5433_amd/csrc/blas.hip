@@ -75,16 +75,16 @@ __global__ void __launch_bounds__(kBlasBlock) k_ms_start(const double2 *b, T2<R>
     }
 }
 
-// r -= alpha A p, and the partial of ||r||^2.
+// r = rin - alpha A p, and the partial of ||r||^2.
 template <typename R>
-__global__ void __launch_bounds__(kBlasBlock) k_r_update(const MsState *st, T2<R> *r, const T2<R> *ap, int64_t n,
-                                                      double *partial) {
+__global__ void __launch_bounds__(kBlasBlock) k_r_update(const MsState *st, const T2<R> *rin, T2<R> *r,
+                                                      const T2<R> *ap, int64_t n, double *partial) {
     if (st->done) return;
     __shared__ double red[kBlasBlock / kWave];
     const R alpha = R(st->alpha);
     double part = 0.0;
     for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
-        T2<R> rv = r[j];
+        T2<R> rv = rin[j];
         const T2<R> q = ap[j];
         rv.x -= alpha * q.x;
         rv.y -= alpha * q.y;
@@ -128,6 +128,106 @@ __global__ void __launch_bounds__(kBlasBlock) k_shift_update(const MsState *st, 
                 np.y = rv.y + beta * pv.y;
                 pi[j] = np;
             }
+        }
+    }
+}
+
+// Base direction of a deferred solve: pd = r + beta pd (skipped once done).
+template <typename R>
+__global__ void __launch_bounds__(kBlasBlock) k_dir_update(const MsState *st, const T2<R> *r, T2<R> *pd, int64_t n) {
+    if (st->done) return;
+    const R beta = R(st->beta);
+    for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
+        const T2<R> rv = r[j];
+        T2<R> pv = pd[j];
+        pv.x = rv.x + beta * pv.x;
+        pv.y = rv.y + beta * pv.y;
+        pd[j] = pv;
+    }
+}
+
+// Coefficients of a deferred pass from the recorded scalars (one wave, lane
+// = shift).  Starting from p = p_i (index 0), every recorded iteration j at
+// which shift i was updated does x += a_j p, then p = b_j p + z_j r^{k0+1+j}
+// (index 1 + j).  Resets the record.
+__global__ void __launch_bounds__(kWave) k_defer_coef(MsState *st, DeferHist *h) {
+    const int l = threadIdx.x;
+    const int len = h->len;
+    const int nv = len < kDefer ? len : kDefer;
+    if (l < st->n) {
+        double cx[kDefer + 1], cp[kDefer + 1];
+#pragma unroll
+        for (int q = 0; q <= kDefer; ++q) {
+            cx[q] = 0.0;
+            cp[q] = q == 0 ? 1.0 : 0.0;
+        }
+        int any = 0;
+        for (int j = 0; j < nv; ++j) {
+            if (!h->u[j][l]) continue;
+            any = 1;
+            const double aj = h->a[j][l], bj = h->b[j][l];
+#pragma unroll
+            for (int q = 0; q <= kDefer; ++q) {
+                cx[q] += aj * cp[q];
+                cp[q] *= bj;
+            }
+            cp[1 + j] += h->z[j][l];
+        }
+#pragma unroll
+        for (int q = 0; q <= kDefer; ++q) {
+            h->cx[l][q] = cx[q];
+            h->cp[l][q] = cp[q];
+        }
+        h->act[l] = any;
+    }
+    __syncthreads();   // every lane has read len
+    if (l == 0) {
+        h->nvalid = nv;
+        h->len = 0;
+    }
+}
+
+// The deferred pass: for every shift changed in the block,
+// x_i += cx0 p_i + sum_m cx_m r_m and p_i = cp0 p_i + sum_m cp_m r_m,
+// the block's residuals read once for all shifts.
+template <typename R>
+__global__ void __launch_bounds__(kBlasBlock) k_defer_apply(const MsState *st, const DeferHist *h, const T2<R> *ring,
+                                                         int64_t slot, ShiftPtrs ptrs, int n_shift, int64_t n) {
+    const int nv = h->nvalid;
+    if (nv == 0) return;
+    for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
+        T2<R> rr[kDefer];
+#pragma unroll
+        for (int m = 0; m < kDefer; ++m) {
+            if (m < nv) {
+                rr[m] = ring[m * slot + j];
+            } else {
+                rr[m].x = R(0);
+                rr[m].y = R(0);
+            }
+        }
+        for (int i = 0; i < n_shift; ++i) {
+            if (!h->act[i]) continue;
+            T2<R> *pi = static_cast<T2<R> *>(ptrs.p[i]);
+            T2<R> *xi = static_cast<T2<R> *>(ptrs.x[i]);
+            const T2<R> pv = pi[j];
+            T2<R> xv = xi[j];
+            const R cx0 = R(h->cx[i][0]), cp0 = R(h->cp[i][0]);
+            xv.x += cx0 * pv.x;
+            xv.y += cx0 * pv.y;
+            T2<R> np;
+            np.x = cp0 * pv.x;
+            np.y = cp0 * pv.y;
+#pragma unroll
+            for (int m = 0; m < kDefer; ++m) {
+                const R cxm = R(h->cx[i][1 + m]), cpm = R(h->cp[i][1 + m]);
+                xv.x += cxm * rr[m].x;
+                xv.y += cxm * rr[m].y;
+                np.x += cpm * rr[m].x;
+                np.y += cpm * rr[m].y;
+            }
+            xi[j] = xv;
+            pi[j] = np;
         }
     }
 }
@@ -238,10 +338,24 @@ hipError_t launch_scalar_init(MsState *st, const double *partial_r, int nparts_r
     return hipGetLastError();
 }
 
-hipError_t launch_r_update(bool dbl, MsState *st, void *r, const void *ap, int64_t n, double *partial, int grid,
-                           hipStream_t s) {
-    if (dbl) hipLaunchKernelGGL(k_r_update<double>, dim3(grid), dim3(kBlasBlock), 0, s, st, static_cast<double2 *>(r), static_cast<const double2 *>(ap), n, partial);
-    else hipLaunchKernelGGL(k_r_update<float>, dim3(grid), dim3(kBlasBlock), 0, s, st, static_cast<float2 *>(r), static_cast<const float2 *>(ap), n, partial);
+hipError_t launch_r_update(bool dbl, MsState *st, const void *rin, void *r, const void *ap, int64_t n, double *partial,
+                           int grid, hipStream_t s) {
+    if (dbl) hipLaunchKernelGGL(k_r_update<double>, dim3(grid), dim3(kBlasBlock), 0, s, st, static_cast<const double2 *>(rin), static_cast<double2 *>(r), static_cast<const double2 *>(ap), n, partial);
+    else hipLaunchKernelGGL(k_r_update<float>, dim3(grid), dim3(kBlasBlock), 0, s, st, static_cast<const float2 *>(rin), static_cast<float2 *>(r), static_cast<const float2 *>(ap), n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_dir_update(bool dbl, MsState *st, const void *r, void *pd, int64_t n, int grid, hipStream_t s) {
+    if (dbl) hipLaunchKernelGGL(k_dir_update<double>, dim3(grid), dim3(kBlasBlock), 0, s, st, static_cast<const double2 *>(r), static_cast<double2 *>(pd), n);
+    else hipLaunchKernelGGL(k_dir_update<float>, dim3(grid), dim3(kBlasBlock), 0, s, st, static_cast<const float2 *>(r), static_cast<float2 *>(pd), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_defer_pass(bool dbl, MsState *st, DeferHist *h, const void *ring, int64_t slot_elems, ShiftPtrs ptrs,
+                             int n_shift, int64_t n, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_defer_coef, dim3(1), dim3(kWave), 0, s, st, h);
+    if (dbl) hipLaunchKernelGGL(k_defer_apply<double>, dim3(grid), dim3(kBlasBlock), 0, s, (const MsState *)st, (const DeferHist *)h, static_cast<const double2 *>(ring), slot_elems, ptrs, n_shift, n);
+    else hipLaunchKernelGGL(k_defer_apply<float>, dim3(grid), dim3(kBlasBlock), 0, s, (const MsState *)st, (const DeferHist *)h, static_cast<const float2 *>(ring), slot_elems, ptrs, n_shift, n);
     return hipGetLastError();
 }
 

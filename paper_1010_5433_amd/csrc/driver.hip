@@ -18,6 +18,12 @@
 // precision (the residual-replacement idea the paper discusses, applied to
 // the base system of the shifted family) and replaces the single precision
 // residual.
+//
+// Double precision multi-shift solves (two or more shifts, zero start) defer
+// the shifted systems' vector updates: the operator acts on the base
+// direction only, so the x_i and p_i of every shift are brought up to date
+// once per block of kDefer iterations from the block's base residuals
+// (kept in a ring of kDefer vectors) and the recorded scalars.
 #include <chrono>
 #include <cstring>
 #include <vector>
@@ -51,8 +57,10 @@ struct ShiftedResult {
 };
 
 static constexpr int kChunk = 8;   // iterations enqueued between flag reads
+static_assert(kChunk % kDefer == 0, "a chunk must end on a deferred pass");
 static constexpr double kReliableDelta = 0.1;   // reliable update after |r| fell 10x
 static constexpr int kReliableCheck = 8;        // iterations between reliable-update checks
+static_assert(kReliableCheck % kDefer == 0, "reliable updates need the solutions brought up to date");
 
 stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult *res, hipStream_t s) {
     const int n = sp.n;
@@ -67,21 +75,34 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
         if (sp.shifts[i] < sp.shifts[base]) base = i;
     const double sigma0 = sp.shifts[base];
 
+    // deferred shift updates (see the top of the file)
+    const bool defer = !sp.x_init && n >= 2;
+    if (defer && sp.reliable_every % kDefer != 0) {
+        set_error("reliable updates must fall on deferred passes");
+        return STAG_EINVAL;
+    }
+
     void *T, *T64, *R, *AP, *P, *XLO = nullptr, *RHI, *PART, *STATE;
     const int ds_grid = dslash_grid(lat->g, kDslashBlock);
     const int bl_grid = blas_grid(ne);
     const int nparts_max = ds_grid > kMaxBlasGrid ? ds_grid : kMaxBlasGrid;
+    const size_t state_bytes = (sizeof(MsState) + 255) / 256 * 256;
     STAG_TRY(ws_get(lat, WS_T, vb, &T));
     STAG_TRY(ws_get(lat, WS_T2, vb64, &T64));
-    STAG_TRY(ws_get(lat, WS_R, vb, &R));
+    STAG_TRY(ws_get(lat, WS_R, vb * (defer ? kDefer : 1), &R));
     STAG_TRY(ws_get(lat, WS_AP, vb, &AP));
-    STAG_TRY(ws_get(lat, WS_P, vb * n, &P));
+    STAG_TRY(ws_get(lat, WS_P, vb * (n + (defer ? 1 : 0)), &P));
     if (!dbl) STAG_TRY(ws_get(lat, WS_XLO, (size_t)vec_bytes(lat, false) * n, &XLO));
     STAG_TRY(ws_get(lat, WS_RHI, vb64, &RHI));
     STAG_TRY(ws_get(lat, WS_PART, sizeof(double) * 2 * nparts_max, &PART));
-    STAG_TRY(ws_get(lat, WS_STATE, sizeof(MsState), &STATE));
+    STAG_TRY(ws_get(lat, WS_STATE, state_bytes + sizeof(DeferHist), &STATE));
     double *part0 = static_cast<double *>(PART), *part1 = part0 + nparts_max;
     MsState *st = static_cast<MsState *>(STATE);
+    DeferHist *hist = reinterpret_cast<DeferHist *>(static_cast<char *>(STATE) + state_bytes);
+    // residual r^k of iteration k: slot k mod kDefer of the ring (deferred) or R
+    auto rslot = [&](int k) -> void * {
+        return defer ? static_cast<char *>(R) + vb * (size_t)(((k % kDefer) + kDefer) % kDefer) : R;
+    };
 
     ShiftPtrs it_ptrs, hi_ptrs, lo_ptrs;
     std::memset(&it_ptrs, 0, sizeof(it_ptrs));
@@ -93,7 +114,9 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
         if (!dbl) lo_ptrs.x[i] = static_cast<char *>(XLO) + (size_t)vec_bytes(lat, false) * i;
         it_ptrs.x[i] = dbl ? sp.x_hi[i] : lo_ptrs.x[i];
     }
-    void *pbase = it_ptrs.p[base];
+    // the direction the operator acts on: the base shift's own p, or (deferred)
+    // a separate vector kept current every iteration
+    void *pbase = defer ? static_cast<char *>(P) + vb * n : it_ptrs.p[base];
 
     // static part of the state
     MsState hs;
@@ -103,6 +126,7 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
     hs.tol = sp.tol;
     hs.max_iter = sp.max_iter;
     hs.rel_delta2 = sp.reliable_every > 0 ? kReliableDelta * kReliableDelta : 0.0;
+    hs.hist = defer ? hist : nullptr;   // its record is emptied by the start step
     for (int i = 0; i < n; ++i) hs.shift_rel[i] = sp.shifts[i] - sigma0;
     STAG_HIP(hipMemcpyAsync(st, &hs, sizeof(hs), hipMemcpyHostToDevice, s));
 
@@ -134,7 +158,9 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
 
     // ---------------------------------------------------------------- start
     if (!sp.x_init) {
-        STAG_HIP(launch_ms_start(dbl, static_cast<const double2 *>(sp.src), R, it_ptrs, n, true, ne, s));
+        // r^0 = b sits where iteration 0 reads it (slot kDefer - 1 of the ring)
+        STAG_HIP(launch_ms_start(dbl, static_cast<const double2 *>(sp.src), rslot(-1), it_ptrs, n, true, ne, s));
+        if (defer) STAG_HIP(hipMemcpyAsync(pbase, rslot(-1), vb, hipMemcpyDeviceToDevice, s));
         if (!dbl)
             for (int i = 0; i < n; ++i) STAG_HIP(hipMemsetAsync(sp.x_hi[i], 0, vb64, s));
         STAG_HIP(launch_norm2(true, sp.src, ne, part0, bl_grid, s));
@@ -164,14 +190,20 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
         d.partial = part0;
         STAG_HIP(launch_dslash(dbl, lat->nrow, DS_NORMAL_DOT, d, s));
         STAG_HIP(launch_reduce_tail(st, part0, ds_grid, TAIL_ALPHA, 0, s));
-        STAG_HIP(launch_r_update(dbl, st, R, AP, ne, part1, bl_grid, s));
+        STAG_HIP(launch_r_update(dbl, st, rslot(k - 1), rslot(k), AP, ne, part1, bl_grid, s));
         STAG_HIP(launch_reduce_tail(st, part1, bl_grid, TAIL_BETA, 0, s));
-        STAG_HIP(launch_shift_update(dbl, st, R, it_ptrs, n, ne, bl_grid, s));
+        if (defer) {
+            STAG_HIP(launch_dir_update(dbl, st, rslot(k), pbase, ne, bl_grid, s));
+            if ((k + 1) % kDefer == 0)
+                STAG_HIP(launch_defer_pass(dbl, st, hist, R, ne, it_ptrs, n, ne, bl_grid, s));
+        } else {
+            STAG_HIP(launch_shift_update(dbl, st, R, it_ptrs, n, ne, bl_grid, s));
+        }
         if (sp.reliable_every > 0 && (k + 1) % sp.reliable_every == 0) {
             STAG_HIP(launch_x_flush(st, hi_ptrs, lo_ptrs, n, ne, true, s));
             STAG_HIP(true_residual(sp.x_hi[base], sigma0, RHI, part0, &st->rel_skip));
             STAG_HIP(launch_reduce_tail(st, part0, ds_grid, TAIL_RELIABLE, 0, s));
-            STAG_HIP(launch_demote(st, static_cast<const double2 *>(RHI), static_cast<float2 *>(R), ne, s));
+            STAG_HIP(launch_demote(st, static_cast<const double2 *>(RHI), static_cast<float2 *>(rslot(k)), ne, s));
         }
         return STAG_OK;
     };

@@ -41,6 +41,7 @@ __device__ __forceinline__ void ms_init_step(MsState *st, double rho, double b2)
         st->n_reliable = 0;
         st->rho_rel = rho;
         st->rel_skip = 1;
+        if (st->hist) st->hist->len = 0;
         st->done = conv ? 1 : 0;
         st->status = conv ? MS_CONVERGED : MS_RUNNING;
     }
@@ -79,15 +80,23 @@ __device__ __forceinline__ void ms_beta_step(MsState *st, double rho_new) {
     const double beta = rho_new / st->rho;
     const double alpha = st->alpha;
     const int it = st->iter + 1;
+    DeferHist *h = st->hist;
+    const int pos = h ? h->len : 0;   // read by every lane before lane 0 advances it
     bool act = false;
     if (l < st->n) {
         const bool was = st->active[l] != 0;
         st->upd[l] = was ? 1 : 0;
+        if (h && pos < kDefer) h->u[pos][l] = was ? 1 : 0;
         if (was) {
             const double zn = st->zeta_next[l];
             const double ratio = zn / st->zeta[l];
             st->a[l] = alpha * ratio;
             st->b[l] = beta * ratio * ratio;
+            if (h && pos < kDefer) {
+                h->a[pos][l] = alpha * ratio;
+                h->b[pos][l] = beta * ratio * ratio;
+                h->z[pos][l] = zn;
+            }
             const double res = fabs(zn) * sqrt(rho_new / st->bnorm2);
             st->resid_iter[l] = res;
             if (res <= st->tol) {
@@ -103,6 +112,7 @@ __device__ __forceinline__ void ms_beta_step(MsState *st, double rho_new) {
     const unsigned long long any = __ballot(act);
     const int upd_base = __shfl(l < st->n ? st->upd[l] : 0, st->base);
     if (l == 0) {
+        if (h) h->len = pos + 1;
         st->upd_p = (upd_base || any) ? 1 : 0;
         st->beta = beta;
         st->beta_prev = beta;

@@ -14,6 +14,27 @@ constexpr int kMaxPartials = 16384;
 
 enum MsStatus { MS_RUNNING = 0, MS_NOCONV = 1, MS_BREAKDOWN = 2, MS_CONVERGED = 3 };
 
+// Deferred shift updates.  The shifted systems' vectors never enter the
+// operator: only the base direction does.  Over kDefer iterations
+//   x_i += a_i^k p_i,   p_i = zeta_i^{k+1} r^{k+1} + b_i^k p_i
+// keeps p_i in the span of its value at the start of the block and the base
+// residuals r^{k0+1} .. r^{k0+kDefer}, so one pass at the end of the block,
+// with coefficients built from the recorded scalars, does the work of
+// kDefer per-iteration passes: each p_i and x_i is read and written once
+// per block instead of once per iteration.
+constexpr int kDefer = 8;
+
+struct DeferHist {
+    int len;        // iterations recorded since the last pass
+    int nvalid;     // iterations covered by the coefficients of the pass
+    int pad[2];
+    double a[kDefer][kMaxShifts], b[kDefer][kMaxShifts], z[kDefer][kMaxShifts];
+    int u[kDefer][kMaxShifts];          // shift i was updated at that iteration
+    int act[kMaxShifts];                // shift i changes in this pass
+    double cx[kMaxShifts][kDefer + 1];  // x_i += cx[0] p_i + sum_m cx[1+m] r_m
+    double cp[kMaxShifts][kDefer + 1];  // p_i  = cp[0] p_i + sum_m cp[1+m] r_m
+};
+
 struct MsState {
     double rho;          // <r, r>
     double alpha, alpha_prev, beta, beta_prev;
@@ -31,6 +52,7 @@ struct MsState {
     int n_reliable;
     int rel_skip;        // 1: the reliable-update kernels of this iteration are no-ops
     int pad[2];
+    DeferHist *hist;     // non-null: the scalar steps record per-iteration coefficients
     double shift_rel[kMaxShifts];   // s_i = sigma_i - sigma_base
     double zeta[kMaxShifts], zeta_prev[kMaxShifts], zeta_next[kMaxShifts];
     double a[kMaxShifts], b[kMaxShifts];
@@ -56,8 +78,16 @@ hipError_t launch_ms_start(bool dbl, const double2 *b, void *r, ShiftPtrs ptrs, 
                            int64_t n, hipStream_t s);
 hipError_t launch_scalar_init(MsState *st, const double *partial_r, int nparts_r, const double *partial_b,
                               int nparts_b, hipStream_t s);
-hipError_t launch_r_update(bool dbl, MsState *st, void *r, const void *ap, int64_t n, double *partial, int grid,
-                           hipStream_t s);
+// r = rin - alpha A p (rin may equal r), and the partials of ||r||^2.
+hipError_t launch_r_update(bool dbl, MsState *st, const void *rin, void *r, const void *ap, int64_t n, double *partial,
+                           int grid, hipStream_t s);
+// Deferred updates: pd = r + beta pd every iteration (the base direction the
+// operator acts on), and at the end of a block the coefficients and the pass
+// over every shift changed in it.  ring: kDefer residual vectors, slot m
+// holding r^{k0+1+m}.
+hipError_t launch_dir_update(bool dbl, MsState *st, const void *r, void *pd, int64_t n, int grid, hipStream_t s);
+hipError_t launch_defer_pass(bool dbl, MsState *st, DeferHist *h, const void *ring, int64_t slot_elems, ShiftPtrs ptrs,
+                             int n_shift, int64_t n, int grid, hipStream_t s);
 hipError_t launch_shift_update(bool dbl, MsState *st, const void *r, ShiftPtrs ptrs, int n_shift, int64_t n, int grid,
                                hipStream_t s);
 // One workgroup sums nparts partials (fixed order) and applies a TailKind step.

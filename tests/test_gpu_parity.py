@@ -315,6 +315,32 @@ def test_single_cg_from_guess(orc):
         assert orc.true_residual(dims, U, 0.05, 0.02, b, unpack(lat, x)) <= 1e-10
 
 
+@pytest.mark.parametrize("mass,shifts,tol,max_iter", [
+    (0.1, "log8", 1e-10, 3), (0.1, "log8", 1e-10, 8), (0.1, "log8", 1e-10, 13), (0.1, "log8", 1e-10, 21),
+    (3.0, [0.0, 5.0, 50.0], 1e-5, 1000), (2.0, [0.0, 1.0, 10.0], 1e-6, 1000), (0.1, [0.0, 0.0, 0.3], 1e-10, 29)])
+def test_multishift_block_boundaries(orc, mass, shifts, tol, max_iter):
+    """The shifted solutions are brought up to date once per block of 8
+    iterations.  Solves that stop inside a block (iteration limit), end
+    within the first block, or carry duplicate shifts must return the
+    iterates of the plain per-iteration recursion (oracle, same limit)."""
+    import paper_1010_5433_amd as stag
+    log(f"block boundaries m={mass} shifts={shifts} tol={tol} max_iter={max_iter}")
+    dims = (4, 4, 4, 4)
+    U = syn.haar_links(dims, 61)
+    b = syn.gaussian_source(dims, 62)
+    if shifts == "log8":
+        shifts = list(syn.logspace_shifts(1e-4, 1.0, 8))
+    xo, rco, io = orc.multishift_cg(dims, U, mass, shifts, b, tol=tol, max_iter=max_iter)
+    lat = lattice_with_links(dims, U)
+    xs, rc, st = _solve(lat, mass, shifts, b, tol=tol, max_iter=max_iter)
+    assert st["iters"] == io["iters"]
+    assert rc == (0 if rco == 0 else stag._abi.STAG_ENOCONV)
+    for i in range(len(shifts)):
+        assert rel(xs[i], xo[i]) <= 1e-12, (i, rel(xs[i], xo[i]))
+        if rco == 0:
+            assert orc.true_residual(dims, U, mass, shifts[i], b, xs[i]) <= tol
+
+
 def test_solver_edge_cases():
     import torch
     import paper_1010_5433_amd as stag
