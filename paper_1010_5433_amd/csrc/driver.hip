@@ -22,8 +22,10 @@
 // Double precision multi-shift solves (two or more shifts, zero start) defer
 // the shifted systems' vector updates: the operator acts on the base
 // direction only, so the x_i and p_i of every shift are brought up to date
-// once per block of kDefer iterations from the block's base residuals
-// (kept in a ring of kDefer vectors) and the recorded scalars.
+// once per block of iterations (16 in double precision; 8 in single
+// precision, where the reliable-update checks need the solutions current
+// every 8 iterations) from the block's base residuals, kept in a ring, and
+// the recorded scalars.
 #include <chrono>
 #include <cstring>
 #include <vector>
@@ -57,10 +59,8 @@ struct ShiftedResult {
 };
 
 static constexpr int kChunk = 8;   // iterations enqueued between flag reads
-static_assert(kChunk % kDefer == 0, "a chunk must end on a deferred pass");
 static constexpr double kReliableDelta = 0.1;   // reliable update after |r| fell 10x
 static constexpr int kReliableCheck = 8;        // iterations between reliable-update checks
-static_assert(kReliableCheck % kDefer == 0, "reliable updates need the solutions brought up to date");
 
 stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult *res, hipStream_t s) {
     const int n = sp.n;
@@ -77,7 +77,9 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
 
     // deferred shift updates (see the top of the file)
     const bool defer = !sp.x_init && n >= 2;
-    if (defer && sp.reliable_every % kDefer != 0) {
+    const int dlen = dbl ? kDefer : 8;   // iterations per deferred block
+    static_assert(kDefer >= 8 && kReliableCheck % 8 == 0, "deferred block lengths");
+    if (defer && sp.reliable_every % dlen != 0) {
         set_error("reliable updates must fall on deferred passes");
         return STAG_EINVAL;
     }
@@ -89,7 +91,7 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
     const size_t state_bytes = (sizeof(MsState) + 255) / 256 * 256;
     STAG_TRY(ws_get(lat, WS_T, vb, &T));
     STAG_TRY(ws_get(lat, WS_T2, vb64, &T64));
-    STAG_TRY(ws_get(lat, WS_R, vb * (defer ? kDefer : 1), &R));
+    STAG_TRY(ws_get(lat, WS_R, vb * (defer ? dlen : 1), &R));
     STAG_TRY(ws_get(lat, WS_AP, vb, &AP));
     STAG_TRY(ws_get(lat, WS_P, vb * (n + (defer ? 1 : 0)), &P));
     if (!dbl) STAG_TRY(ws_get(lat, WS_XLO, (size_t)vec_bytes(lat, false) * n, &XLO));
@@ -99,9 +101,9 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
     double *part0 = static_cast<double *>(PART), *part1 = part0 + nparts_max;
     MsState *st = static_cast<MsState *>(STATE);
     DeferHist *hist = reinterpret_cast<DeferHist *>(static_cast<char *>(STATE) + state_bytes);
-    // residual r^k of iteration k: slot k mod kDefer of the ring (deferred) or R
+    // residual r^k of iteration k: slot k mod dlen of the ring (deferred) or R
     auto rslot = [&](int k) -> void * {
-        return defer ? static_cast<char *>(R) + vb * (size_t)(((k % kDefer) + kDefer) % kDefer) : R;
+        return defer ? static_cast<char *>(R) + vb * (size_t)(((k % dlen) + dlen) % dlen) : R;
     };
 
     ShiftPtrs it_ptrs, hi_ptrs, lo_ptrs;
@@ -158,7 +160,7 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
 
     // ---------------------------------------------------------------- start
     if (!sp.x_init) {
-        // r^0 = b sits where iteration 0 reads it (slot kDefer - 1 of the ring)
+        // r^0 = b sits where iteration 0 reads it (slot dlen - 1 of the ring)
         STAG_HIP(launch_ms_start(dbl, static_cast<const double2 *>(sp.src), rslot(-1), it_ptrs, n, true, ne, s));
         if (defer) STAG_HIP(hipMemcpyAsync(pbase, rslot(-1), vb, hipMemcpyDeviceToDevice, s));
         if (!dbl)
@@ -194,7 +196,7 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
         STAG_HIP(launch_reduce_tail(st, part1, bl_grid, TAIL_BETA, 0, s));
         if (defer) {
             STAG_HIP(launch_dir_update(dbl, st, rslot(k), pbase, ne, bl_grid, s));
-            if ((k + 1) % kDefer == 0)
+            if ((k + 1) % dlen == 0)
                 STAG_HIP(launch_defer_pass(dbl, st, hist, R, ne, it_ptrs, n, ne, bl_grid, s));
         } else {
             STAG_HIP(launch_shift_update(dbl, st, R, it_ptrs, n, ne, bl_grid, s));
@@ -244,6 +246,8 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
     if (rc != STAG_OK) return rc;
 
     // ---------------------------------------------------------------- finish
+    // the last block may end between passes (a no-op when it does not)
+    if (defer) STAG_HIP(launch_defer_pass(dbl, st, hist, R, ne, it_ptrs, n, ne, bl_grid, s));
     if (!dbl) STAG_HIP(launch_x_flush(st, hi_ptrs, lo_ptrs, n, ne, false, s));
     for (int i = 0; i < n; ++i) {
         STAG_HIP(true_residual(sp.x_hi[i], sp.shifts[i], nullptr, part0, nullptr));

@@ -15,14 +15,14 @@ constexpr int kMaxPartials = 16384;
 enum MsStatus { MS_RUNNING = 0, MS_NOCONV = 1, MS_BREAKDOWN = 2, MS_CONVERGED = 3 };
 
 // Deferred shift updates.  The shifted systems' vectors never enter the
-// operator: only the base direction does.  Over kDefer iterations
+// operator: only the base direction does.  Over L iterations
 //   x_i += a_i^k p_i,   p_i = zeta_i^{k+1} r^{k+1} + b_i^k p_i
 // keeps p_i in the span of its value at the start of the block and the base
-// residuals r^{k0+1} .. r^{k0+kDefer}, so one pass at the end of the block,
-// with coefficients built from the recorded scalars, does the work of
-// kDefer per-iteration passes: each p_i and x_i is read and written once
-// per block instead of once per iteration.
-constexpr int kDefer = 8;
+// residuals r^{k0+1} .. r^{k0+L}, so one pass at the end of the block, with
+// coefficients built from the recorded scalars, does the work of L
+// per-iteration passes: each p_i and x_i is read and written once per block
+// instead of once per iteration.  Blocks hold up to kDefer iterations.
+constexpr int kDefer = 16;
 
 struct DeferHist {
     int len;        // iterations recorded since the last pass
@@ -83,8 +83,8 @@ hipError_t launch_r_update(bool dbl, MsState *st, const void *rin, void *r, cons
                            int grid, hipStream_t s);
 // Deferred updates: pd = r + beta pd every iteration (the base direction the
 // operator acts on), and at the end of a block the coefficients and the pass
-// over every shift changed in it.  ring: kDefer residual vectors, slot m
-// holding r^{k0+1+m}.
+// over every shift changed in it.  ring: one residual vector per iteration
+// of the block, slot m holding r^{k0+1+m}.
 hipError_t launch_dir_update(bool dbl, MsState *st, const void *r, void *pd, int64_t n, int grid, hipStream_t s);
 hipError_t launch_defer_pass(bool dbl, MsState *st, DeferHist *h, const void *ring, int64_t slot_elems, ShiftPtrs ptrs,
                              int n_shift, int64_t n, int grid, hipStream_t s);
