@@ -34,6 +34,8 @@ struct BSys {
     int nchunk_ds;         // Dslash partials: ceil(Vh / 64)
     int nchunk_bl;         // vector partials: ceil(3 Vh / kBChunk)
     int x_init;            // start from xhi[0] (single shift) instead of zero
+    int dlen;              // deferred shift updates in blocks of dlen iterations (0: every iteration)
+    int pad;
     double m2;             // mass^2
     double shifts[kMaxShifts];
     MsState *st;
@@ -41,6 +43,9 @@ struct BSys {
     double *part_bl;
     const double2 *src;
     void *r, *ap, *t;      // iteration precision
+    void *ring;            // deferred: dlen residual vectors, r^k in slot k mod dlen
+    void *pd;              // deferred: the base direction the operator acts on
+    DeferHist *hist;       // deferred: recorded scalars and pass coefficients
     double2 *t64, *rhi;    // double precision work vectors
     void *p[kMaxShifts];
     void *x[kMaxShifts];   // iteration precision accumulators (== xhi for double)
@@ -69,9 +74,14 @@ enum BVecOp {
     BV_SHIFT_UPDATE = 4,
     BV_FLUSH = 5,      // xhi += x, x = 0 (single precision), when a reliable update is due
     BV_FLUSH_FINAL = 6,// same, always
-    BV_DEMOTE = 7      // r = (float) rhi, when a reliable update is due
+    BV_DEMOTE = 7,     // r = (float) rhi, when a reliable update is due
+    BV_DEFER_APPLY = 8 // deferred systems: the pass over every shift changed in the block
 };
-hipError_t launch_bvec(bool dbl, BView v, int op, int max_blocks, hipStream_t s);
+// it: the iteration the op belongs to (selects ring slots of deferred systems;
+// BV_START writes r^0 to the slot iteration 0 reads)
+hipError_t launch_bvec(bool dbl, BView v, int op, int max_blocks, hipStream_t s, int it = 0);
+// coefficients of the deferred pass of every deferred system
+hipError_t launch_bdefer_coef(BView v, hipStream_t s);
 
 enum BTail {
     BT_INIT = 0,       // zero start: rho = |b|^2 from part_bl

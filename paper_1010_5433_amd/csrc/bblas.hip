@@ -22,8 +22,10 @@ template <typename R> __device__ __forceinline__ T2<R> mk2(R a, R b) {
     return v;
 }
 
+__host__ __device__ __forceinline__ int ring_slot(int k, int d) { return ((k % d) + d) % d; }
+
 template <typename R>
-__global__ void __launch_bounds__(kBBlock) kb_vec(BView v, int op) {
+__global__ void __launch_bounds__(kBBlock) kb_vec(BView v, int op, int it) {
     const BSys &s = v.sys[blockIdx.y];
     constexpr int kWavesPerBlock = kBBlock / kWave;
     if ((int)blockIdx.x * kWavesPerBlock >= s.nchunk_bl) return;
@@ -34,15 +36,21 @@ __global__ void __launch_bounds__(kBBlock) kb_vec(BView v, int op) {
     const int64_t j0 = (int64_t)chunk * kBChunk + lane;
     double part = 0.0;
     bool reduce = false;
+    // residual of iteration k: its ring slot (deferred systems) or s.r
+    auto rvec = [&](int k) -> T2<R> * {
+        return s.dlen ? static_cast<T2<R> *>(s.ring) + (int64_t)ring_slot(k, s.dlen) * n : static_cast<T2<R> *>(s.r);
+    };
 
     if (op == BV_START) {
-        T2<R> *r = static_cast<T2<R> *>(s.r);
+        T2<R> *r = rvec(-1);
+        T2<R> *pd = static_cast<T2<R> *>(s.pd);
         for (int e = 0; e < 4; ++e) {
             const int64_t j = j0 + e * kWave;
             if (j >= n) break;
             const double2 b = s.src[j];
             const T2<R> bv = mk2<R>(R(b.x), R(b.y));
             r[j] = bv;
+            if (s.dlen) pd[j] = bv;
             for (int i = 0; i < s.n; ++i) {
                 static_cast<T2<R> *>(s.p[i])[j] = bv;
                 static_cast<T2<R> *>(s.x[i])[j] = mk2<R>(R(0), R(0));
@@ -74,18 +82,32 @@ __global__ void __launch_bounds__(kBBlock) kb_vec(BView v, int op) {
         if (st->done) return;
         reduce = true;
         const R alpha = R(st->alpha);
-        T2<R> *r = static_cast<T2<R> *>(s.r);
+        const T2<R> *rin = rvec(it - 1);
+        T2<R> *r = rvec(it);
         const T2<R> *ap = static_cast<const T2<R> *>(s.ap);
         for (int e = 0; e < 4; ++e) {
             const int64_t j = j0 + e * kWave;
             if (j < n) {
-                T2<R> rv = r[j];
+                T2<R> rv = rin[j];
                 const T2<R> q = ap[j];
                 rv.x -= alpha * q.x;
                 rv.y -= alpha * q.y;
                 r[j] = rv;
                 part += double(rv.x) * double(rv.x) + double(rv.y) * double(rv.y);
             }
+        }
+    } else if (op == BV_SHIFT_UPDATE && s.dlen) {
+        // deferred system: only the base direction pd = r + beta pd
+        if (st->done) return;
+        const T2<R> *r = rvec(it);
+        T2<R> *pd = static_cast<T2<R> *>(s.pd);
+        const R beta = R(st->beta);
+        for (int e = 0; e < 4; ++e) {
+            const int64_t j = j0 + e * kWave;
+            if (j >= n) break;
+            const T2<R> rv = r[j];
+            const T2<R> pv = pd[j];
+            pd[j] = mk2<R>(rv.x + beta * pv.x, rv.y + beta * pv.y);
         }
     } else if (op == BV_SHIFT_UPDATE) {
         if (!st->upd_valid) return;
@@ -128,9 +150,32 @@ __global__ void __launch_bounds__(kBBlock) kb_vec(BView v, int op) {
                 xl[j] = mk2<R>(R(0), R(0));
             }
         }
+    } else if (op == BV_DEFER_APPLY) {
+        if (!s.dlen) return;
+        const DeferHist *h = s.hist;
+        const int nv = h->nvalid;
+        if (nv == 0) return;
+        const T2<R> *ring = static_cast<const T2<R> *>(s.ring);
+        for (int e = 0; e < 4; ++e) {
+            const int64_t j = j0 + e * kWave;
+            if (j >= n) break;
+            T2<R> rr[kDefer];
+#pragma unroll
+            for (int m = 0; m < kDefer; ++m) rr[m] = m < nv ? ring[m * n + j] : mk2<R>(R(0), R(0));
+            for (int i = 0; i < s.n; ++i) {
+                if (!h->act[i]) continue;
+                T2<R> *pi = static_cast<T2<R> *>(s.p[i]);
+                T2<R> *xi = static_cast<T2<R> *>(s.x[i]);
+                T2<R> pv = pi[j];
+                T2<R> xv = xi[j];
+                defer_combine<T2<R>, R>(h, i, rr, xv, pv);
+                xi[j] = xv;
+                pi[j] = pv;
+            }
+        }
     } else if (op == BV_DEMOTE) {
         if (st->rel_skip) return;
-        T2<R> *r = static_cast<T2<R> *>(s.r);
+        T2<R> *r = rvec(it);
         for (int e = 0; e < 4; ++e) {
             const int64_t j = j0 + e * kWave;
             if (j >= n) break;
@@ -144,11 +189,24 @@ __global__ void __launch_bounds__(kBBlock) kb_vec(BView v, int op) {
     }
 }
 
-hipError_t launch_bvec(bool dbl, BView v, int op, int max_blocks, hipStream_t s) {
+hipError_t launch_bvec(bool dbl, BView v, int op, int max_blocks, hipStream_t s, int it) {
     if (v.nsys <= 0) return hipSuccess;
     const dim3 grid(max_blocks, v.nsys), blk(kBBlock);
-    if (dbl) hipLaunchKernelGGL(kb_vec<double>, grid, blk, 0, s, v, op);
-    else hipLaunchKernelGGL(kb_vec<float>, grid, blk, 0, s, v, op);
+    if (dbl) hipLaunchKernelGGL(kb_vec<double>, grid, blk, 0, s, v, op, it);
+    else hipLaunchKernelGGL(kb_vec<float>, grid, blk, 0, s, v, op, it);
+    return hipGetLastError();
+}
+
+// One wave per system (deferred systems only).
+__global__ void __launch_bounds__(kWave) kb_defer_coef(BView v) {
+    const BSys &s = v.sys[blockIdx.x];
+    if (!s.dlen) return;
+    defer_coef_step(s.n, s.hist);
+}
+
+hipError_t launch_bdefer_coef(BView v, hipStream_t s) {
+    if (v.nsys <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_defer_coef, dim3(v.nsys), dim3(kWave), 0, s, v);
     return hipGetLastError();
 }
 

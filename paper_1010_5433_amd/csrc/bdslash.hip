@@ -195,6 +195,14 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
     for (int l = 1; l < nlat; ++l)
         if (lats[l]->nrow != nrow) return invalid("all lattices of a batch must use the same link format");
 
+    // ---- deferred shift updates for multi-shift systems from a zero start
+    // (blocks of kDefer iterations in double precision, 8 in single
+    // precision so that passes fall on the reliable-update checks)
+    const int dlen_all = dbl ? kDefer : 8;
+    if (!dbl && opt.reliable_every > 0 && opt.reliable_every % dlen_all != 0)
+        return invalid("reliable updates must fall on deferred passes");
+    auto dlen_of = [&](int k) { return (spec[k].n >= 2 && !spec[k].x_init) ? dlen_all : 0; };
+
     // ---- work arena (carved from the first lattice's handle)
     int max_ds = 1;
     for (int l = 0; l < nlat; ++l) max_ds = std::max(max_ds, dslash_grid(lats[l]->g, kDslashBlock));
@@ -206,6 +214,7 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
         size_t b = al256(sizeof(double) * nds) + al256(sizeof(double) * nbl) + al256(sizeof(double) * max_ds);
         b += 3 * al256(vb) + 2 * al256(v64) + spec[k].n * al256(vb);
         if (!dbl) b += spec[k].n * al256(vb);
+        if (dlen_of(k)) b += dlen_of(k) * al256(vb) + al256(vb) + al256(sizeof(DeferHist));
         bytes += b;
     }
     void *arena = nullptr;
@@ -247,6 +256,7 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
         y.nchunk_ds = (int)((vh + 63) / 64);
         y.nchunk_bl = (int)((3 * vh + kBChunk - 1) / kBChunk);
         y.x_init = sp.x_init ? 1 : 0;
+        y.dlen = dlen_of(k);
         y.m2 = sp.mass * sp.mass;
         for (int i = 0; i < sp.n; ++i) y.shifts[i] = sp.shifts[i];
         y.st = d_st + k;
@@ -264,6 +274,11 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
             y.xhi[i] = static_cast<double2 *>(sp.sols[i]);
             y.x[i] = dbl ? sp.sols[i] : take(vb);
         }
+        if (y.dlen) {
+            y.ring = take((size_t)y.dlen * al256(vb));
+            y.pd = take(vb);
+            y.hist = reinterpret_cast<DeferHist *>(take(sizeof(DeferHist)));
+        }
         MsState &st = h_st[k];
         std::memset(&st, 0, sizeof(MsState));
         st.n = sp.n;
@@ -271,6 +286,7 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
         st.tol = opt.tol;
         st.max_iter = opt.max_iter;
         st.rel_delta2 = (!dbl && opt.reliable_every > 0) ? 0.01 : 0.0;
+        st.hist = y.hist;   // emptied by the start step
         for (int i = 0; i < sp.n; ++i) st.shift_rel[i] = sp.shifts[i] - sp.shifts[y.base];
         max_n = std::max(max_n, sp.n);
         max_blocks = std::max(max_blocks, (y.nchunk_bl + kBBlock / kWave - 1) / (kBBlock / kWave));
@@ -336,13 +352,14 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
             const BSys &y = h_sys[k];
             a.done[r] = &d_st[k].done;
             a.nchunk[r] = y.nchunk_ds;
+            void *dir = y.dlen ? y.pd : y.p[y.base];   // the base direction
             if (role == BD_OE) {
-                a.in[r] = y.p[y.base];
+                a.in[r] = dir;
                 a.out[r] = y.t;
             } else {
                 a.in[r] = y.t;
                 a.out[r] = y.ap;
-                a.aux[r] = y.p[y.base];
+                a.aux[r] = dir;
                 a.c[r] = y.m2 + y.shifts[y.base];
                 a.part[r] = y.part_ds;
             }
@@ -411,6 +428,8 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
             args[l].push_back({make_args(l, grp, BD_OE), make_args(l, grp, BD_EO)});
 
     // ---- iterations
+    bool any_defer = false;
+    for (int k = 0; k < nsys; ++k) any_defer = any_defer || h_sys[k].dlen > 0;
     const bool use_rel = !dbl && opt.reliable_every > 0;
     const int check = use_rel ? opt.reliable_every : 0;
     auto iteration = [&](int it) -> hipError_t {
@@ -423,9 +442,13 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
                 if (e != hipSuccess) return e;
             }
         if (e == hipSuccess) e = launch_btail(v, BT_ALPHA, s);
-        if (e == hipSuccess) e = launch_bvec(dbl, v, BV_R_UPDATE, max_blocks, s);
+        if (e == hipSuccess) e = launch_bvec(dbl, v, BV_R_UPDATE, max_blocks, s, it);
         if (e == hipSuccess) e = launch_btail(v, BT_BETA, s);
-        if (e == hipSuccess) e = launch_bvec(dbl, v, BV_SHIFT_UPDATE, max_blocks, s);
+        if (e == hipSuccess) e = launch_bvec(dbl, v, BV_SHIFT_UPDATE, max_blocks, s, it);
+        if (e == hipSuccess && any_defer && (it + 1) % dlen_all == 0) {
+            e = launch_bdefer_coef(v, s);
+            if (e == hipSuccess) e = launch_bvec(dbl, v, BV_DEFER_APPLY, max_blocks, s, it);
+        }
         if (e == hipSuccess && check > 0 && (it + 1) % check == 0) {
             // reliable update of every system whose residual fell tenfold since its last one
             e = launch_bvec(dbl, v, BV_FLUSH, max_blocks, s);
@@ -435,7 +458,7 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
                     e = launch_reduce_tail(d_st + k, pres[k], dslash_grid(spec[k].lat->g, kDslashBlock), TAIL_RELIABLE,
                                            0, s);
             }
-            if (e == hipSuccess) e = launch_bvec(dbl, v, BV_DEMOTE, max_blocks, s);
+            if (e == hipSuccess) e = launch_bvec(dbl, v, BV_DEMOTE, max_blocks, s, it);
         }
         return e;
     };
@@ -469,7 +492,12 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
     (void)hipEventDestroy(ev[1]);
     if (rc != STAG_OK) return rc;
 
-    // ---- finish: flush single precision accumulators, double precision true residuals
+    // ---- finish: the last deferred pass (the loop may end inside a block),
+    // flush single precision accumulators, double precision true residuals
+    if (any_defer) {
+        STAG_HIP(launch_bdefer_coef(v, s));
+        STAG_HIP(launch_bvec(dbl, v, BV_DEFER_APPLY, max_blocks, s));
+    }
     if (!dbl) STAG_HIP(launch_bvec(dbl, v, BV_FLUSH_FINAL, max_blocks, s));
     for (int k = 0; k < nsys; ++k)
         for (int i = 0; i < spec[k].n; ++i) {

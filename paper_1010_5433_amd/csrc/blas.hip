@@ -146,46 +146,8 @@ __global__ void __launch_bounds__(kBlasBlock) k_dir_update(const MsState *st, co
     }
 }
 
-// Coefficients of a deferred pass from the recorded scalars (one wave, lane
-// = shift).  Starting from p = p_i (index 0), every recorded iteration j at
-// which shift i was updated does x += a_j p, then p = b_j p + z_j r^{k0+1+j}
-// (index 1 + j).  Resets the record.
-__global__ void __launch_bounds__(kWave) k_defer_coef(MsState *st, DeferHist *h) {
-    const int l = threadIdx.x;
-    const int len = h->len;
-    const int nv = len < kDefer ? len : kDefer;
-    if (l < st->n) {
-        double cx[kDefer + 1], cp[kDefer + 1];
-#pragma unroll
-        for (int q = 0; q <= kDefer; ++q) {
-            cx[q] = 0.0;
-            cp[q] = q == 0 ? 1.0 : 0.0;
-        }
-        int any = 0;
-        for (int j = 0; j < nv; ++j) {
-            if (!h->u[j][l]) continue;
-            any = 1;
-            const double aj = h->a[j][l], bj = h->b[j][l];
-#pragma unroll
-            for (int q = 0; q <= kDefer; ++q) {
-                cx[q] += aj * cp[q];
-                cp[q] *= bj;
-            }
-            cp[1 + j] += h->z[j][l];
-        }
-#pragma unroll
-        for (int q = 0; q <= kDefer; ++q) {
-            h->cx[l][q] = cx[q];
-            h->cp[l][q] = cp[q];
-        }
-        h->act[l] = any;
-    }
-    __syncthreads();   // every lane has read len
-    if (l == 0) {
-        h->nvalid = nv;
-        h->len = 0;
-    }
-}
+// Coefficients of a deferred pass (one wave, lane = shift).
+__global__ void __launch_bounds__(kWave) k_defer_coef(MsState *st, DeferHist *h) { defer_coef_step(st->n, h); }
 
 // The deferred pass: for every shift changed in the block,
 // x_i += cx0 p_i + sum_m cx_m r_m and p_i = cp0 p_i + sum_m cp_m r_m,
@@ -210,24 +172,11 @@ __global__ void __launch_bounds__(kBlasBlock) k_defer_apply(const MsState *st, c
             if (!h->act[i]) continue;
             T2<R> *pi = static_cast<T2<R> *>(ptrs.p[i]);
             T2<R> *xi = static_cast<T2<R> *>(ptrs.x[i]);
-            const T2<R> pv = pi[j];
+            T2<R> pv = pi[j];
             T2<R> xv = xi[j];
-            const R cx0 = R(h->cx[i][0]), cp0 = R(h->cp[i][0]);
-            xv.x += cx0 * pv.x;
-            xv.y += cx0 * pv.y;
-            T2<R> np;
-            np.x = cp0 * pv.x;
-            np.y = cp0 * pv.y;
-#pragma unroll
-            for (int m = 0; m < kDefer; ++m) {
-                const R cxm = R(h->cx[i][1 + m]), cpm = R(h->cp[i][1 + m]);
-                xv.x += cxm * rr[m].x;
-                xv.y += cxm * rr[m].y;
-                np.x += cpm * rr[m].x;
-                np.y += cpm * rr[m].y;
-            }
+            defer_combine<T2<R>, R>(h, i, rr, xv, pv);
             xi[j] = xv;
-            pi[j] = np;
+            pi[j] = pv;
         }
     }
 }

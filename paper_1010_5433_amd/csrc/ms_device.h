@@ -139,6 +139,69 @@ __device__ __forceinline__ void ms_beta_step(MsState *st, double rho_new) {
     }
 }
 
+// Coefficients of a deferred pass from the recorded scalars (lane = shift,
+// lanes 0..n-1 of one workgroup).  Starting from p = p_i (index 0), every
+// recorded iteration j at which shift i was updated does x += a_j p, then
+// p = b_j p + z_j r^{k0+1+j} (index 1 + j).  Resets the record.  Every
+// thread of the workgroup must call it.
+__device__ __forceinline__ void defer_coef_step(int n, DeferHist *h) {
+    const int l = threadIdx.x;
+    const int len = h->len;
+    const int nv = len < kDefer ? len : kDefer;
+    if (l < n) {
+        double cx[kDefer + 1], cp[kDefer + 1];
+#pragma unroll
+        for (int q = 0; q <= kDefer; ++q) {
+            cx[q] = 0.0;
+            cp[q] = q == 0 ? 1.0 : 0.0;
+        }
+        int any = 0;
+        for (int j = 0; j < nv; ++j) {
+            if (!h->u[j][l]) continue;
+            any = 1;
+            const double aj = h->a[j][l], bj = h->b[j][l];
+#pragma unroll
+            for (int q = 0; q <= kDefer; ++q) {
+                cx[q] += aj * cp[q];
+                cp[q] *= bj;
+            }
+            cp[1 + j] += h->z[j][l];
+        }
+#pragma unroll
+        for (int q = 0; q <= kDefer; ++q) {
+            h->cx[l][q] = cx[q];
+            h->cp[l][q] = cp[q];
+        }
+        h->act[l] = any;
+    }
+    __syncthreads();   // every lane has read len
+    if (l == 0) {
+        h->nvalid = nv;
+        h->len = 0;
+    }
+}
+
+// One entry of the deferred pass for shift i:
+// x += cx0 p + sum_m cx_m r_m,  p = cp0 p + sum_m cp_m r_m (rr[m] = 0 past the block).
+template <typename V, typename R>
+__device__ __forceinline__ void defer_combine(const DeferHist *h, int i, const V (&rr)[kDefer], V &xv, V &pv) {
+    const R cx0 = R(h->cx[i][0]), cp0 = R(h->cp[i][0]);
+    xv.x += cx0 * pv.x;
+    xv.y += cx0 * pv.y;
+    V np;
+    np.x = cp0 * pv.x;
+    np.y = cp0 * pv.y;
+#pragma unroll
+    for (int m = 0; m < kDefer; ++m) {
+        const R cxm = R(h->cx[i][1 + m]), cpm = R(h->cp[i][1 + m]);
+        xv.x += cxm * rr[m].x;
+        xv.y += cxm * rr[m].y;
+        np.x += cpm * rr[m].x;
+        np.y += cpm * rr[m].y;
+    }
+    pv = np;
+}
+
 // What the one-workgroup reduction kernel does with the reduced sum.
 enum TailKind {
     TAIL_ALPHA = 1,      // total = <p, A p>: alpha and zeta; retires the update flag once done
