@@ -166,6 +166,49 @@ def batched_experiment(args):
     return out
 
 
+def rational_experiment(lat, mass, src, tol, n_poles):
+    """The RHMC's rational functions on the headline lattice: Zolotarev's
+    M^(1/2) (heatbath of two flavours) and M^(-1/2) (their Metropolis
+    action) on [m^2, m^2 + 16], applied with the weighted solutions summed
+    on the fly, against the multi-shift solve of the same poles followed by
+    the weighted sum."""
+    import torch
+
+    import paper_1010_5433_amd as stag
+
+    lo, hi = mass * mass, mass * mass + 16.0
+    out = {"poles": n_poles, "range": [lo, hi]}
+    for name, power in (("heatbath_sqrt", 1), ("action_inv_sqrt", -1)):
+        a0, al, sh, err = stag.zolotarev(power, lo, hi, n_poles)
+        res = torch.empty_like(src)
+        lat.rational_apply(mass, a0, al, sh, src, out=res, tol=tol)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rc, st, dot = lat.rational_apply(mass, a0, al, sh, src, out=res, tol=tol)
+        t_rat = time.perf_counter() - t0
+        if rc != 0:
+            raise RuntimeError(f"rational application failed: {rc}")
+        sols = [torch.empty_like(src) for _ in sh]
+        lat.multishift_cg(mass, sh, src, sols=sols, tol=tol)   # warm-up, with the sum below
+        comb = a0 * src
+        for a, x in zip(al, sols):
+            comb.add_(x, alpha=a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rc2, st2 = lat.multishift_cg(mass, sh, src, sols=sols, tol=tol)
+        comb = a0 * src
+        for a, x in zip(al, sols):
+            comb.add_(x, alpha=a)
+        torch.cuda.synchronize()
+        t_ms = time.perf_counter() - t0
+        diff = float(torch.linalg.vector_norm(comb - res) / torch.linalg.vector_norm(comb))
+        log(f"rational {name}: {t_rat:.4f} s ({st['iters']} iterations) vs multi-shift + sum {t_ms:.4f} s; "
+            f"max rel. approximation error {err:.1e}; results differ by {diff:.1e}")
+        out[name] = dict(seconds=round(t_rat, 4), iters=st["iters"], multishift_then_sum_s=round(t_ms, 4),
+                         max_rel_err=err, rel_diff_vs_multishift=diff, re_src_dot_out=dot)
+    return out
+
+
 def learned_experiment(args, n_test_fields):
     """Train the gauge-equivariant preconditioner on 16^4 fields and judge it
     in flexible CG on held-out 32^4 fields against plain FP64 CG."""
@@ -264,6 +307,8 @@ def main():
     ap.add_argument("--train-pairs", type=int, default=0)
     ap.add_argument("--pairs", default="mx", choices=["mx", "solve"])
     ap.add_argument("--test-fields", type=int, default=4, help="held-out fields of --learned-only")
+    ap.add_argument("--no-rational", action="store_true")
+    ap.add_argument("--rational-poles", type=int, default=24)
     ap.add_argument("--learned-fmt", default=None, choices=["18", "12", "8"],
                     help="link storage of the held-out fields of the learned experiment (default: --fmt)")
     args = ap.parse_args()
@@ -399,6 +444,8 @@ def main():
     lat.set_links(torch.from_numpy(U).cuda(), args.fmt)
     log(f"dslash: {dsl}")
 
+    if not args.no_rational:
+        extra["rational"] = rational_experiment(lat, mass, src, tol, args.rational_poles)
     if not args.no_batched:
         extra["batched"] = batched_experiment(args)
     if not args.no_learned:

@@ -219,6 +219,39 @@ stag_status stag_multishift_cg_batched(const stag_system *systems, int n_systems
  * last batched solve of the calling thread. */
 stag_status stag_batch_last_config(int *block, int *rpt);
 
+/* ------------------------------------------------------------------ rational functions
+ * The RHMC of Section 2 applies rational functions of M, in partial
+ * fractions r(M) = alpha0 + sum_i alpha_i (M + shifts[i])^-1, to the
+ * pseudo-fermion fields: r(M) ~ M^(1/4) (or another power) in the heatbath,
+ * r(M) ~ M^(-1/2) in the action of the Metropolis step, whose inversions
+ * Section 4 keeps in double precision.
+ *
+ * out = alpha0 src + sum_i alpha_i (M + shifts[i])^-1 src by one double
+ * precision multi-shift CG from zero (Section 6).  The weighted solutions
+ * are summed into out as the solver goes: no per-shift solution vector is
+ * stored or returned.  src and out are STAG_F64 library vectors (no
+ * overlap); alphas and shifts are HOST arrays of n (1..64) entries.  Shift
+ * i stops when |zeta_i| ||r|| <= tol ||src||, so in exact arithmetic
+ *   ||out - r(M) src|| <= tol ||src|| sum_i |alpha_i| / (m^2 + shifts[i]).
+ * *dot (host, may be NULL) receives Re <src, out> (the action when src is
+ * the pseudo-fermion field).  stats: iters, iters_shift, resid_iter and
+ * seconds are filled; resid_true is left zero (no solutions are kept).
+ * Requires mass > 0, shifts >= 0, finite alphas, tol > 0, links set.
+ * Returns STAG_ENOCONV after max_iter iterations (out then holds the sum at
+ * that iteration), STAG_EBREAKDOWN on a non-positive curvature.
+ * Synchronous. */
+stag_status stag_rational_apply(stag_lattice *lat, double mass, double alpha0, const double *alphas,
+                                const double *shifts, int n, const void *src, void *out, double tol,
+                                int max_iter, double *dot, stag_cg_stats *stats, void *stream);
+
+/* Zolotarev's optimal relative approximation of x^(-1/2) (power = -1) or
+ * x^(1/2) = x * x^(-1/2) (power = +1) on [lo, hi] (0 < lo < hi), with n
+ * poles (1..64): writes *alpha0, alphas[n], shifts[n] (HOST arrays; all
+ * shifts > 0) and *max_rel_err = max |r(x) / x^power - 1| over [lo, hi]
+ * (may be NULL).  Host computation, no GPU needed. */
+stag_status stag_zolotarev(int power, double lo, double hi, int n, double *alpha0, double *alphas,
+                           double *shifts, double *max_rel_err);
+
 /* ------------------------------------------------------------------ learned preconditioner
  * Not part of the paper: an extension that preconditions the double
  * precision single-shift solve of the Metropolis step (Section 4 keeps that

@@ -150,6 +150,23 @@ class Oracle:
                                              _p(its), _p(ri), _p(rt)), "multishift_cg")
         return x, rc, dict(iters=it.value, iters_shift=its, resid_iter=ri, resid_true=rt)
 
+    def rational_apply(self, dims, links, mass, alpha0, alphas, shifts, b, tol=1e-10, max_iter=100000,
+                       antiperiodic_t=True):
+        """r(M) b = alpha0 b + sum_i alpha_i (M + shift_i)^-1 b, the partial
+        fraction form of the rational functions the RHMC applies (Section 2:
+        rational approximations for the Metropolis step and the molecular
+        dynamics), by its definition: each (M + shift_i)^-1 b from the
+        multi-shift CG above, then the weighted sum.
+        Returns (out, status, info); info as multishift_cg, plus dot = Re <b, out>."""
+        b = _cplx(b)
+        x, rc, info = self.multishift_cg(dims, links, mass, shifts, b, tol=tol, max_iter=max_iter,
+                                         antiperiodic_t=antiperiodic_t)
+        out = float(alpha0) * b
+        for a, xi in zip(alphas, x):
+            out = out + float(a) * xi
+        info = dict(info, dot=float(np.vdot(b, out).real))
+        return out, rc, info
+
 
     # ---------------------------------------------------------------- learned preconditioner
     NET_NPARAM = 656

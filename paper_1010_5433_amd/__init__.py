@@ -20,7 +20,7 @@ from ._abi import (F32, F64, MIXED, LINK8, LINK12, LINK18, MIX_BF16, MIX_FOLDED,
                    System, batch_flags, load_library, status_name)
 
 __all__ = ["Lattice", "CgStats", "StagError", "F64", "F32", "MIXED", "LINK18", "LINK12",
-           "library_path", "vec_empty", "multishift_cg_batched", "batch_last_config", "Net",
+           "library_path", "vec_empty", "multishift_cg_batched", "batch_last_config", "Net", "zolotarev",
            "NET_NPARAM"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -145,6 +145,26 @@ class Lattice:
                     "stag_multishift_cg")
         return sols, rc, st.to_dict(n)
 
+    def rational_apply(self, mass, alpha0, alphas, shifts, src: torch.Tensor, out=None, tol=1e-10,
+                       max_iter=100000):
+        """out = alpha0 src + sum_i alphas[i] (M + shifts[i])^-1 src (double
+        precision).  Returns (out, status, stats, Re <src, out>)."""
+        shifts = [float(s) for s in shifts]
+        alphas = [float(a) for a in alphas]
+        n = len(shifts)
+        if len(alphas) != n:
+            raise ValueError("alphas and shifts differ in length")
+        if out is None:
+            out = torch.empty_like(src)
+        sh = (ctypes.c_double * n)(*shifts)
+        al = (ctypes.c_double * n)(*alphas)
+        dot = ctypes.c_double(0.0)
+        st = CgStats()
+        rc = _check(_L.stag_rational_apply(self._h, float(mass), float(alpha0), al, sh, n, _ptr(src), _ptr(out),
+                                           float(tol), int(max_iter), ctypes.byref(dot), ctypes.byref(st),
+                                           _stream()), "stag_rational_apply")
+        return out, rc, st.to_dict(n), dot.value
+
     def cg(self, mass, shift, src: torch.Tensor, x: torch.Tensor, tol=1e-10, max_iter=100000,
            prec="f64"):
         """Single-shift CG for (M + shift) x = src from the given x (overwritten)."""
@@ -232,6 +252,19 @@ class Net:
         _check(_L.stag_net_train_step(self._h, lat._h, _ptr(b), _ptr(x), int(b.shape[0]), float(lr),
                                       _MIX.get(mode, mode), ctypes.byref(loss), _stream()), "stag_net_train_step")
         return loss.value
+
+
+def zolotarev(power, lo, hi, n):
+    """Zolotarev's optimal relative approximation of x^(-1/2) (power -1) or
+    x^(1/2) (power +1) on [lo, hi] with n poles: (alpha0, alphas, shifts,
+    max relative error)."""
+    a0 = ctypes.c_double(0.0)
+    al = (ctypes.c_double * n)()
+    sh = (ctypes.c_double * n)()
+    err = ctypes.c_double(0.0)
+    _check(_L.stag_zolotarev(int(power), float(lo), float(hi), int(n), ctypes.byref(a0), al, sh,
+                             ctypes.byref(err)), "stag_zolotarev")
+    return a0.value, list(al), list(sh), err.value
 
 
 def multishift_cg_batched(systems, tol=1e-10, max_iter=100000, prec="f64", no_graph=False,

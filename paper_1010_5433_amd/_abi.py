@@ -96,6 +96,10 @@ SIGNATURES = {
     "stag_net_grad": (_i, [_v, _v, _v, _v, ctypes.POINTER(_d), _i, _v]),
     "stag_net_train_step": (_i, [_v, _v, _v, _v, _i, _d, _i, ctypes.POINTER(_d), _v]),
     "stag_fcg_solve": (_i, [_v, _d, _d, _v, _v, _v, _i, _d, _i, ctypes.POINTER(CgStats), _v]),
+    "stag_rational_apply": (_i, [_v, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d), _i, _v, _v, _d, _i,
+                                 ctypes.POINTER(_d), ctypes.POINTER(CgStats), _v]),
+    "stag_zolotarev": (_i, [_i, _d, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
+                            ctypes.POINTER(_d)]),
     "stag_hbm_probe": (_i, [_v, _v, ctypes.c_int64, _i, _v]),
     "stag_status_string": (ctypes.c_char_p, [_i]),
     "stag_last_error": (ctypes.c_char_p, []),

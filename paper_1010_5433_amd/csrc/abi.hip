@@ -41,6 +41,11 @@ stag_status multishift_cg(stag_lattice *lat, double mass, const double *shifts, 
                           hipStream_t s);
 stag_status single_cg(stag_lattice *lat, double mass, double shift, const void *src, void *x, double tol,
                       int max_iter, stag_prec prec, stag_cg_stats *stats, hipStream_t s);
+stag_status rational_apply(stag_lattice *lat, double mass, double alpha0, const double *alphas, const double *shifts,
+                           int n, const void *src, void *out, double tol, int max_iter, double *dot,
+                           stag_cg_stats *stats, hipStream_t s);
+stag_status zolotarev(int power, double lo, double hi, int n, double *alpha0, double *alphas, double *shifts,
+                      double *delta_out);
 
 static stag_status use_device(const stag_lattice *lat) {
     int dev = -1;
@@ -248,6 +253,42 @@ stag_status stag_multishift_cg(stag_lattice *lat, double mass, const double *shi
         }
         return multishift_cg(lat, mass, shifts, n_shifts, src, sols, tol, max_iter, prec, stats,
                              static_cast<hipStream_t>(stream));
+    } catch (...) {
+        set_error("host allocation failed");
+        return STAG_ENOMEM;
+    }
+}
+
+stag_status stag_rational_apply(stag_lattice *lat, double mass, double alpha0, const double *alphas,
+                                const double *shifts, int n, const void *src, void *out, double tol, int max_iter,
+                                double *dot, stag_cg_stats *stats, void *stream) {
+    try {
+        STAG_TRY(check_lattice(lat, true));
+        STAG_TRY(check_solver_args(mass, tol, max_iter, STAG_F64));
+        if (!alphas || !shifts || !src || !out) return invalid("null argument");
+        if (out == src) return invalid("out aliases the source");
+        if (n < 1 || n > STAG_MAX_SHIFTS) return invalid("n must be in [1, 64]");
+        if (!std::isfinite(alpha0)) return invalid("alpha0 must be finite");
+        for (int i = 0; i < n; ++i) {
+            if (!(shifts[i] >= 0) || !std::isfinite(shifts[i])) return invalid("shifts must be >= 0 and finite");
+            if (!std::isfinite(alphas[i])) return invalid("alphas must be finite");
+        }
+        return rational_apply(lat, mass, alpha0, alphas, shifts, n, src, out, tol, max_iter, dot, stats,
+                              static_cast<hipStream_t>(stream));
+    } catch (...) {
+        set_error("host allocation failed");
+        return STAG_ENOMEM;
+    }
+}
+
+stag_status stag_zolotarev(int power, double lo, double hi, int n, double *alpha0, double *alphas, double *shifts,
+                           double *max_rel_err) {
+    if (power != -1 && power != 1) return invalid("power must be -1 (x^-1/2) or +1 (x^1/2)");
+    if (!(lo > 0) || !(hi > lo) || !std::isfinite(hi)) return invalid("need 0 < lo < hi");
+    if (n < 1 || n > STAG_MAX_SHIFTS) return invalid("n must be in [1, 64]");
+    if (!alpha0 || !alphas || !shifts) return invalid("null argument");
+    try {
+        return zolotarev(power, lo, hi, n, alpha0, alphas, shifts, max_rel_err);
     } catch (...) {
         set_error("host allocation failed");
         return STAG_ENOMEM;

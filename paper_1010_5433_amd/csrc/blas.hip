@@ -147,14 +147,18 @@ __global__ void __launch_bounds__(kBlasBlock) k_dir_update(const MsState *st, co
 }
 
 // Coefficients of a deferred pass (one wave, lane = shift).
-__global__ void __launch_bounds__(kWave) k_defer_coef(MsState *st, DeferHist *h) { defer_coef_step(st->n, h); }
+__global__ void __launch_bounds__(kWave) k_defer_coef(MsState *st, DeferHist *h) {
+    defer_coef_step(st->n, h, st->rat ? st->wgt : nullptr);
+}
 
 // The deferred pass: for every shift changed in the block,
 // x_i += cx0 p_i + sum_m cx_m r_m and p_i = cp0 p_i + sum_m cp_m r_m,
-// the block's residuals read once for all shifts.
-template <typename R>
+// the block's residuals read once for all shifts.  RAT: the (weighted)
+// increments of all shifts go into one output vector instead.
+template <typename R, bool RAT>
 __global__ void __launch_bounds__(kBlasBlock) k_defer_apply(const MsState *st, const DeferHist *h, const T2<R> *ring,
-                                                         int64_t slot, ShiftPtrs ptrs, int n_shift, int64_t n) {
+                                                         int64_t slot, ShiftPtrs ptrs, int n_shift, int64_t n,
+                                                         T2<R> *out) {
     const int nv = h->nvalid;
     if (nv == 0) return;
     for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
@@ -168,17 +172,43 @@ __global__ void __launch_bounds__(kBlasBlock) k_defer_apply(const MsState *st, c
                 rr[m].y = R(0);
             }
         }
+        T2<R> acc;
+        if (RAT) acc = out[j];
         for (int i = 0; i < n_shift; ++i) {
             if (!h->act[i]) continue;
             T2<R> *pi = static_cast<T2<R> *>(ptrs.p[i]);
-            T2<R> *xi = static_cast<T2<R> *>(ptrs.x[i]);
             T2<R> pv = pi[j];
-            T2<R> xv = xi[j];
-            defer_combine<T2<R>, R>(h, i, rr, xv, pv);
-            xi[j] = xv;
+            if (RAT) {
+                defer_combine<T2<R>, R>(h, i, rr, acc, pv);
+            } else {
+                T2<R> *xi = static_cast<T2<R> *>(ptrs.x[i]);
+                T2<R> xv = xi[j];
+                defer_combine<T2<R>, R>(h, i, rr, xv, pv);
+                xi[j] = xv;
+            }
             pi[j] = pv;
         }
+        if (RAT) out[j] = acc;
     }
+}
+
+__global__ void __launch_bounds__(kBlasBlock) k_scale(const double2 *b, double c, double2 *out, int64_t n) {
+    for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
+        const double2 v = b[j];
+        out[j] = make_double2(c * v.x, c * v.y);
+    }
+}
+
+__global__ void __launch_bounds__(kBlasBlock) k_dot_re(const double2 *a, const double2 *b, int64_t n,
+                                                    double *partial) {
+    __shared__ double red[kBlasBlock / kWave];
+    double part = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
+        const double2 u = a[j], v = b[j];
+        part += u.x * v.x + u.y * v.y;
+    }
+    const double s = block_sum(part, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
 __global__ void __launch_bounds__(kBlasBlock) k_x_flush(const MsState *st, ShiftPtrs hi, ShiftPtrs lo, int n_shift,
@@ -257,6 +287,8 @@ __global__ void __launch_bounds__(kTailBlock) k_reduce_tail(MsState *st, const d
         }
     } else if (kind == TAIL_TRUE_RESID) {
         if (threadIdx.x == 0) st->resid_true[idx] = st->bnorm2 > 0.0 ? sqrt(total / st->bnorm2) : sqrt(total);
+    } else if (kind == TAIL_SCRATCH) {
+        if (threadIdx.x == 0) st->scratch[idx] = total;
     }
 }
 
@@ -301,10 +333,26 @@ hipError_t launch_dir_update(bool dbl, MsState *st, const void *r, void *pd, int
 }
 
 hipError_t launch_defer_pass(bool dbl, MsState *st, DeferHist *h, const void *ring, int64_t slot_elems, ShiftPtrs ptrs,
-                             int n_shift, int64_t n, int grid, hipStream_t s) {
+                             int n_shift, int64_t n, int grid, hipStream_t s, void *out) {
     hipLaunchKernelGGL(k_defer_coef, dim3(1), dim3(kWave), 0, s, st, h);
-    if (dbl) hipLaunchKernelGGL(k_defer_apply<double>, dim3(grid), dim3(kBlasBlock), 0, s, (const MsState *)st, (const DeferHist *)h, static_cast<const double2 *>(ring), slot_elems, ptrs, n_shift, n);
-    else hipLaunchKernelGGL(k_defer_apply<float>, dim3(grid), dim3(kBlasBlock), 0, s, (const MsState *)st, (const DeferHist *)h, static_cast<const float2 *>(ring), slot_elems, ptrs, n_shift, n);
+    if (out) {
+        if (!dbl) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_defer_apply<double, true>), dim3(grid), dim3(kBlasBlock), 0, s, (const MsState *)st, (const DeferHist *)h, static_cast<const double2 *>(ring), slot_elems, ptrs, n_shift, n, static_cast<double2 *>(out));
+    } else if (dbl) {
+        hipLaunchKernelGGL((k_defer_apply<double, false>), dim3(grid), dim3(kBlasBlock), 0, s, (const MsState *)st, (const DeferHist *)h, static_cast<const double2 *>(ring), slot_elems, ptrs, n_shift, n, (double2 *)nullptr);
+    } else {
+        hipLaunchKernelGGL((k_defer_apply<float, false>), dim3(grid), dim3(kBlasBlock), 0, s, (const MsState *)st, (const DeferHist *)h, static_cast<const float2 *>(ring), slot_elems, ptrs, n_shift, n, (float2 *)nullptr);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(const double2 *b, double c, double2 *out, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale, dim3(blas_grid(n)), dim3(kBlasBlock), 0, s, b, c, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot_re(const double2 *a, const double2 *b, int64_t n, double *partial, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot_re, dim3(grid), dim3(kBlasBlock), 0, s, a, b, n, partial);
     return hipGetLastError();
 }
 

@@ -47,6 +47,11 @@ struct ShiftedSolve {
     int max_iter;
     bool dbl_iter;            // double precision iterations
     int reliable_every;       // 0: no reliable updates
+    // rational application (double precision, zero start): rat_out =
+    // rat_w0 src + sum_i rat_w[i] x_i, with no x_i stored (x_hi unused)
+    const double *rat_w = nullptr;
+    double rat_w0 = 0.0;
+    void *rat_out = nullptr;
 };
 
 struct ShiftedResult {
@@ -56,6 +61,7 @@ struct ShiftedResult {
     int iters_shift[kMaxShifts];
     double resid_iter[kMaxShifts];
     double resid_true[kMaxShifts];
+    double dot;               // rational application: Re <src, out>
 };
 
 static constexpr int kChunk = 8;   // iterations enqueued between flag reads
@@ -76,7 +82,12 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
     const double sigma0 = sp.shifts[base];
 
     // deferred shift updates (see the top of the file)
-    const bool defer = !sp.x_init && n >= 2;
+    const bool rat = sp.rat_out != nullptr;
+    if (rat && (!dbl || sp.x_init || sp.reliable_every)) {
+        set_error("the rational application runs in double precision from a zero start");
+        return STAG_EINVAL;
+    }
+    const bool defer = rat || (!sp.x_init && n >= 2);
     const int dlen = dbl ? kDefer : 8;   // iterations per deferred block
     static_assert(kDefer >= 8 && kReliableCheck % 8 == 0, "deferred block lengths");
     if (defer && sp.reliable_every % dlen != 0) {
@@ -112,9 +123,9 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
     std::memset(&lo_ptrs, 0, sizeof(lo_ptrs));
     for (int i = 0; i < n; ++i) {
         it_ptrs.p[i] = static_cast<char *>(P) + vb * i;
-        hi_ptrs.x[i] = sp.x_hi[i];
+        hi_ptrs.x[i] = rat ? nullptr : sp.x_hi[i];
         if (!dbl) lo_ptrs.x[i] = static_cast<char *>(XLO) + (size_t)vec_bytes(lat, false) * i;
-        it_ptrs.x[i] = dbl ? sp.x_hi[i] : lo_ptrs.x[i];
+        it_ptrs.x[i] = rat ? nullptr : dbl ? sp.x_hi[i] : lo_ptrs.x[i];
     }
     // the direction the operator acts on: the base shift's own p, or (deferred)
     // a separate vector kept current every iteration
@@ -129,6 +140,9 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
     hs.max_iter = sp.max_iter;
     hs.rel_delta2 = sp.reliable_every > 0 ? kReliableDelta * kReliableDelta : 0.0;
     hs.hist = defer ? hist : nullptr;   // its record is emptied by the start step
+    hs.rat = rat ? 1 : 0;
+    if (rat)
+        for (int i = 0; i < n; ++i) hs.wgt[i] = sp.rat_w[i];
     for (int i = 0; i < n; ++i) hs.shift_rel[i] = sp.shifts[i] - sigma0;
     STAG_HIP(hipMemcpyAsync(st, &hs, sizeof(hs), hipMemcpyHostToDevice, s));
 
@@ -161,7 +175,10 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
     // ---------------------------------------------------------------- start
     if (!sp.x_init) {
         // r^0 = b sits where iteration 0 reads it (slot dlen - 1 of the ring)
-        STAG_HIP(launch_ms_start(dbl, static_cast<const double2 *>(sp.src), rslot(-1), it_ptrs, n, true, ne, s));
+        STAG_HIP(launch_ms_start(dbl, static_cast<const double2 *>(sp.src), rslot(-1), it_ptrs, n, !rat, ne, s));
+        if (rat)
+            STAG_HIP(launch_scale(static_cast<const double2 *>(sp.src), sp.rat_w0, static_cast<double2 *>(sp.rat_out),
+                                  ne, s));
         if (defer) STAG_HIP(hipMemcpyAsync(pbase, rslot(-1), vb, hipMemcpyDeviceToDevice, s));
         if (!dbl)
             for (int i = 0; i < n; ++i) STAG_HIP(hipMemsetAsync(sp.x_hi[i], 0, vb64, s));
@@ -197,7 +214,7 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
         if (defer) {
             STAG_HIP(launch_dir_update(dbl, st, rslot(k), pbase, ne, bl_grid, s));
             if ((k + 1) % dlen == 0)
-                STAG_HIP(launch_defer_pass(dbl, st, hist, R, ne, it_ptrs, n, ne, bl_grid, s));
+                STAG_HIP(launch_defer_pass(dbl, st, hist, R, ne, it_ptrs, n, ne, bl_grid, s, sp.rat_out));
         } else {
             STAG_HIP(launch_shift_update(dbl, st, R, it_ptrs, n, ne, bl_grid, s));
         }
@@ -247,15 +264,23 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
 
     // ---------------------------------------------------------------- finish
     // the last block may end between passes (a no-op when it does not)
-    if (defer) STAG_HIP(launch_defer_pass(dbl, st, hist, R, ne, it_ptrs, n, ne, bl_grid, s));
+    if (defer) STAG_HIP(launch_defer_pass(dbl, st, hist, R, ne, it_ptrs, n, ne, bl_grid, s, sp.rat_out));
     if (!dbl) STAG_HIP(launch_x_flush(st, hi_ptrs, lo_ptrs, n, ne, false, s));
-    for (int i = 0; i < n; ++i) {
-        STAG_HIP(true_residual(sp.x_hi[i], sp.shifts[i], nullptr, part0, nullptr));
-        STAG_HIP(launch_reduce_tail(st, part0, ds_grid, TAIL_TRUE_RESID, i, s));
+    if (rat) {
+        // no solutions are kept: report Re <src, out> instead of true residuals
+        STAG_HIP(launch_dot_re(static_cast<const double2 *>(sp.src), static_cast<const double2 *>(sp.rat_out), ne,
+                               part0, bl_grid, s));
+        STAG_HIP(launch_reduce_tail(st, part0, bl_grid, TAIL_SCRATCH, 0, s));
+    } else {
+        for (int i = 0; i < n; ++i) {
+            STAG_HIP(true_residual(sp.x_hi[i], sp.shifts[i], nullptr, part0, nullptr));
+            STAG_HIP(launch_reduce_tail(st, part0, ds_grid, TAIL_TRUE_RESID, i, s));
+        }
     }
     STAG_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
     STAG_HIP(hipStreamSynchronize(s));
     res->status = hs.status;
+    res->dot = hs.scratch[0];
     res->iters = hs.iter;
     res->n_reliable = hs.n_reliable;
     for (int i = 0; i < n; ++i) {
@@ -358,6 +383,40 @@ stag_status multishift_cg(stag_lattice *lat, double mass, const double *shifts, 
     }
     st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = st;
+    return rc;
+}
+
+stag_status rational_apply(stag_lattice *lat, double mass, double alpha0, const double *alphas, const double *shifts,
+                           int n, const void *src, void *out, double tol, int max_iter, double *dot,
+                           stag_cg_stats *stats, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    ShiftedSolve sp;
+    sp.mass = mass;
+    sp.n = n;
+    sp.shifts = shifts;
+    sp.src = src;
+    sp.x_hi = nullptr;
+    sp.x_init = false;
+    sp.tol = tol;
+    sp.max_iter = max_iter;
+    sp.dbl_iter = true;
+    sp.reliable_every = 0;
+    sp.rat_w = alphas;
+    sp.rat_w0 = alpha0;
+    sp.rat_out = out;
+    ShiftedResult r;
+    STAG_TRY(run_shifted(lat, sp, &r, s));
+    const stag_status rc = status_of(r.status);
+    if (dot) *dot = r.dot;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->iters = r.iters;
+        for (int i = 0; i < n; ++i) {
+            stats->iters_shift[i] = r.iters_shift[i];
+            stats->resid_iter[i] = r.resid_iter[i];
+        }
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
     return rc;
 }
 

@@ -143,8 +143,9 @@ __device__ __forceinline__ void ms_beta_step(MsState *st, double rho_new) {
 // lanes 0..n-1 of one workgroup).  Starting from p = p_i (index 0), every
 // recorded iteration j at which shift i was updated does x += a_j p, then
 // p = b_j p + z_j r^{k0+1+j} (index 1 + j).  Resets the record.  Every
-// thread of the workgroup must call it.
-__device__ __forceinline__ void defer_coef_step(int n, DeferHist *h) {
+// thread of the workgroup must call it.  With weights w (rational
+// application) the x coefficients of shift i are scaled by w[i].
+__device__ __forceinline__ void defer_coef_step(int n, DeferHist *h, const double *w = nullptr) {
     const int l = threadIdx.x;
     const int len = h->len;
     const int nv = len < kDefer ? len : kDefer;
@@ -167,9 +168,10 @@ __device__ __forceinline__ void defer_coef_step(int n, DeferHist *h) {
             }
             cp[1 + j] += h->z[j][l];
         }
+        const double wl = w ? w[l] : 1.0;
 #pragma unroll
         for (int q = 0; q <= kDefer; ++q) {
-            h->cx[l][q] = cx[q];
+            h->cx[l][q] = wl * cx[q];
             h->cp[l][q] = cp[q];
         }
         h->act[l] = any;
@@ -207,7 +209,8 @@ enum TailKind {
     TAIL_ALPHA = 1,      // total = <p, A p>: alpha and zeta; retires the update flag once done
     TAIL_BETA = 2,       // total = |r|^2: beta, shift coefficients, freeze tests
     TAIL_RELIABLE = 3,   // total = ||b - A x||^2 after a reliable update
-    TAIL_TRUE_RESID = 4  // total = ||b - (M + sigma_i) x_i||^2 of shift idx
+    TAIL_TRUE_RESID = 4, // total = ||b - (M + sigma_i) x_i||^2 of shift idx
+    TAIL_SCRATCH = 5     // total into scratch[idx]
 };
 
 }  // namespace stag

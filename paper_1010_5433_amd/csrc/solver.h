@@ -51,13 +51,15 @@ struct MsState {
     int upd_p;           // the base direction is updated this iteration
     int n_reliable;
     int rel_skip;        // 1: the reliable-update kernels of this iteration are no-ops
-    int pad[2];
+    int rat;             // rational application: the deferred passes weight shift i by wgt[i]
+    int pad;
     DeferHist *hist;     // non-null: the scalar steps record per-iteration coefficients
     double shift_rel[kMaxShifts];   // s_i = sigma_i - sigma_base
     double zeta[kMaxShifts], zeta_prev[kMaxShifts], zeta_next[kMaxShifts];
     double a[kMaxShifts], b[kMaxShifts];
     double resid_iter[kMaxShifts];
     double resid_true[kMaxShifts];
+    double wgt[kMaxShifts];         // weights of the rational application
     int active[kMaxShifts];
     int upd[kMaxShifts];
     int iters_shift[kMaxShifts];
@@ -86,8 +88,15 @@ hipError_t launch_r_update(bool dbl, MsState *st, const void *rin, void *r, cons
 // over every shift changed in it.  ring: one residual vector per iteration
 // of the block, slot m holding r^{k0+1+m}.
 hipError_t launch_dir_update(bool dbl, MsState *st, const void *r, void *pd, int64_t n, int grid, hipStream_t s);
+// out == nullptr: x_i += ... for every shift; otherwise (rational
+// application, double precision) out += sum_i wgt_i (x_i increment) and no
+// x_i is kept.
 hipError_t launch_defer_pass(bool dbl, MsState *st, DeferHist *h, const void *ring, int64_t slot_elems, ShiftPtrs ptrs,
-                             int n_shift, int64_t n, int grid, hipStream_t s);
+                             int n_shift, int64_t n, int grid, hipStream_t s, void *out = nullptr);
+// out = c * b (double precision)
+hipError_t launch_scale(const double2 *b, double c, double2 *out, int64_t n, hipStream_t s);
+// partials of Re <a, b> (double precision), one per block of `grid`
+hipError_t launch_dot_re(const double2 *a, const double2 *b, int64_t n, double *partial, int grid, hipStream_t s);
 hipError_t launch_shift_update(bool dbl, MsState *st, const void *r, ShiftPtrs ptrs, int n_shift, int64_t n, int grid,
                                hipStream_t s);
 // One workgroup sums nparts partials (fixed order) and applies a TailKind step.

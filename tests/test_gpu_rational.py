@@ -1,0 +1,137 @@
+"""GPU parity of the rational-function application (C ABI) with the FP64
+oracle, and properties of Zolotarev's approximations at full size.
+
+Tolerances: the library and the oracle each stop shift i at
+|zeta_i| ||r|| <= tol ||b||, so each result lies within
+tol ||b|| sum_i |alpha_i| / (m^2 + s_i) of r(M) b (in exact arithmetic); the
+two may differ by twice that, plus FP64 rounding (1e-13 relative).
+"""
+import numpy as np
+import pytest
+
+import stag_synth as syn
+from tests import lattice_np as ln
+from tests.gpu_common import lattice_with_links, links_np, log, pack, rel, unpack
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1010_5433_amd  # noqa: F401
+
+
+def _bound(b, mass, alphas, shifts, tol):
+    return tol * np.linalg.norm(b) * sum(abs(a) / (mass * mass + s) for a, s in zip(alphas, shifts))
+
+
+CASES = [((4, 4, 4, 4), "haar", "18", 0.1, 11), ((4, 4, 2, 6), "smooth", "12", 0.05, 12),
+         ((8, 8, 8, 8), "smooth", "8", 0.02, 13), ((6, 4, 2, 8), "haar", "18", 0.2, 14)]
+
+
+@pytest.mark.parametrize("dims,kind,fmt,mass,seed", CASES)
+def test_rational_apply_vs_oracle(orc, dims, kind, fmt, mass, seed):
+    log(f"rational apply {dims} {kind} fmt={fmt} m={mass}")
+    rng = np.random.default_rng(seed)
+    U = links_np(dims, kind, 0.5, seed)
+    b = syn.gaussian_source(dims, seed + 100)
+    n = 6
+    shifts = list(np.sort(rng.uniform(0.0, 2.0, n)))
+    alphas = list(rng.normal(size=n))
+    alpha0 = float(rng.normal())
+    tol = 1e-10
+    lat = lattice_with_links(dims, U, fmt)
+    out, rc, st, dot = lat.rational_apply(mass, alpha0, alphas, shifts, pack(lat, b), tol=tol)
+    want, rco, info = orc.rational_apply(dims, U, mass, alpha0, alphas, shifts, b, tol=tol)
+    assert rc == 0 and rco == 0
+    assert abs(st["iters"] - info["iters"]) <= 1
+    got = unpack(lat, out)
+    err = np.linalg.norm(got - want)
+    assert err <= 2 * _bound(b, mass, alphas, shifts, tol) + 1e-13 * np.linalg.norm(want), err
+    assert abs(dot - info["dot"]) <= 1e-9 * abs(info["dot"]) + 1e-12 * np.linalg.norm(b) ** 2
+
+
+@pytest.mark.parametrize("max_iter", [5, 16, 21])
+def test_rational_apply_stops_inside_a_block(orc, max_iter):
+    """The weighted solutions are summed once per block of 16 iterations; a
+    solve stopped by the iteration limit returns the sum at that iteration."""
+    import paper_1010_5433_amd as stag
+    dims = (4, 4, 4, 4)
+    U = syn.haar_links(dims, 61)
+    b = syn.gaussian_source(dims, 62)
+    alpha0, alphas, shifts = 0.5, [1.0, -0.3, 0.2], [0.0, 0.2, 1.0]
+    lat = lattice_with_links(dims, U)
+    out, rc, st, dot = lat.rational_apply(0.1, alpha0, alphas, shifts, pack(lat, b), max_iter=max_iter)
+    want, rco, info = orc.rational_apply(dims, U, 0.1, alpha0, alphas, shifts, b, max_iter=max_iter)
+    assert rc == stag._abi.STAG_ENOCONV and rco == 1
+    assert st["iters"] == info["iters"] == max_iter
+    assert rel(unpack(lat, out), want) <= 1e-12
+
+
+def test_rational_inverse_square_root_dense(orc):
+    """Zolotarev's x^(-1/2) on [m^2, m^2 + 16] applied on the GPU equals
+    M^(-1/2) b from the dense eigen-decomposition within its error."""
+    import paper_1010_5433_amd as stag
+    dims, m = (4, 4, 2, 2), 0.1
+    U = syn.haar_links(dims, 31)
+    b = syn.gaussian_source(dims, 32)
+    vh = int(np.prod(dims)) // 2
+    M = ln.dense_normal_matrix(lambda v: orc.normal_op(dims, U, m, 0.0, v), 3 * vh)
+    w, V = np.linalg.eigh(M)
+    exact = (V @ ((V.conj().T @ b.ravel()) / np.sqrt(w))).reshape(b.shape)
+    a0, al, sh, err = stag.zolotarev(-1, m * m, m * m + 16.0, 16)
+    lat = lattice_with_links(dims, U)
+    out, rc, st, dot = lat.rational_apply(m, a0, al, sh, pack(lat, b), tol=1e-13)
+    assert rc == 0
+    assert rel(unpack(lat, out), exact) <= err + 1e-11
+    action = np.vdot(b, exact).real
+    assert abs(dot - action) <= (err + 1e-11) * action
+
+
+@pytest.mark.parametrize("dims,fmt", [((8, 8, 8, 8), "12"), ((32, 32, 32, 32), "8")])
+def test_heatbath_then_action_is_identity(dims, fmt):
+    """r_-(r_+(b)) with r_+ ~ M^(1/2), r_- ~ M^(-1/2) (same poles) returns b to
+    within the two approximation errors: a property that holds at any size,
+    checked here also at the 32^4 size the benchmark times."""
+    import paper_1010_5433_amd as stag
+    log(f"heatbath/action round trip {dims}")
+    m = 0.01 if dims[0] == 32 else 0.05
+    U = links_np(dims, "smooth", 0.5, 301 if dims[0] == 32 else 7)
+    b = syn.gaussian_source(dims, 302)
+    lat = lattice_with_links(dims, U, fmt)
+    lo, hi = m * m, m * m + 16.0
+    ap0, apl, sh, errp = stag.zolotarev(1, lo, hi, 24)
+    am0, aml, sh2, errm = stag.zolotarev(-1, lo, hi, 24)
+    src = pack(lat, b)
+    half, rc1, st1, _ = lat.rational_apply(m, ap0, apl, sh, src, tol=1e-12)
+    back, rc2, st2, action = lat.rational_apply(m, am0, aml, sh2, half, tol=1e-12)
+    assert rc1 == 0 and rc2 == 0
+    log(f"  errors {errp:.1e} {errm:.1e}; iterations {st1['iters']} {st2['iters']}; "
+        f"round trip {rel(unpack(lat, back), b):.2e}")
+    assert rel(unpack(lat, back), b) <= 2 * (errp + errm) + 1e-9
+    # <r_+ b, r_- r_+ b> = <r_+ b, b> ~ <b, M^(1/2) b>
+    assert abs(action - np.vdot(unpack(lat, half), b).real) <= 1e-8 * abs(action)
+
+
+def test_rational_apply_edge_cases():
+    import torch
+    import paper_1010_5433_amd as stag
+    dims = (4, 4, 4, 4)
+    lat = lattice_with_links(dims, syn.haar_links(dims, 1))
+    zero = pack(lat, np.zeros((128, 3), np.complex128))
+    out, rc, st, dot = lat.rational_apply(0.1, 2.0, [1.0, 0.5], [0.0, 0.3], zero)
+    torch.cuda.synchronize()
+    assert rc == 0 and st["iters"] == 0 and dot == 0.0
+    assert float(out.abs().max()) == 0.0
+    src = pack(lat, syn.gaussian_source(dims, 2))
+    for bad in [dict(mass=-0.1), dict(shifts=[-1.0, 0.0]), dict(alphas=[float("nan"), 1.0]),
+                dict(alphas=[], shifts=[])]:
+        kw = dict(mass=0.1, alpha0=0.0, alphas=[1.0, 1.0], shifts=[0.0, 0.5])
+        kw.update(bad)
+        with pytest.raises(stag.StagError):
+            lat.rational_apply(kw["mass"], kw["alpha0"], kw["alphas"], kw["shifts"], src)
+    with pytest.raises(stag.StagError):
+        lat.rational_apply(0.1, 0.0, [1.0], [0.0], src, out=src)
