@@ -180,6 +180,7 @@ def rational_experiment(lat, mass, src, tol, n_poles):
     out = {"poles": n_poles, "range": [lo, hi]}
     for name, power in (("heatbath_sqrt", 1), ("action_inv_sqrt", -1)):
         a0, al, sh, err = stag.zolotarev(power, lo, hi, n_poles)
+        out.setdefault("coefficients", {})[name] = "Zolotarev"
         res = torch.empty_like(src)
         lat.rational_apply(mass, a0, al, sh, src, out=res, tol=tol)   # warm-up
         torch.cuda.synchronize()
@@ -206,6 +207,23 @@ def rational_experiment(lat, mass, src, tol, n_poles):
             f"max rel. approximation error {err:.1e}; results differ by {diff:.1e}")
         out[name] = dict(seconds=round(t_rat, 4), iters=st["iters"], multishift_then_sum_s=round(t_ms, 4),
                          max_rel_err=err, rel_diff_vs_multishift=diff, re_src_dot_out=dot)
+    # two flavours: heatbath phi = M^(1/4) xi (Remez, 20 poles), then the
+    # action <phi, M^(-1/2) phi>, which must equal <xi, xi>
+    h0, hl, hs, herr = stag.rational_power(0.25, lo, hi, 20)
+    s0, sl, ss, serr = stag.zolotarev(-1, lo, hi, n_poles)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi, rc1, st1, _ = lat.rational_apply(mass, h0, hl, hs, src, tol=tol)
+    t_h = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, rc2, st2, action = lat.rational_apply(mass, s0, sl, ss, phi, tol=tol)
+    t_a = time.perf_counter() - t0
+    xx = float((src.double() * src.double()).sum())
+    log(f"two-flavour heatbath M^(1/4) {t_h:.4f} s, action {t_a:.4f} s; S / <xi,xi> - 1 = {action / xx - 1:.2e} "
+        f"(approximation errors {herr:.1e}, {serr:.1e})")
+    out["two_flavour"] = dict(heatbath_quarter_s=round(t_h, 4), heatbath_poles=20, heatbath_max_rel_err=herr,
+                              action_s=round(t_a, 4), action_over_xi2_minus_1=action / xx - 1,
+                              iters=[st1["iters"], st2["iters"]])
     return out
 
 

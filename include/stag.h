@@ -252,6 +252,19 @@ stag_status stag_rational_apply(stag_lattice *lat, double mass, double alpha0, c
 stag_status stag_zolotarev(int power, double lo, double hi, int n, double *alpha0, double *alphas,
                            double *shifts, double *max_rel_err);
 
+/* Best relative rational approximation of x^power on [lo, hi] for power in
+ * (-1, 0) or (0, 1) (M^(1/4) for the two-flavour heatbath, M^(-1/4),
+ * M^(1/8), ...), same output convention as stag_zolotarev.  Negative powers
+ * get type (n-1, n) (alpha0 = 0, residues > 0); positive powers q use
+ * x^q = x * x^(q-1) (alpha0 > 0, residues < 0).  +-1/2 is Zolotarev's
+ * closed form; other powers come from Remez's exchange algorithm, continued
+ * in the power from that closed form (1 <= n <= 24).  Once the error falls
+ * below 1e-12 the coefficients are returned as they stand (double precision
+ * rounding leaves no alternation to resolve); STAG_EINVAL if the iteration
+ * fails to converge above that level.  Host computation. */
+stag_status stag_rational_power(double power, double lo, double hi, int n, double *alpha0, double *alphas,
+                                double *shifts, double *max_rel_err);
+
 /* ------------------------------------------------------------------ learned preconditioner
  * Not part of the paper: an extension that preconditions the double
  * precision single-shift solve of the Metropolis step (Section 4 keeps that

@@ -20,7 +20,7 @@ from ._abi import (F32, F64, MIXED, LINK8, LINK12, LINK18, MIX_BF16, MIX_FOLDED,
                    System, batch_flags, load_library, status_name)
 
 __all__ = ["Lattice", "CgStats", "StagError", "F64", "F32", "MIXED", "LINK18", "LINK12",
-           "library_path", "vec_empty", "multishift_cg_batched", "batch_last_config", "Net", "zolotarev",
+           "library_path", "vec_empty", "multishift_cg_batched", "batch_last_config", "Net", "zolotarev", "rational_power",
            "NET_NPARAM"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -264,6 +264,18 @@ def zolotarev(power, lo, hi, n):
     err = ctypes.c_double(0.0)
     _check(_L.stag_zolotarev(int(power), float(lo), float(hi), int(n), ctypes.byref(a0), al, sh,
                              ctypes.byref(err)), "stag_zolotarev")
+    return a0.value, list(al), list(sh), err.value
+
+
+def rational_power(power, lo, hi, n):
+    """Best relative approximation of x^power (power in (-1, 0) or (0, 1)) on
+    [lo, hi] with n poles: (alpha0, alphas, shifts, max relative error)."""
+    a0 = ctypes.c_double(0.0)
+    al = (ctypes.c_double * n)()
+    sh = (ctypes.c_double * n)()
+    err = ctypes.c_double(0.0)
+    _check(_L.stag_rational_power(float(power), float(lo), float(hi), int(n), ctypes.byref(a0), al, sh,
+                                  ctypes.byref(err)), "stag_rational_power")
     return a0.value, list(al), list(sh), err.value
 
 

@@ -100,6 +100,8 @@ SIGNATURES = {
                                  ctypes.POINTER(_d), ctypes.POINTER(CgStats), _v]),
     "stag_zolotarev": (_i, [_i, _d, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
                             ctypes.POINTER(_d)]),
+    "stag_rational_power": (_i, [_d, _d, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
+                                 ctypes.POINTER(_d)]),
     "stag_hbm_probe": (_i, [_v, _v, ctypes.c_int64, _i, _v]),
     "stag_status_string": (ctypes.c_char_p, [_i]),
     "stag_last_error": (ctypes.c_char_p, []),

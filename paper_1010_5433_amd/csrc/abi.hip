@@ -46,6 +46,8 @@ stag_status rational_apply(stag_lattice *lat, double mass, double alpha0, const 
                            stag_cg_stats *stats, hipStream_t s);
 stag_status zolotarev(int power, double lo, double hi, int n, double *alpha0, double *alphas, double *shifts,
                       double *delta_out);
+stag_status rational_power(double power, double lo, double hi, int n, double *alpha0, double *alphas, double *shifts,
+                           double *delta_out);
 
 static stag_status use_device(const stag_lattice *lat) {
     int dev = -1;
@@ -289,6 +291,21 @@ stag_status stag_zolotarev(int power, double lo, double hi, int n, double *alpha
     if (!alpha0 || !alphas || !shifts) return invalid("null argument");
     try {
         return zolotarev(power, lo, hi, n, alpha0, alphas, shifts, max_rel_err);
+    } catch (...) {
+        set_error("host allocation failed");
+        return STAG_ENOMEM;
+    }
+}
+
+stag_status stag_rational_power(double power, double lo, double hi, int n, double *alpha0, double *alphas,
+                                double *shifts, double *max_rel_err) {
+    if (!(power > -1.0 && power < 1.0) || power == 0.0) return invalid("power must lie in (-1, 0) or (0, 1)");
+    if (!(lo > 0) || !(hi > lo) || !std::isfinite(hi)) return invalid("need 0 < lo < hi");
+    const int nmax = (power == 0.5 || power == -0.5) ? STAG_MAX_SHIFTS : 24;
+    if (n < 1 || n > nmax) return invalid("n must be in [1, 64] for powers +-1/2 and in [1, 24] otherwise");
+    if (!alpha0 || !alphas || !shifts) return invalid("null argument");
+    try {
+        return rational_power(power, lo, hi, n, alpha0, alphas, shifts, max_rel_err);
     } catch (...) {
         set_error("host allocation failed");
         return STAG_ENOMEM;

@@ -143,4 +143,245 @@ stag_status zolotarev(int power, double lo, double hi, int n, double *alpha0, do
     return STAG_OK;
 }
 
+// ---------------------------------------------------------------- other powers
+// Best relative approximation of y^(-p), 0 < p < 1, on [1, B] of type
+// (n-1, n), R(y) = sum_i a_i / (y + c_i), by Remez's exchange algorithm with
+// Newton steps on the 2n + 1 equations R(y_j) y_j^p - 1 = s_j E at reference
+// points y_j of alternating sign s_j (unknowns a_i, ln c_i, E), continued in
+// p from Zolotarev's solution at p = 1/2 in steps of at most 0.02.  Long
+// double throughout.
+namespace {
+
+typedef long double ld;
+
+struct RatFn {
+    std::vector<ld> a, lc;   // residues, log of the pole offsets
+};
+
+ld rel_err(ld y, ld p, const RatFn &r) {
+    ld acc = 0.0L;
+    for (size_t i = 0; i < r.a.size(); ++i) acc += r.a[i] / (y + std::exp(r.lc[i]));
+    return acc * std::pow(y, p) - 1.0L;
+}
+
+// Local extrema of the error on a grid in t = ln y, refined by golden-section
+// search, reduced to an alternating sequence (largest |e| per sign run).
+std::vector<ld> alternating_extrema(ld p, ld B, const RatFn &r, int ngrid, std::vector<ld> *vals) {
+    const ld T = std::log(B);
+    std::vector<ld> t(ngrid + 1), e(ngrid + 1);
+    for (int k = 0; k <= ngrid; ++k) {
+        t[k] = T * k / ngrid;
+        e[k] = rel_err(std::exp(t[k]), p, r);
+    }
+    std::vector<ld> pos, val;
+    auto push = [&](ld tt, ld ee) {
+        if (!val.empty() && ((ee > 0) == (val.back() > 0))) {
+            if (std::fabs(ee) > std::fabs(val.back())) {
+                pos.back() = tt;
+                val.back() = ee;
+            }
+        } else {
+            pos.push_back(tt);
+            val.push_back(ee);
+        }
+    };
+    push(t[0], e[0]);
+    const ld gr = 0.5L * (std::sqrt(5.0L) - 1.0L);
+    for (int k = 1; k < ngrid; ++k) {
+        const bool mx = e[k] >= e[k - 1] && e[k] >= e[k + 1];
+        const bool mn = e[k] <= e[k - 1] && e[k] <= e[k + 1];
+        if (!mx && !mn) continue;
+        const ld sg = mx ? 1.0L : -1.0L;
+        ld a = t[k - 1], b = t[k + 1];
+        ld x1 = b - gr * (b - a), x2 = a + gr * (b - a);
+        ld f1 = sg * rel_err(std::exp(x1), p, r), f2 = sg * rel_err(std::exp(x2), p, r);
+        for (int it = 0; it < 80 && b - a > 1e-15L * (1.0L + T); ++it) {
+            if (f1 > f2) {
+                b = x2;
+                x2 = x1;
+                f2 = f1;
+                x1 = b - gr * (b - a);
+                f1 = sg * rel_err(std::exp(x1), p, r);
+            } else {
+                a = x1;
+                x1 = x2;
+                f1 = f2;
+                x2 = a + gr * (b - a);
+                f2 = sg * rel_err(std::exp(x2), p, r);
+            }
+        }
+        push(f1 > f2 ? x1 : x2, sg * std::max(f1, f2));
+    }
+    push(t[ngrid], e[ngrid]);
+    if (vals) *vals = val;
+    return pos;
+}
+
+// Below this relative error the coefficients, stored in double precision,
+// cannot be improved further.
+constexpr ld kRoundingFloor = 1e-12L;
+
+// Newton steps on the reference equations; false if the system is singular.
+bool remez_newton(ld p, const std::vector<ld> &y, const std::vector<ld> &sg, RatFn &r, ld &E) {
+    const int n = (int)r.a.size(), m = 2 * n + 1;
+    std::vector<ld> F(m), J((size_t)m * m), du(m);
+    auto residual = [&](const RatFn &q, ld e, std::vector<ld> &out) {
+        ld worst = 0.0L;
+        for (int j = 0; j < m; ++j) {
+            out[j] = rel_err(y[j], p, q) - sg[j] * e;
+            worst = std::max(worst, std::fabs(out[j]));
+        }
+        return worst;
+    };
+    ld f0 = residual(r, E, F);
+    for (int it = 0; it < 40 && f0 > 1e-18L; ++it) {
+        for (int j = 0; j < m; ++j) {
+            const ld w = std::pow(y[j], p);
+            for (int i = 0; i < n; ++i) {
+                const ld c = std::exp(r.lc[i]), d = y[j] + c;
+                J[(size_t)j * m + i] = w / d;
+                J[(size_t)j * m + n + i] = -w * r.a[i] * c / (d * d);
+            }
+            J[(size_t)j * m + 2 * n] = -sg[j];
+            du[j] = -F[j];
+        }
+        // Gaussian elimination with partial pivoting
+        for (int c = 0; c < m; ++c) {
+            int piv = c;
+            for (int k = c + 1; k < m; ++k)
+                if (std::fabs(J[(size_t)k * m + c]) > std::fabs(J[(size_t)piv * m + c])) piv = k;
+            if (!(std::fabs(J[(size_t)piv * m + c]) > 0.0L)) return false;
+            if (piv != c) {
+                for (int k = 0; k < m; ++k) std::swap(J[(size_t)c * m + k], J[(size_t)piv * m + k]);
+                std::swap(du[c], du[piv]);
+            }
+            for (int k = c + 1; k < m; ++k) {
+                const ld f = J[(size_t)k * m + c] / J[(size_t)c * m + c];
+                if (f == 0.0L) continue;
+                for (int q = c; q < m; ++q) J[(size_t)k * m + q] -= f * J[(size_t)c * m + q];
+                du[k] -= f * du[c];
+            }
+        }
+        for (int c = m - 1; c >= 0; --c) {
+            ld acc = du[c];
+            for (int q = c + 1; q < m; ++q) acc -= J[(size_t)c * m + q] * du[q];
+            du[c] = acc / J[(size_t)c * m + c];
+        }
+        // damped update
+        ld lam = 1.0L;
+        RatFn trial = r;
+        ld Et = E, f1 = 0.0L;
+        std::vector<ld> Ft(m);
+        for (;;) {
+            for (int i = 0; i < n; ++i) {
+                trial.a[i] = r.a[i] + lam * du[i];
+                trial.lc[i] = r.lc[i] + lam * du[n + i];
+            }
+            Et = E + lam * du[2 * n];
+            f1 = residual(trial, Et, Ft);
+            if ((std::isfinite((double)f1) && f1 < f0) || lam < 1e-4L) break;
+            lam *= 0.5L;
+        }
+        if (!std::isfinite((double)f1)) return false;
+        r = trial;
+        E = Et;
+        F = Ft;
+        f0 = f1;
+    }
+    return true;
+}
+
+}  // namespace
+
+stag_status rational_power(double power, double lo, double hi, int n, double *alpha0, double *alphas, double *shifts,
+                           double *delta_out) {
+    if (power == -0.5 || power == 0.5) return zolotarev(power < 0 ? -1 : 1, lo, hi, n, alpha0, alphas, shifts, delta_out);
+    const ld B = (ld)hi / (ld)lo;
+    const ld p_target = power < 0 ? -(ld)power : 1.0L - (ld)power;   // approximate y^(-p)
+    // start: Zolotarev's y^(-1/2) on [1, B]
+    std::vector<double> za(n), zs(n);
+    double z0 = 0.0, zd = 0.0;
+    STAG_TRY(zolotarev(-1, 1.0, (double)B, n, &z0, za.data(), zs.data(), &zd));
+    RatFn r;
+    r.a.assign(za.begin(), za.end());
+    for (int i = 0; i < n; ++i) r.lc.push_back(std::log((ld)zs[i]));
+    const int m = 2 * n + 1, ngrid = 300 * m;
+    std::vector<ld> vals;
+    std::vector<ld> pos = alternating_extrema(0.5L, B, r, ngrid, &vals);
+    if ((int)pos.size() < m) return invalid("approximation of this degree is below double precision; use fewer poles");
+    while ((int)pos.size() > m) {
+        if (std::fabs(vals.front()) < std::fabs(vals.back())) {
+            pos.erase(pos.begin());
+            vals.erase(vals.begin());
+        } else {
+            pos.pop_back();
+            vals.pop_back();
+        }
+    }
+    std::vector<ld> y(m), sg(m);
+    for (int j = 0; j < m; ++j) {
+        y[j] = std::exp(pos[j]);
+        sg[j] = vals[j] > 0 ? 1.0L : -1.0L;
+    }
+    ld E = std::fabs(vals[0]);
+    const int nsteps = std::max(1, (int)std::ceil(std::fabs((double)(p_target - 0.5L)) / 0.02));
+    ld emax = 0.0L;
+    for (int step = 1; step <= nsteps; ++step) {
+        const ld p = 0.5L + (p_target - 0.5L) * step / nsteps;
+        bool ok = false;
+        for (int it = 0; it < 30; ++it) {
+            if (!remez_newton(p, y, sg, r, E)) break;
+            pos = alternating_extrema(p, B, r, ngrid, &vals);
+            ld vall = 0.0L;
+            for (ld v : vals) vall = std::max(vall, std::fabs(v));
+            if (vall < kRoundingFloor) {
+                // the error is at the level of double precision rounding of
+                // the coefficients: no alternation left to resolve
+                emax = vall;
+                ok = true;
+                break;
+            }
+            while ((int)pos.size() > m) {
+                if (std::fabs(vals.front()) < std::fabs(vals.back())) {
+                    pos.erase(pos.begin());
+                    vals.erase(vals.begin());
+                } else {
+                    pos.pop_back();
+                    vals.pop_back();
+                }
+            }
+            if ((int)pos.size() < m) break;
+            ld vmin = 1e300L, vmax = 0.0L;
+            for (int j = 0; j < m; ++j) {
+                y[j] = std::exp(pos[j]);
+                sg[j] = vals[j] > 0 ? 1.0L : -1.0L;
+                vmin = std::min(vmin, std::fabs(vals[j]));
+                vmax = std::max(vmax, std::fabs(vals[j]));
+            }
+            emax = vmax;
+            if (vmin > (1.0L - 1e-5L) * vmax) {
+                ok = true;
+                break;
+            }
+        }
+        if (!ok) return invalid("Remez iteration did not converge; use fewer poles or a narrower range");
+    }
+    // back to x = lo y: x^(-p) = lo^(-p) y^(-p) ~ sum a_i lo^(1-p) / (x + lo c_i)
+    const ld scale = std::pow((ld)lo, 1.0L - p_target);
+    ld a0 = 0.0L;
+    for (int i = 0; i < n; ++i) {
+        const ld al = r.a[i] * scale, sh = (ld)lo * std::exp(r.lc[i]);
+        if (power < 0) {
+            alphas[i] = (double)al;
+        } else {   // x^(1-p) = x * x^(-p)
+            a0 += al;
+            alphas[i] = (double)(-al * sh);
+        }
+        shifts[i] = (double)sh;
+    }
+    *alpha0 = (double)a0;
+    if (delta_out) *delta_out = (double)emax;
+    return STAG_OK;
+}
+
 }  // namespace stag

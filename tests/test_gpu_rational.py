@@ -116,6 +116,46 @@ def test_heatbath_then_action_is_identity(dims, fmt):
     assert abs(action - np.vdot(unpack(lat, half), b).real) <= 1e-8 * abs(action)
 
 
+@pytest.mark.parametrize("dims,fmt", [((8, 8, 8, 8), "12"), ((32, 32, 32, 32), "8")])
+def test_two_flavour_heatbath_and_action(dims, fmt):
+    """The RHMC start of a trajectory for two flavours: phi = M^(1/4) xi
+    (heatbath), then S = <phi, M^(-1/2) phi> equals <xi, xi> up to the two
+    approximation errors -- an identity at any size, checked also at the
+    32^4 size the benchmark times."""
+    import paper_1010_5433_amd as stag
+    m = 0.01 if dims[0] == 32 else 0.05
+    U = links_np(dims, "smooth", 0.5, 301 if dims[0] == 32 else 7)
+    xi = syn.gaussian_source(dims, 303)
+    lat = lattice_with_links(dims, U, fmt)
+    lo, hi = m * m, m * m + 16.0
+    h0, hl, hs, herr = stag.rational_power(0.25, lo, hi, 20)
+    s0, sl, ss, serr = stag.rational_power(-0.5, lo, hi, 24)
+    phi, rc1, _, _ = lat.rational_apply(m, h0, hl, hs, pack(lat, xi), tol=1e-12)
+    _, rc2, _, action = lat.rational_apply(m, s0, sl, ss, phi, tol=1e-12)
+    assert rc1 == 0 and rc2 == 0
+    xx = float(np.vdot(xi, xi).real)
+    log(f"  {dims}: S = {action:.12e}, <xi,xi> = {xx:.12e}, rel {abs(action - xx) / xx:.1e} "
+        f"(errors {herr:.1e}, {serr:.1e})")
+    assert abs(action - xx) <= (2 * herr + serr + 1e-9) * xx
+
+
+def test_quarter_power_four_times_is_the_operator():
+    """(r_1/4)^4 b = M b within four times the approximation error, with M b
+    from the library's normal operator (no rational function involved)."""
+    import paper_1010_5433_amd as stag
+    dims, m = (8, 8, 8, 8), 0.05
+    U = links_np(dims, "smooth", 0.5, 7)
+    b = syn.gaussian_source(dims, 304)
+    lat = lattice_with_links(dims, U, "18")
+    h0, hl, hs, herr = stag.rational_power(0.25, m * m, m * m + 16.0, 20)
+    v = pack(lat, b)
+    for _ in range(4):
+        v, rc, _, _ = lat.rational_apply(m, h0, hl, hs, v, tol=1e-13)
+        assert rc == 0
+    mb = unpack(lat, lat.normal_op(m, 0.0, pack(lat, b)))
+    assert rel(unpack(lat, v), mb) <= 4 * herr + 1e-9
+
+
 def test_rational_apply_edge_cases():
     import torch
     import paper_1010_5433_amd as stag

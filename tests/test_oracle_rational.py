@@ -65,6 +65,52 @@ def test_zolotarev_square_root_form(B, n):
     assert a0 > 0 and all(a < 0 for a in al)
 
 
+def _alternations(power, lo, hi, a0, al, sh, npts=200001):
+    x = lo * np.exp(np.linspace(0.0, np.log(hi / lo), npts))
+    e = (a0 + sum(a / (x + s) for a, s in zip(al, sh))) / x ** power - 1.0
+    emax = np.abs(e).max()
+    big = np.abs(e) > 0.5 * emax
+    sg, eb = np.sign(e[big]), e[big]
+    cut = np.where(np.diff(sg) != 0)[0] + 1
+    peaks = np.array([np.abs(r).max() for r in np.split(eb, cut)])
+    return emax, len(cut), peaks.min() / emax
+
+
+@pytest.mark.parametrize("power", [0.25, -0.25, 0.125, -0.75, -0.375])
+@pytest.mark.parametrize("n", [8, 14, 20])
+def test_rational_power_alternation(power, n):
+    """Remez's result for other powers: 2n sign changes between equal peaks
+    (the alternation certificate of the best approximation of its type), the
+    claimed error is the observed one, and the sign pattern of the residues
+    matches the function (x^-p: positive residues, alpha0 = 0; x^q: alpha0 > 0,
+    negative residues)."""
+    import paper_1010_5433_amd as stag
+    lo, hi = 1e-4, 16.0001
+    a0, al, sh, err = stag.rational_power(power, lo, hi, n)
+    emax, nalt, spread = _alternations(power, lo, hi, a0, al, sh)
+    assert nalt == 2 * n
+    assert spread >= 0.995
+    assert abs(emax - err) <= 1e-2 * err
+    assert all(s > 0 for s in sh)
+    if power < 0:
+        assert a0 == 0.0 and all(a > 0 for a in al)
+    else:
+        assert a0 > 0 and all(a < 0 for a in al)
+    if n > 8:
+        assert err < stag.rational_power(power, lo, hi, n - 6)[3]
+
+
+def test_rational_power_half_is_zolotarev():
+    import paper_1010_5433_amd as stag
+    assert stag.rational_power(-0.5, 0.01, 5.0, 10) == stag.zolotarev(-1, 0.01, 5.0, 10)
+    with pytest.raises(stag.StagError):
+        stag.rational_power(0.0, 0.01, 5.0, 10)
+    with pytest.raises(stag.StagError):
+        stag.rational_power(1.0, 0.01, 5.0, 10)
+    with pytest.raises(stag.StagError):
+        stag.rational_power(0.25, 0.01, 5.0, 30)
+
+
 def test_zolotarev_rejects_bad_arguments():
     import paper_1010_5433_amd as stag
     for args in [(0, 1.0, 2.0, 4), (-1, 0.0, 2.0, 4), (-1, 2.0, 1.0, 4), (-1, 1.0, 2.0, 0), (-1, 1.0, 2.0, 65)]:
