@@ -228,7 +228,7 @@ def rational_experiment(lat, mass, src, tol, n_poles):
 
 
 def learned_experiment(args, n_test_fields):
-    """Train the gauge-equivariant preconditioner on 16^4 fields and judge it
+    """Train the gauge-equivariant preconditioner on 16^4 fields and test it
     in flexible CG on held-out 32^4 fields against plain FP64 CG."""
     fmt = args.learned_fmt or args.fmt
     import numpy as np

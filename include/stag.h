@@ -337,8 +337,8 @@ stag_status stag_net_train_step(stag_net *net, stag_lattice *lat, const void *b,
  * on a single precision copy of the residual; everything else is double
  * precision.  net == NULL runs plain double precision CG.  The residual is
  * re-computed in double precision from x whenever the iterated one reaches
- * tol ||src|| (the judge); the iteration stops if it meets tol, else it
- * restarts from it.  The solver falls back to plain double precision CG,
+ * tol ||src|| (the double precision check); the iteration stops if it
+ * meets tol, else it restarts from it.  The solver falls back to plain double precision CG,
  * warm-started, when <r, P r> <= 0, a curvature is not positive or finite,
  * or the residual stalls for 50 iterations (stats->fallback_used = 1).
  * stats->iters counts both parts; stats->resid_true[0] is the final

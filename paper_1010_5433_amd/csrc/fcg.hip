@@ -12,7 +12,7 @@
 // enqueues chunks of iterations and reads a 4-byte state word one chunk
 // behind; kernels enqueued after the state left "running" return at once.
 // When the iterated residual reaches tol ||b|| the host recomputes the
-// residual b - (M + shift) x in double precision (the judge) and either
+// residual b - (M + shift) x in double precision (the final check) and either
 // stops or restarts the iteration from the true residual.  A non-positive
 // or non-finite <r, P r> or <p, A p>, or 50 iterations without a new
 // smallest residual, hand the solve to plain double precision CG from the
@@ -42,7 +42,7 @@ struct FcgState {
     double bb;          // |b|^2
     double tol2bb;      // tol^2 |b|^2
     double best;        // smallest iterated |r|^2 so far
-    double resid_true2; // |b - A x|^2 of the last judge
+    double resid_true2; // |b - A x|^2 of the last check
     int since_best;
     int iter;
     int max_iter;
@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(kFcgBlock) k_fcg_init(FcgState *st, const doub
     }
 }
 
-// after r = b - A x: |r|^2 (kind 0: start or restart; kind 1: judge only)
+// after r = b - A x: |r|^2 (kind 0: start or restart; kind 1: check only)
 __global__ void __launch_bounds__(kFcgBlock) k_fcg_resid(FcgState *st, const double *part, int n, int kind) {
     __shared__ double red[kFcgBlock / kWave];
     const double rr = fixed_sum(part, n, red);
@@ -405,7 +405,7 @@ stag_status fcg_solve(stag_lattice *lat, double mass, double shift, const void *
         }
         run = rep[0];
         if (run == FCG_CONVERGED) {
-            // the judge: the double precision residual of x
+            // the final check: the double precision residual of x
             if (residual(false) != hipSuccess) {
                 rc = STAG_EHIP;
                 break;

@@ -2,7 +2,7 @@
 
 Everything numerical runs in the library's kernels: the training pairs are
 made with the library's double precision operator and solver, the network
-is trained by its forward, backward and Adam kernels, and it is judged inside
+is trained by its forward, backward and Adam kernels, and it is evaluated inside
 its flexible CG.  This module only drives those calls.
 
 Training pairs.  For a source/solution pair (b, x) of M x = b the loss
