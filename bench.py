@@ -35,15 +35,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-FMT_NROW = {"18": 3, "12": 2, "8": 1}
+FMT_NROW = {"18": 3, "12": 2, "8": 1, "18p": 13, "12p": 12}   # "p": one field of float pairs
 
 
 def dslash_bytes_per_site(dbl: bool, nrow: int, mode: str = "plain") -> int:
     """Minimum unique HBM traffic of one half-Dslash per output site: all 8
     links once, the input vector once (neighbours re-read from cache), the
     output once; the normal-operator epilogue also reads p.  Links take
-    9, 6 or 4 complex words (18-, 12- or 8-real storage)."""
-    bl = (16 if dbl else 8) * (4 if nrow == 1 else 3 * nrow)
+    9, 6 or 4 complex words (18-, 12- or 8-real storage); a float-pair
+    field moves the same bytes as the double field in double precision and
+    its single precision half in single precision."""
+    rows = nrow - 10 if nrow > 10 else nrow
+    bl = (16 if dbl else 8) * (4 if rows == 1 else 3 * rows)
     bv = 48 if dbl else 24
     return 8 * bl + (3 if mode == "epilogue" else 2) * bv
 
@@ -305,7 +308,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="f64", choices=["mixed", "f64", "f32"])
-    ap.add_argument("--fmt", default="8", choices=["18", "12", "8"])
+    ap.add_argument("--fmt", default="8", choices=["18", "12", "8", "18p", "12p"])
     ap.add_argument("--cpu-sample-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64-reference", action="store_true")
@@ -450,7 +453,7 @@ def main():
                 kernel=kname, bytes_per_launch=algo, avg_launch_us=round(sec * 1e6, 2))
     # every precision and link format, for the record (same field, repacked)
     dsl = {}
-    for fmt in ("8", "12", "18"):
+    for fmt in ("8", "12", "18", "12p", "18p"):
         if fmt != args.fmt:
             lat.set_links(torch.from_numpy(U).cuda(), fmt)
         for p in ("f64", "f32"):

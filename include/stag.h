@@ -69,9 +69,15 @@ typedef enum {
     STAG_LINK18 = 0, /* all 9 complex entries of each link */
     STAG_LINK12 = 1, /* first two rows; third rebuilt as conj(row0 x row1)
                         (Section 5, 12-real representation); needs SU(3) links */
-    STAG_LINK8 = 2   /* not in the paper: U01, U02, U10 and the phases of U00
+    STAG_LINK8 = 2,  /* not in the paper: U01, U02, U10 and the phases of U00
                         and U20; the rest rebuilt from unitarity and det U = 1.
                         Needs SU(3) links with U01, U02 not both zero */
+    STAG_LINK18_PAIRS = 3, /* Section 5's float pairs: each double a stored as
+                        b = float(a) and c = float(a - b) (a = b + c to about
+                        2^-48 |a|), as the only device copy: the single
+                        precision kernels read the b half, the double
+                        precision ones b + c.  All 9 entries */
+    STAG_LINK12_PAIRS = 4  /* the same for the first two rows (SU(3) links) */
 } stag_link_fmt;
 
 #define STAG_MAX_SHIFTS 64
@@ -108,7 +114,9 @@ int64_t stag_half_volume(const stag_lattice *lat);
  * (4,V,3,3).  Both a double and a single precision copy are stored in the
  * even/odd structure-of-arrays layout (element-major, site index fastest;
  * Section 5 and its Figure 2), keeping all 9 entries, the first two rows or
- * 8 reals (fmt).  Links must be SU(3) for STAG_LINK12 and STAG_LINK8.  For
+ * 8 reals (fmt); the _PAIRS formats keep one field of float pairs for
+ * both precisions instead (2/3 of the memory of the two copies).  Links
+ * must be SU(3) for STAG_LINK12, STAG_LINK12_PAIRS and STAG_LINK8.  For
  * STAG_LINK8 the call rebuilds the double precision field on the device and
  * returns STAG_EINVAL (links left unset) if any entry is off by more than
  * 1e-12, which catches links that have no 8-real form; it then waits for

@@ -16,7 +16,7 @@ import os
 
 import torch
 
-from ._abi import (F32, F64, MIXED, LINK8, LINK12, LINK18, MIX_BF16, MIX_FOLDED, MIX_FOLDED_BF16, MIX_FP32, NET_NPARAM, CgStats, StagError,
+from ._abi import (F32, F64, MIXED, LINK8, LINK12, LINK18, LINK12_PAIRS, LINK18_PAIRS, MIX_BF16, MIX_FOLDED, MIX_FOLDED_BF16, MIX_FP32, NET_NPARAM, CgStats, StagError,
                    System, batch_flags, load_library, status_name)
 
 __all__ = ["Lattice", "CgStats", "StagError", "F64", "F32", "MIXED", "LINK18", "LINK12",
@@ -33,7 +33,8 @@ def library_path() -> str:
 _L = load_library(library_path())
 
 _PREC = {"f64": F64, "f32": F32, "mixed": MIXED, F64: F64, F32: F32, MIXED: MIXED}
-_FMT = {"18": LINK18, "12": LINK12, "8": LINK8, 18: LINK18, 12: LINK12, 8: LINK8}
+_FMT = {"18": LINK18, "12": LINK12, "8": LINK8, 18: LINK18, 12: LINK12, 8: LINK8,
+        "18p": LINK18_PAIRS, "12p": LINK12_PAIRS}
 
 
 def _stream():

@@ -8,7 +8,7 @@ import os
 STAG_OK, STAG_ENOCONV, STAG_EBREAKDOWN = 0, 1, 2
 STAG_EINVAL, STAG_ENOMEM, STAG_EHIP = -1, -2, -3
 F64, F32, MIXED = 0, 1, 2
-LINK18, LINK12, LINK8 = 0, 1, 2
+LINK18, LINK12, LINK8, LINK18_PAIRS, LINK12_PAIRS = 0, 1, 2, 3, 4
 MAX_SHIFTS = 64
 NET_NPARAM = 656
 MIX_BF16, MIX_FP32, MIX_FOLDED, MIX_FOLDED_BF16 = 0, 1, 2, 3

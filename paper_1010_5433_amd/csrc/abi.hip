@@ -108,7 +108,7 @@ stag_status stag_lattice_destroy(stag_lattice *lat) {
     if (!lat) return STAG_OK;
     (void)hipSetDevice(lat->device);
     (void)hipDeviceSynchronize();
-    (void)hipFree(lat->links64);
+    if (lat->links64 != lat->links32) (void)hipFree(lat->links64);   // one field when stored as float pairs
     (void)hipFree(lat->links32);
     (void)hipFree(lat->links16);
     for (int k = 0; k < WS_NSLOTS; ++k) (void)hipFree(lat->ws[k]);
@@ -126,19 +126,29 @@ static constexpr double kLink8MaxError = 1e-12;
 stag_status stag_links_set(stag_lattice *lat, const void *links, stag_link_fmt fmt, void *stream) {
     STAG_TRY(check_lattice(lat, false));
     if (!links) return invalid("null links");
-    if (fmt != STAG_LINK18 && fmt != STAG_LINK12 && fmt != STAG_LINK8) return invalid("unknown link format");
+    if (fmt != STAG_LINK18 && fmt != STAG_LINK12 && fmt != STAG_LINK8 && fmt != STAG_LINK18_PAIRS &&
+        fmt != STAG_LINK12_PAIRS)
+        return invalid("unknown link format");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int nrow = fmt == STAG_LINK8 ? 1 : fmt == STAG_LINK12 ? 2 : 3;
+    const int nrow = fmt == STAG_LINK8 ? 1 : fmt == STAG_LINK12 ? 2 : fmt == STAG_LINK18 ? 3
+                                                                 : fmt == STAG_LINK12_PAIRS ? kHiLo + 2 : kHiLo + 3;
     STAG_HIP(hipStreamSynchronize(s));
-    if (lat->links64) STAG_HIP(hipFree(lat->links64));
+    if (lat->links64 && lat->links64 != lat->links32) STAG_HIP(hipFree(lat->links64));
     if (lat->links32) STAG_HIP(hipFree(lat->links32));
     if (lat->links16) STAG_HIP(hipFree(lat->links16));
     lat->links64 = lat->links32 = lat->links16 = nullptr;
     lat->nrow = 0;
-    STAG_HIP(hipMalloc(&lat->links64, link_field_bytes(true, nrow, lat->Vh)));
-    STAG_HIP(hipMalloc(&lat->links32, link_field_bytes(false, nrow, lat->Vh)));
-    STAG_HIP(launch_pack_links(lat->g, links, lat->links64, true, nrow, s));
-    STAG_HIP(launch_pack_links(lat->g, links, lat->links32, false, nrow, s));
+    if (nrow > kHiLo) {
+        // one field: single precision values, then their double precision remainders
+        STAG_HIP(hipMalloc(&lat->links32, link_field_bytes(true, nrow, lat->Vh)));
+        lat->links64 = lat->links32;
+        STAG_HIP(launch_pack_links(lat->g, links, lat->links64, true, nrow, s));
+    } else {
+        STAG_HIP(hipMalloc(&lat->links64, link_field_bytes(true, nrow, lat->Vh)));
+        STAG_HIP(hipMalloc(&lat->links32, link_field_bytes(false, nrow, lat->Vh)));
+        STAG_HIP(launch_pack_links(lat->g, links, lat->links64, true, nrow, s));
+        STAG_HIP(launch_pack_links(lat->g, links, lat->links32, false, nrow, s));
+    }
     if (nrow == 1) {
         // the 8-real form needs u01, u02 not both zero: check the rebuilt field
         const int nb = check_links_blocks(lat->g);

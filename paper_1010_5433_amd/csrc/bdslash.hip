@@ -148,9 +148,12 @@ static hipError_t bd_launch(bool dbl, int nrow, int role, BDslashCfg cfg, const 
     if (a.nrhs < 1 || a.nrhs > cfg.rpt || a.nrhs > kMaxRpt) return hipErrorInvalidValue;
     if (cfg.block != 64 && cfg.block != 128 && cfg.block != 256) return hipErrorInvalidValue;
     if (dbl) {
+        if (nrow == kHiLo + 2) return bd_launch_nrow<double, kHiLo + 2>(role, cfg, a, s);
+        if (nrow == kHiLo + 3) return bd_launch_nrow<double, kHiLo + 3>(role, cfg, a, s);
         if (nrow == 1) return bd_launch_nrow<double, 1>(role, cfg, a, s);
         return nrow == 2 ? bd_launch_nrow<double, 2>(role, cfg, a, s) : bd_launch_nrow<double, 3>(role, cfg, a, s);
     }
+    nrow = nrow_single(nrow);   // a float-pair field: its hi half
     if (nrow == 1) return bd_launch_nrow<float, 1>(role, cfg, a, s);
     return nrow == 2 ? bd_launch_nrow<float, 2>(role, cfg, a, s) : bd_launch_nrow<float, 3>(role, cfg, a, s);
 }

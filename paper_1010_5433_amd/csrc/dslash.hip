@@ -104,9 +104,12 @@ static hipError_t launch_mode(int mode, const DslashArgs &a, hipStream_t s) {
 
 hipError_t launch_dslash(bool dbl, int nrow, int mode, const DslashArgs &a, hipStream_t s) {
     if (dbl) {
+        if (nrow == kHiLo + 2) return launch_mode<double, kHiLo + 2>(mode, a, s);
+        if (nrow == kHiLo + 3) return launch_mode<double, kHiLo + 3>(mode, a, s);
         if (nrow == 1) return launch_mode<double, 1>(mode, a, s);
         return nrow == 2 ? launch_mode<double, 2>(mode, a, s) : launch_mode<double, 3>(mode, a, s);
     }
+    nrow = nrow_single(nrow);   // a float-pair field: its hi half
     if (nrow == 1) return launch_mode<float, 1>(mode, a, s);
     return nrow == 2 ? launch_mode<float, 2>(mode, a, s) : launch_mode<float, 3>(mode, a, s);
 }

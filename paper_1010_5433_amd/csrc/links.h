@@ -242,6 +242,101 @@ template <> struct LinkLayout<float, 1> {
     }
 };
 
+// Double precision links stored as pairs of floats (Section 5 of the paper:
+// a double a kept as b = RN_float(a) and c = RN_float(a - b), a = b + c to
+// about 2^-48 |a|), as the one device copy of the field: the 8 link blocks
+// of the single precision form (hi) come first, the 8 blocks of the
+// remainders (lo) after them, both in the LinkLayout<float, NROW> form.
+// Single precision kernels read the first half as an ordinary single
+// precision field; double precision kernels read both halves and add them
+// in double.  Coded as NROW = kHiLo + 2 (12 reals) or kHiLo + 3 (18 reals).
+constexpr int kHiLo = 10;
+
+__device__ __forceinline__ cplx<double> hilo_pair(float hre, float him, float lre, float lim) {
+    return {double(hre) + double(lre), double(him) + double(lim)};
+}
+__device__ __forceinline__ void hilo_split(const cplx<double> &a, float &hre, float &him, float &lre, float &lim) {
+    hre = float(a.re);
+    him = float(a.im);
+    lre = float(a.re - double(hre));
+    lim = float(a.im - double(him));
+}
+
+template <> struct LinkLayout<double, kHiLo + 2> {
+    static constexpr int64_t kHalf = 48;               // bytes per link of each half
+    static constexpr int64_t kBytesPerLink = 2 * kHalf;
+    __device__ static __forceinline__ su3<double> load(const void *base, int64_t vh, int blk, int64_t i) {
+        const float4 *h = reinterpret_cast<const float4 *>(static_cast<const char *>(base) + (int64_t)blk * kHalf * vh);
+        const float4 *l = reinterpret_cast<const float4 *>(static_cast<const char *>(base) + (int64_t)(8 + blk) * kHalf * vh);
+        su3<double> u;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float4 a = ld_nt(&h[k * vh + i]), b = ld_nt(&l[k * vh + i]);
+            const int e0 = 2 * k, e1 = 2 * k + 1;   // entries {u00,u01}, {u02,u10}, {u11,u12}
+            u.e[e0 / 3][e0 % 3] = hilo_pair(a.x, a.y, b.x, b.y);
+            u.e[e1 / 3][e1 % 3] = hilo_pair(a.z, a.w, b.z, b.w);
+        }
+        su3_rebuild_row2(u);
+        return u;
+    }
+    __device__ static __forceinline__ void store(void *base, int64_t vh, int blk, int64_t i, const su3<double> &u) {
+        float4 *h = reinterpret_cast<float4 *>(static_cast<char *>(base) + (int64_t)blk * kHalf * vh);
+        float4 *l = reinterpret_cast<float4 *>(static_cast<char *>(base) + (int64_t)(8 + blk) * kHalf * vh);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int e0 = 2 * k, e1 = 2 * k + 1;
+            float4 a, b;
+            hilo_split(u.e[e0 / 3][e0 % 3], a.x, a.y, b.x, b.y);
+            hilo_split(u.e[e1 / 3][e1 % 3], a.z, a.w, b.z, b.w);
+            h[k * vh + i] = a;
+            l[k * vh + i] = b;
+        }
+    }
+};
+
+template <> struct LinkLayout<double, kHiLo + 3> {
+    static constexpr int64_t kHalf = 72;
+    static constexpr int64_t kBytesPerLink = 2 * kHalf;
+    __device__ static __forceinline__ su3<double> load(const void *base, int64_t vh, int blk, int64_t i) {
+        const char *hb = static_cast<const char *>(base) + (int64_t)blk * kHalf * vh;
+        const char *lb = static_cast<const char *>(base) + (int64_t)(8 + blk) * kHalf * vh;
+        const float4 *h = reinterpret_cast<const float4 *>(hb), *l = reinterpret_cast<const float4 *>(lb);
+        su3<double> u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {   // entries 2k and 2k + 1 in row-major order
+            const float4 a = ld_nt(&h[k * vh + i]), b = ld_nt(&l[k * vh + i]);
+            const int e0 = 2 * k, e1 = 2 * k + 1;
+            u.e[e0 / 3][e0 % 3] = hilo_pair(a.x, a.y, b.x, b.y);
+            u.e[e1 / 3][e1 % 3] = hilo_pair(a.z, a.w, b.z, b.w);
+        }
+        const float2 a = ld_nt(reinterpret_cast<const float2 *>(hb + 64 * vh) + i);
+        const float2 b = ld_nt(reinterpret_cast<const float2 *>(lb + 64 * vh) + i);
+        u.e[2][2] = hilo_pair(a.x, a.y, b.x, b.y);
+        return u;
+    }
+    __device__ static __forceinline__ void store(void *base, int64_t vh, int blk, int64_t i, const su3<double> &u) {
+        char *hb = static_cast<char *>(base) + (int64_t)blk * kHalf * vh;
+        char *lb = static_cast<char *>(base) + (int64_t)(8 + blk) * kHalf * vh;
+        float4 *h = reinterpret_cast<float4 *>(hb), *l = reinterpret_cast<float4 *>(lb);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int e0 = 2 * k, e1 = 2 * k + 1;
+            float4 a, b;
+            hilo_split(u.e[e0 / 3][e0 % 3], a.x, a.y, b.x, b.y);
+            hilo_split(u.e[e1 / 3][e1 % 3], a.z, a.w, b.z, b.w);
+            h[k * vh + i] = a;
+            l[k * vh + i] = b;
+        }
+        float2 a, b;
+        hilo_split(u.e[2][2], a.x, a.y, b.x, b.y);
+        reinterpret_cast<float2 *>(hb + 64 * vh)[i] = a;
+        reinterpret_cast<float2 *>(lb + 64 * vh)[i] = b;
+    }
+};
+
+// Single precision form of a stored format (the hi half of a float-pair field).
+inline int nrow_single(int nrow) { return nrow > kHiLo ? nrow - kHiLo : nrow; }
+
 // Low-precision copy for the learned preconditioner: 12 reals in bfloat16,
 // 3 planes of 4 bf16 (8 bytes) per site: {u00, u01}, {u02, u10}, {u11, u12};
 // the third row is rebuilt in single precision.
@@ -283,7 +378,8 @@ template <> struct LinkLayout<BF16Link, 2> {
 // Bytes of one packed link field (both parities, 4 directions).
 inline int64_t link_field_bytes(bool dbl, int nrow, int64_t vh) {
     int64_t per;
-    if (nrow == 1) per = dbl ? 64 : 32;
+    if (nrow > kHiLo) per = 2 * (nrow - kHiLo == 3 ? 72 : 48);   // one field for both precisions
+    else if (nrow == 1) per = dbl ? 64 : 32;
     else per = dbl ? 16 * 3 * nrow : (nrow == 3 ? 72 : 48);
     return per * 8 * vh;
 }

@@ -78,7 +78,7 @@ NetArgs net_args(const stag_net *net, const stag_lattice *lat, const void *r, fl
     std::memset(&a, 0, sizeof(a));
     a.g = lat->g;
     a.links = lat->links32;
-    a.nrow = lat->nrow;
+    a.nrow = nrow_single(lat->nrow);
     a.links16 = lat->links16;
     a.w = net->w;
     a.r = static_cast<const float2 *>(r);

@@ -131,10 +131,13 @@ hipError_t launch_pack_links(const Geom &g, const void *canon, void *dst, bool d
     const int64_t n = 8 * (int64_t)g.Vh;
     const double2 *c = static_cast<const double2 *>(canon);
     if (dbl) {
-        if (nrow == 1) hipLaunchKernelGGL((k_pack_links<double, 1>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
+        if (nrow == kHiLo + 2) hipLaunchKernelGGL((k_pack_links<double, kHiLo + 2>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
+        else if (nrow == kHiLo + 3) hipLaunchKernelGGL((k_pack_links<double, kHiLo + 3>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
+        else if (nrow == 1) hipLaunchKernelGGL((k_pack_links<double, 1>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
         else if (nrow == 2) hipLaunchKernelGGL((k_pack_links<double, 2>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
         else hipLaunchKernelGGL((k_pack_links<double, 3>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
     } else {
+        if (nrow > kHiLo) return hipErrorInvalidValue;   // float pairs are packed in one double pass
         if (nrow == 1) hipLaunchKernelGGL((k_pack_links<float, 1>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
         else if (nrow == 2) hipLaunchKernelGGL((k_pack_links<float, 2>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
         else hipLaunchKernelGGL((k_pack_links<float, 3>), dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, dst);
@@ -144,6 +147,7 @@ hipError_t launch_pack_links(const Geom &g, const void *canon, void *dst, bool d
 
 hipError_t launch_pack_links16(const Geom &g, const void *links32, int nrow, void *dst, hipStream_t s) {
     const int64_t n = 8 * (int64_t)g.Vh;
+    nrow = nrow_single(nrow);
     if (nrow == 1) hipLaunchKernelGGL(k_pack_links16<1>, dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g.Vh, links32, dst);
     else if (nrow == 2) hipLaunchKernelGGL(k_pack_links16<2>, dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g.Vh, links32, dst);
     else hipLaunchKernelGGL(k_pack_links16<3>, dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g.Vh, links32, dst);

@@ -50,7 +50,7 @@ def test_tables_bit_exact(orc, dims, antiperiodic):
 
 
 @pytest.mark.parametrize("dims", SMALL + FULL)
-@pytest.mark.parametrize("fmt", ["18", "12", "8"])
+@pytest.mark.parametrize("fmt", ["18", "12", "8", "18p", "12p"])
 def test_dslash_f64(orc, dims, fmt):
     log(f"dslash f64 {dims} fmt={fmt}")
     U = links_np(dims, "haar" if np.prod(dims) < 4096 else "smooth", 0.5, 11)
@@ -65,7 +65,7 @@ def test_dslash_f64(orc, dims, fmt):
 
 
 @pytest.mark.parametrize("dims", SMALL + FULL)
-@pytest.mark.parametrize("fmt", ["18", "12", "8"])
+@pytest.mark.parametrize("fmt", ["18", "12", "8", "18p", "12p"])
 def test_dslash_f32(orc, dims, fmt):
     log(f"dslash f32 {dims} fmt={fmt}")
     U = links_np(dims, "haar" if np.prod(dims) < 4096 else "smooth", 0.5, 11)
@@ -279,6 +279,38 @@ def test_links8_rejects_unit_links():
         lat.set_links(to_dev(ln.free_links(dims)), "8")
     with pytest.raises(stag.StagError):     # no links were kept
         lat.dslash_eo(0, pack(lat, np.ones((lat.Vh, 3), complex)))
+
+
+@pytest.mark.parametrize("dims,fmt", [((4, 4, 4, 4), "12p"), ((6, 4, 2, 8), "18p"), ((32, 32, 32, 8), "12p")])
+def test_float_pair_links_single_half_is_the_single_field(dims, fmt):
+    """The float-pair field's first half is the single precision field: the
+    single precision Dslash on it is bit-identical to the one on the plain
+    single precision format."""
+    log(f"float pairs, single precision half {dims} {fmt}")
+    U = links_np(dims, "smooth", 0.5, 12)
+    lat_p = lattice_with_links(dims, U, fmt)
+    lat_s = lattice_with_links(dims, U, fmt[:-1])
+    v = pack(lat_p, syn.gaussian_source(dims, 13), "f32")
+    for par in (0, 1):
+        assert bool((lat_p.dslash_eo(par, v) == lat_s.dslash_eo(par, v)).all())
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_multishift_config3_float_pair_links(orc, prec):
+    """The 32^4 solve with the one float-pair copy of the links (12 reals):
+    every shift at FP64 true residual <= 1e-10 by the oracle's operator."""
+    c = syn.config("c3_32x32x32x32_smooth")
+    log(f"multishift config 3 (32^4), float-pair links, prec={prec}")
+    U = links_np(c["dims"], "smooth", c["links"][1], c["links"][2])
+    b = syn.gaussian_source(c["dims"], c["source_seed"])
+    shifts = syn.logspace_shifts(*c["shifts"])
+    lat = lattice_with_links(c["dims"], U, "12p")
+    xs, rc, st = _solve(lat, c["mass"], shifts, b, prec=prec)
+    log(f"  iters {st['iters']} refine {st['refine_iters']} seconds {st['seconds']:.3f}")
+    assert rc == 0
+    for i in (0, 7, 15):
+        r = orc.true_residual(c["dims"], U, c["mass"], shifts[i], b, xs[i])
+        assert r <= 1e-10, (i, r)
 
 
 @pytest.mark.parametrize("prec", ["f64", "mixed"])
