@@ -342,3 +342,20 @@ def test_inputs_are_seeded():
     assert np.array_equal(syn.gaussian_source((4, 4, 4, 4), 3), syn.gaussian_source((4, 4, 4, 4), 3))
     s = syn.gaussian_source((8, 8, 8, 8), 1)
     assert abs(np.mean(np.abs(s) ** 2) - 1.0) < 0.02
+
+
+def test_float_pair_split_bound():
+    """Section 5's storage of a double as two floats, b = RN_float(a) and
+    c = RN_float(a - b): |a - (b + c)| <= 2^-48 |a| (the remainder is
+    rounded once more, so the pair is not exact), and b alone is the single
+    precision value.  Checked on link-like entries (|a| <= 1) and on a wide
+    range of magnitudes."""
+    rng = np.random.default_rng(41)
+    a = np.concatenate([rng.uniform(-1, 1, 200000),
+                        rng.standard_normal(200000) * np.exp(rng.uniform(-30, 30, 200000))])
+    b = a.astype(np.float32)
+    c = (a - b.astype(np.float64)).astype(np.float32)
+    err = np.abs(a - (b.astype(np.float64) + c.astype(np.float64)))
+    assert np.all(err <= 2.0 ** -48 * np.abs(a))
+    assert np.max(err / np.abs(a)) > 2.0 ** -52      # not exact in general
+    assert np.array_equal(b, a.astype(np.float32))
