@@ -63,6 +63,28 @@ def test_batched_vs_oracle_and_unbatched(orc, prec):
             assert abs(stats[k]["iters"] - st1["iters"]) <= 1
 
 
+@pytest.mark.parametrize("max_iter", [13, 21])
+def test_batched_stops_inside_a_block(orc, max_iter):
+    """Multi-shift systems of a batch bring their shifted solutions up to date
+    once per block of 16 iterations; a batch stopped by the iteration limit
+    inside a block returns every system's iterates at that iteration (the
+    oracle's, same limit).  A single-shift system (updated every iteration)
+    rides in the same batch."""
+    import torch
+    import paper_1010_5433_amd as stag
+    log(f"batched, stop at {max_iter}")
+    specs = [((4, 4, 4, 4), 51, 0.1, [0.0, 0.05, 0.5], [7, 8]), ((6, 4, 2, 4), 52, 0.2, [0.01], [9])]
+    lats, systems, host = _setup(specs)
+    sols, rc, stats = stag.multishift_cg_batched(systems, prec="f64", max_iter=max_iter)
+    torch.cuda.synchronize()
+    assert rc == stag._abi.STAG_ENOCONV
+    for k, (dims, U, mass, shifts, b) in enumerate(host):
+        xo, rco, io = orc.multishift_cg(dims, U, mass, shifts, b, tol=1e-10, max_iter=max_iter)
+        assert stats[k]["iters"] == io["iters"] == max_iter
+        for i in range(len(shifts)):
+            assert rel(unpack(systems[k]["lat"], sols[k][i]), xo[i]) <= 1e-12, (k, i)
+
+
 def test_launch_shapes_agree():
     import torch
     import paper_1010_5433_amd as stag
