@@ -146,6 +146,57 @@ __global__ void __launch_bounds__(kBlasBlock) k_dir_update(const MsState *st, co
     }
 }
 
+// Fused forms (see solver.h).  Every block reduces the partials in the order
+// of k_reduce_tail (threads stride kBlasBlock, then block_sum), so alpha and
+// beta equal the tail kernel's bit for bit.
+template <typename R>
+__global__ void __launch_bounds__(kBlasBlock) k_r_update_fused(MsState *st, const double *pq_part, int npq,
+                                                            const T2<R> *rin, T2<R> *r, const T2<R> *ap, int64_t n,
+                                                            double *partial) {
+    if (st->done) return;
+    __shared__ double red[kBlasBlock / kWave];
+    double t = 0.0;
+    for (int k = threadIdx.x; k < npq; k += kBlasBlock) t += pq_part[k];
+    const double pap = block_sum(t, red);
+    const bool bad = !(pap > 0.0) || !isfinite(pap);
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) st->rho_snap = st->rho;
+        ms_alpha_step(st, pap);   // records a breakdown and ends the solve when bad
+    }
+    if (bad) return;
+    const R alpha = R(st->rho / pap);   // rho is not written by this kernel
+    double part = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
+        T2<R> rv = rin[j];
+        const T2<R> q = ap[j];
+        rv.x -= alpha * q.x;
+        rv.y -= alpha * q.y;
+        r[j] = rv;
+        part += abs2<R>(rv);
+    }
+    const double s = block_sum(part, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlasBlock) k_dir_update_fused(MsState *st, const double *r_part, int nr,
+                                                              const T2<R> *r, T2<R> *pd, int64_t n) {
+    if (st->done) return;
+    __shared__ double red[kBlasBlock / kWave];
+    double t = 0.0;
+    for (int k = threadIdx.x; k < nr; k += kBlasBlock) t += r_part[k];
+    const double rho_new = block_sum(t, red);
+    const R beta = R(rho_new / st->rho_snap);   // block 0 rewrites rho below, not rho_snap
+    if (blockIdx.x == 0) ms_beta_step(st, rho_new);
+    for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
+        const T2<R> rv = r[j];
+        T2<R> pv = pd[j];
+        pv.x = rv.x + beta * pv.x;
+        pv.y = rv.y + beta * pv.y;
+        pd[j] = pv;
+    }
+}
+
 // Coefficients of a deferred pass (one wave, lane = shift).
 __global__ void __launch_bounds__(kWave) k_defer_coef(MsState *st, DeferHist *h) {
     defer_coef_step(st->n, h, st->rat ? st->wgt : nullptr);
@@ -343,6 +394,20 @@ hipError_t launch_defer_pass(bool dbl, MsState *st, DeferHist *h, const void *ri
     } else {
         hipLaunchKernelGGL((k_defer_apply<float, false>), dim3(grid), dim3(kBlasBlock), 0, s, (const MsState *)st, (const DeferHist *)h, static_cast<const float2 *>(ring), slot_elems, ptrs, n_shift, n, (float2 *)nullptr);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_r_update_fused(bool dbl, MsState *st, const double *pq_part, int npq, const void *rin, void *r,
+                                 const void *ap, int64_t n, double *partial, int grid, hipStream_t s) {
+    if (dbl) hipLaunchKernelGGL(k_r_update_fused<double>, dim3(grid), dim3(kBlasBlock), 0, s, st, pq_part, npq, static_cast<const double2 *>(rin), static_cast<double2 *>(r), static_cast<const double2 *>(ap), n, partial);
+    else hipLaunchKernelGGL(k_r_update_fused<float>, dim3(grid), dim3(kBlasBlock), 0, s, st, pq_part, npq, static_cast<const float2 *>(rin), static_cast<float2 *>(r), static_cast<const float2 *>(ap), n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_dir_update_fused(bool dbl, MsState *st, const double *r_part, int nr, const void *r, void *pd,
+                                   int64_t n, int grid, hipStream_t s) {
+    if (dbl) hipLaunchKernelGGL(k_dir_update_fused<double>, dim3(grid), dim3(kBlasBlock), 0, s, st, r_part, nr, static_cast<const double2 *>(r), static_cast<double2 *>(pd), n);
+    else hipLaunchKernelGGL(k_dir_update_fused<float>, dim3(grid), dim3(kBlasBlock), 0, s, st, r_part, nr, static_cast<const float2 *>(r), static_cast<float2 *>(pd), n);
     return hipGetLastError();
 }
 

@@ -208,14 +208,16 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
         d.c = m2 + sigma0;
         d.partial = part0;
         STAG_HIP(launch_dslash(dbl, lat->nrow, DS_NORMAL_DOT, d, s));
-        STAG_HIP(launch_reduce_tail(st, part0, ds_grid, TAIL_ALPHA, 0, s));
-        STAG_HIP(launch_r_update(dbl, st, rslot(k - 1), rslot(k), AP, ne, part1, bl_grid, s));
-        STAG_HIP(launch_reduce_tail(st, part1, bl_grid, TAIL_BETA, 0, s));
         if (defer) {
-            STAG_HIP(launch_dir_update(dbl, st, rslot(k), pbase, ne, bl_grid, s));
+            // the scalar steps ride in the two vector kernels (no tail launches)
+            STAG_HIP(launch_r_update_fused(dbl, st, part0, ds_grid, rslot(k - 1), rslot(k), AP, ne, part1, bl_grid, s));
+            STAG_HIP(launch_dir_update_fused(dbl, st, part1, bl_grid, rslot(k), pbase, ne, bl_grid, s));
             if ((k + 1) % dlen == 0)
                 STAG_HIP(launch_defer_pass(dbl, st, hist, R, ne, it_ptrs, n, ne, bl_grid, s, sp.rat_out));
         } else {
+            STAG_HIP(launch_reduce_tail(st, part0, ds_grid, TAIL_ALPHA, 0, s));
+            STAG_HIP(launch_r_update(dbl, st, rslot(k - 1), rslot(k), AP, ne, part1, bl_grid, s));
+            STAG_HIP(launch_reduce_tail(st, part1, bl_grid, TAIL_BETA, 0, s));
             STAG_HIP(launch_shift_update(dbl, st, R, it_ptrs, n, ne, bl_grid, s));
         }
         if (sp.reliable_every > 0 && (k + 1) % sp.reliable_every == 0) {

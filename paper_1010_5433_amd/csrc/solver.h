@@ -42,6 +42,7 @@ struct MsState {
     double tol;          // relative tolerance
     double rho_rel;      // |r|^2 right after the last reliable update (or the start)
     double rel_delta2;   // reliable update once |r|^2 < rel_delta2 * rho_rel (0: never)
+    double rho_snap;     // rho of this iteration, kept for the fused beta step
     double scratch[4];   // reduced values handed to the host
     int n, base;
     int iter, max_iter;
@@ -88,6 +89,16 @@ hipError_t launch_r_update(bool dbl, MsState *st, const void *rin, void *r, cons
 // over every shift changed in it.  ring: one residual vector per iteration
 // of the block, slot m holding r^{k0+1+m}.
 hipError_t launch_dir_update(bool dbl, MsState *st, const void *r, void *pd, int64_t n, int grid, hipStream_t s);
+// The same two steps with the scalar recursion folded in: every block sums
+// the partials of the previous reduction itself (the fixed order of the
+// one-workgroup tail, so the scalars are bit for bit those of the separate
+// tail kernel) and block 0 also advances the recursion.
+//   r update: <p, A p> from pq_part (npq) -> alpha, zeta_i; r = rin - alpha A p; |r|^2 partials
+//   direction: |r|^2 from r_part (nr) -> beta, shift coefficients, freeze tests; pd = r + beta pd
+hipError_t launch_r_update_fused(bool dbl, MsState *st, const double *pq_part, int npq, const void *rin, void *r,
+                                 const void *ap, int64_t n, double *partial, int grid, hipStream_t s);
+hipError_t launch_dir_update_fused(bool dbl, MsState *st, const double *r_part, int nr, const void *r, void *pd,
+                                   int64_t n, int grid, hipStream_t s);
 // out == nullptr: x_i += ... for every shift; otherwise (rational
 // application, double precision) out += sum_i wgt_i (x_i increment) and no
 // x_i is kept.
