@@ -296,6 +296,32 @@ def test_fcg_polynomial_preconditioner_gains(orc):
         assert st1["iters"] <= 0.7 * st0["iters"]
 
 
+@pytest.mark.parametrize("mode", ["folded", "folded_bf16"])
+def test_fcg_full_size_polynomial(orc, mode):
+    """At the 32^4 size and mass the benchmark times: flexible CG with the
+    polynomial preconditioner P = (a + b) - M in the network's folded
+    kernels meets the FP64 tolerance (checked with the oracle's operator)
+    in fewer iterations than plain CG."""
+    import torch
+    import paper_1010_5433_amd as stag
+    dims, m = (32, 32, 32, 32), 0.01
+    log(f"fcg 32^4 polynomial preconditioner, {mode}")
+    U = links_np(dims, "smooth", 0.5, 550)
+    lat = lattice_with_links(dims, U, "8")
+    lmax = 1.1 * _lambda_max(lat, m, dims, iters=60)
+    net = stag.Net(poly_theta(m * m + lmax - m * m, 1.0, scale=1.0 / lmax))
+    b = syn.gaussian_source(dims, 650)
+    src = pack(lat, b)
+    x0 = torch.zeros_like(src)
+    _, rc0, st0 = lat.fcg_solve(m, 0.0, src, x0, net=None, tol=1e-10)
+    x1 = torch.zeros_like(src)
+    _, rc1, st1 = lat.fcg_solve(m, 0.0, src, x1, net=net, mode=mode, tol=1e-10)
+    log(f"  plain {st0['iters']} iterations, preconditioned {st1['iters']}")
+    assert rc0 == 0 and rc1 == 0 and st1["fallback_used"] == 0
+    assert st1["iters"] <= 0.7 * st0["iters"]
+    assert orc.true_residual(dims, U, m, 0.0, b, unpack(lat, x1)) <= 1e-10
+
+
 def test_fcg_fallback_on_indefinite_preconditioner(orc):
     """P = -I makes <r, P r> < 0: the solver abandons the network, finishes
     with plain CG from where it was and still meets tol."""
