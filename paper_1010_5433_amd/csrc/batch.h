@@ -75,7 +75,12 @@ enum BVecOp {
     BV_FLUSH = 5,      // xhi += x, x = 0 (single precision), when a reliable update is due
     BV_FLUSH_FINAL = 6,// same, always
     BV_DEMOTE = 7,     // r = (float) rhi, when a reliable update is due
-    BV_DEFER_APPLY = 8 // deferred systems: the pass over every shift changed in the block
+    BV_DEFER_APPLY = 8,// deferred systems: the pass over every shift changed in the block
+    // batches whose systems are all deferred: the alpha and beta steps ride in
+    // the vector kernels (each block sums its system's partials in kb_tail's
+    // order; block 0 of the system advances the recursion)
+    BV_R_UPDATE_FUSED = 9,
+    BV_DIR_FUSED = 10
 };
 // it: the iteration the op belongs to (selects ring slots of deferred systems;
 // BV_START writes r^0 to the slot iteration 0 reads)

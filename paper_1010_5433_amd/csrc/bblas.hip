@@ -78,10 +78,24 @@ __global__ void __launch_bounds__(kBBlock) kb_vec(BView v, int op, int it) {
                 part += b.x * b.x + b.y * b.y;
             }
         }
-    } else if (op == BV_R_UPDATE) {
+    } else if (op == BV_R_UPDATE || op == BV_R_UPDATE_FUSED) {
         if (st->done) return;
         reduce = true;
-        const R alpha = R(st->alpha);
+        R alpha;
+        if (op == BV_R_UPDATE_FUSED) {
+            __shared__ double red[kBBlock / kWave];
+            double t = 0.0;
+            for (int k = threadIdx.x; k < s.nchunk_ds; k += kBBlock) t += s.part_ds[k];
+            const double pap = block_sum(t, red);
+            if (blockIdx.x == 0) {
+                if (threadIdx.x == 0) st->rho_snap = st->rho;
+                ms_alpha_step(st, pap);
+            }
+            if (!(pap > 0.0) || !isfinite(pap)) return;
+            alpha = R(st->rho / pap);   // rho is not written by this kernel
+        } else {
+            alpha = R(st->alpha);
+        }
         const T2<R> *rin = rvec(it - 1);
         T2<R> *r = rvec(it);
         const T2<R> *ap = static_cast<const T2<R> *>(s.ap);
@@ -96,12 +110,22 @@ __global__ void __launch_bounds__(kBBlock) kb_vec(BView v, int op, int it) {
                 part += double(rv.x) * double(rv.x) + double(rv.y) * double(rv.y);
             }
         }
-    } else if (op == BV_SHIFT_UPDATE && s.dlen) {
+    } else if ((op == BV_SHIFT_UPDATE && s.dlen) || op == BV_DIR_FUSED) {
         // deferred system: only the base direction pd = r + beta pd
         if (st->done) return;
         const T2<R> *r = rvec(it);
         T2<R> *pd = static_cast<T2<R> *>(s.pd);
-        const R beta = R(st->beta);
+        R beta;
+        if (op == BV_DIR_FUSED) {
+            __shared__ double red[kBBlock / kWave];
+            double t = 0.0;
+            for (int k = threadIdx.x; k < s.nchunk_bl; k += kBBlock) t += s.part_bl[k];
+            const double rho_new = block_sum(t, red);
+            beta = R(rho_new / st->rho_snap);   // block 0 rewrites rho below, not rho_snap
+            if (blockIdx.x == 0) ms_beta_step(st, rho_new);
+        } else {
+            beta = R(st->beta);
+        }
         for (int e = 0; e < 4; ++e) {
             const int64_t j = j0 + e * kWave;
             if (j >= n) break;

@@ -431,8 +431,11 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
             args[l].push_back({make_args(l, grp, BD_OE), make_args(l, grp, BD_EO)});
 
     // ---- iterations
-    bool any_defer = false;
-    for (int k = 0; k < nsys; ++k) any_defer = any_defer || h_sys[k].dlen > 0;
+    bool any_defer = false, all_defer = true;
+    for (int k = 0; k < nsys; ++k) {
+        any_defer = any_defer || h_sys[k].dlen > 0;
+        all_defer = all_defer && h_sys[k].dlen > 0;
+    }
     const bool use_rel = !dbl && opt.reliable_every > 0;
     const int check = use_rel ? opt.reliable_every : 0;
     auto iteration = [&](int it) -> hipError_t {
@@ -444,10 +447,15 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
                 e = bd_launch(dbl, nrow, BD_EO, cfg[l], pa.second, s);
                 if (e != hipSuccess) return e;
             }
-        if (e == hipSuccess) e = launch_btail(v, BT_ALPHA, s);
-        if (e == hipSuccess) e = launch_bvec(dbl, v, BV_R_UPDATE, max_blocks, s, it);
-        if (e == hipSuccess) e = launch_btail(v, BT_BETA, s);
-        if (e == hipSuccess) e = launch_bvec(dbl, v, BV_SHIFT_UPDATE, max_blocks, s, it);
+        if (all_defer) {
+            if (e == hipSuccess) e = launch_bvec(dbl, v, BV_R_UPDATE_FUSED, max_blocks, s, it);
+            if (e == hipSuccess) e = launch_bvec(dbl, v, BV_DIR_FUSED, max_blocks, s, it);
+        } else {
+            if (e == hipSuccess) e = launch_btail(v, BT_ALPHA, s);
+            if (e == hipSuccess) e = launch_bvec(dbl, v, BV_R_UPDATE, max_blocks, s, it);
+            if (e == hipSuccess) e = launch_btail(v, BT_BETA, s);
+            if (e == hipSuccess) e = launch_bvec(dbl, v, BV_SHIFT_UPDATE, max_blocks, s, it);
+        }
         if (e == hipSuccess && any_defer && (it + 1) % dlen_all == 0) {
             e = launch_bdefer_coef(v, s);
             if (e == hipSuccess) e = launch_bvec(dbl, v, BV_DEFER_APPLY, max_blocks, s, it);

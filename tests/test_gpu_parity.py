@@ -398,3 +398,31 @@ def test_solver_edge_cases():
     bad = pack(lat, np.full((128, 3), np.nan + 0j))
     sols, rc, st = lat.multishift_cg(0.1, [0.0], bad)
     assert rc == stag._abi.STAG_EBREAKDOWN
+
+
+def test_side_stream_gives_the_same_results():
+    """Every call is ordered on the caller's current stream: the Dslash and a
+    multi-shift solve on a side stream equal those on the default stream
+    bit for bit, and their outputs are ready once that stream is
+    synchronised."""
+    import torch
+    log("side stream")
+    dims = (8, 8, 8, 8)
+    U = links_np(dims, "smooth", 0.5, 71)
+    b = syn.gaussian_source(dims, 72)
+    lat = lattice_with_links(dims, U, "8")
+    src = pack(lat, b)
+    shifts = [0.0, 0.01, 0.3]
+    d0 = lat.dslash_eo(0, src)
+    x0, rc0, st0 = lat.multishift_cg(0.05, shifts, src)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        d1 = lat.dslash_eo(0, src)
+        x1, rc1, st1 = lat.multishift_cg(0.05, shifts, src)
+    side.synchronize()
+    assert rc0 == rc1 == 0 and st0["iters"] == st1["iters"]
+    assert torch.equal(d0, d1)
+    for a, c in zip(x0, x1):
+        assert torch.equal(a, c)
