@@ -40,12 +40,12 @@ SMALL_BATCH = [
 ]
 
 
-@pytest.mark.parametrize("prec", ["f64", "mixed"])
-def test_batched_vs_oracle_and_unbatched(orc, prec):
+@pytest.mark.parametrize("prec,fmt", [("f64", "18"), ("mixed", "18"), ("f64", "12p"), ("mixed", "12p")])
+def test_batched_vs_oracle_and_unbatched(orc, prec, fmt):
     import torch
     import paper_1010_5433_amd as stag
-    log(f"batched small prec={prec}")
-    lats, systems, host = _setup(SMALL_BATCH)
+    log(f"batched small prec={prec} fmt={fmt}")
+    lats, systems, host = _setup(SMALL_BATCH, fmt)
     sols, rc, stats = stag.multishift_cg_batched(systems, prec=prec)
     torch.cuda.synchronize()
     assert rc == 0
