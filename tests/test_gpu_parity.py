@@ -426,3 +426,24 @@ def test_side_stream_gives_the_same_results():
     assert torch.equal(d0, d1)
     for a, c in zip(x0, x1):
         assert torch.equal(a, c)
+
+
+def test_multishift_64_shifts(orc):
+    """The largest shift count (one lane per shift in the scalar and
+    deferred-coefficient kernels): every shift meets tol by the oracle's
+    operator and matches the oracle's solution."""
+    dims = (4, 4, 4, 4)
+    log("multishift with 64 shifts")
+    U = syn.haar_links(dims, 81)
+    b = syn.gaussian_source(dims, 82)
+    shifts = list(syn.logspace_shifts(1e-5, 10.0, 64))
+    lat = lattice_with_links(dims, U)
+    xs, rc, st = _solve(lat, 0.1, shifts, b)
+    xo, rco, io = orc.multishift_cg(dims, U, 0.1, shifts, b, tol=1e-10)
+    assert rc == 0 and rco == 0
+    assert abs(st["iters"] - io["iters"]) <= 1
+    for i in range(64):
+        assert orc.true_residual(dims, U, 0.1, shifts[i], b, xs[i]) <= 1e-10, i
+        kappa = (0.01 + 16.0 + shifts[i]) / (0.01 + shifts[i])   # spectrum of M + s in [m^2 + s, m^2 + 16 + s]
+        assert rel(xs[i], xo[i]) <= 2 * kappa * 1e-10, i
+
