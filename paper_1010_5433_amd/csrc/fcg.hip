@@ -43,6 +43,7 @@ struct FcgState {
     double tol2bb;      // tol^2 |b|^2
     double best;        // smallest iterated |r|^2 so far
     double resid_true2; // |b - A x|^2 of the last check
+    double rz_snap;     // <r, z> of the current direction, kept for the fused beta step
     int since_best;
     int iter;
     int max_iter;
@@ -97,27 +98,10 @@ __global__ void __launch_bounds__(kFcgBlock) k_fcg_start(FcgState *st, const dou
     }
 }
 
-// alpha = <r, z> / <p, A p>
-__global__ void __launch_bounds__(kFcgBlock) k_fcg_alpha(FcgState *st, const double *part, int n) {
-    __shared__ double red[kFcgBlock / kWave];
-    if (st->run != FCG_RUNNING) return;
-    const double pq = fixed_sum(part, n, red);
-    if (threadIdx.x == 0) {
-        if (!(pq > 0.0) || !isfinite(pq)) st->run = FCG_FALLBACK;
-        else st->alpha = st->rz / pq;
-    }
-}
-
-// |r|^2, convergence, stagnation; beta (Polak-Ribiere) and the new <r, z>.
+// |r|^2, convergence, stagnation; beta (Polak-Ribiere) and the new <r, z>,
+// from the reduced sums (thread 0 of one workgroup).
 // r_{k+1} - r_k = -alpha_k q_k, so <z_{k+1}, r_{k+1} - r_k> = -alpha_k <z_{k+1}, q_k>.
-__global__ void __launch_bounds__(kFcgBlock) k_fcg_beta(FcgState *st, const double *part_rr, int n_rr,
-                                                     const double *part_a, const double *part_b, int n_ab) {
-    __shared__ double red[kFcgBlock / kWave];
-    if (st->run != FCG_RUNNING) return;
-    const double rr = fixed_sum(part_rr, n_rr, red);
-    const double za = -st->alpha * fixed_sum(part_a, n_ab, red);
-    const double rz = fixed_sum(part_b, n_ab, red);
-    if (threadIdx.x != 0) return;
+__device__ __forceinline__ void fcg_beta_step(FcgState *st, double rr, double za, double rz) {
     st->iter += 1;
     st->rr = rr;
     if (!isfinite(rr)) {
@@ -147,12 +131,26 @@ __global__ void __launch_bounds__(kFcgBlock) k_fcg_beta(FcgState *st, const doub
     st->rz = rz;
 }
 
-// x += alpha p; r -= alpha q; r32 = (float) r; partial |r|^2
-__global__ void __launch_bounds__(kFcgBlock) k_fcg_step(const FcgState *st, double2 *x, double2 *r, float2 *r32,
-                                                     const double2 *p, const double2 *q, int64_t n, double *part) {
+// alpha with the step, beta with the direction: every workgroup reduces the
+// previous kernel's partials itself, in one fixed order (so all workgroups
+// hold the same scalars, and every run the same bits); workgroup 0 also
+// advances the state.  A workgroup that runs after workgroup 0 ended the
+// iteration (converged, fall-back, limit) may still write p: the host then
+// restarts from p = z or leaves p unused.
+__global__ void __launch_bounds__(kFcgBlock) k_fcg_step_fused(FcgState *st, const double *part_pq, int n_pq,
+                                                           double2 *x, double2 *r, float2 *r32, const double2 *p,
+                                                           const double2 *q, int64_t n, double *part) {
     __shared__ double red[kFcgBlock / kWave];
     if (st->run != FCG_RUNNING) return;
-    const double alpha = st->alpha;
+    const double pq = fixed_sum(part_pq, n_pq, red);
+    const bool bad = !(pq > 0.0) || !isfinite(pq);
+    const double alpha = st->rz / pq;   // rz is not written by this kernel
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rz_snap = st->rz;
+        if (bad) st->run = FCG_FALLBACK;
+        else st->alpha = alpha;
+    }
+    if (bad) return;
     double acc = 0.0;
     for (int64_t j = (int64_t)blockIdx.x * kFcgBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kFcgBlock) {
         const double2 pv = p[j], qv = q[j];
@@ -168,6 +166,25 @@ __global__ void __launch_bounds__(kFcgBlock) k_fcg_step(const FcgState *st, doub
     }
     const double s = block_sum(acc, red);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kFcgBlock) k_fcg_dir_fused(FcgState *st, const double *part_rr, int n_rr,
+                                                          const double *part_a, const double *part_b, int n_ab,
+                                                          double2 *p, const float2 *z32, int64_t n) {
+    __shared__ double red[kFcgBlock / kWave];
+    if (st->run != FCG_RUNNING) return;
+    const double rr = fixed_sum(part_rr, n_rr, red);
+    const double za = -st->alpha * fixed_sum(part_a, n_ab, red);
+    const double rz = fixed_sum(part_b, n_ab, red);
+    const double beta = za / st->rz_snap;   // workgroup 0 rewrites rz below, not rz_snap
+    if (blockIdx.x == 0 && threadIdx.x == 0) fcg_beta_step(st, rr, za, rz);
+    for (int64_t j = (int64_t)blockIdx.x * kFcgBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kFcgBlock) {
+        const float2 zv = z32[j];
+        double2 pv = p[j];
+        pv.x = double(zv.x) + beta * pv.x;
+        pv.y = double(zv.y) + beta * pv.y;
+        p[j] = pv;
+    }
 }
 
 // r32 = (float) r (start and restart)
@@ -202,19 +219,6 @@ __global__ void __launch_bounds__(kFcgBlock) k_fcg_z(const FcgState *st, const f
     if (threadIdx.x == 0) {
         part_a[blockIdx.x] = sa;
         part_b[blockIdx.x] = sb;
-    }
-}
-
-// p = z + beta p
-__global__ void __launch_bounds__(kFcgBlock) k_fcg_dir(const FcgState *st, double2 *p, const float2 *z32, int64_t n) {
-    if (st->run != FCG_RUNNING) return;
-    const double beta = st->beta;
-    for (int64_t j = (int64_t)blockIdx.x * kFcgBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kFcgBlock) {
-        const float2 zv = z32[j];
-        double2 pv = p[j];
-        pv.x = double(zv.x) + beta * pv.x;
-        pv.y = double(zv.y) + beta * pv.y;
-        p[j] = pv;
     }
 }
 
@@ -327,19 +331,16 @@ stag_status fcg_solve(stag_lattice *lat, double mass, double shift, const void *
         e.partial = pq;
         err = launch_dslash(true, lat->nrow, DS_NORMAL_DOT, e, s);
         if (err != hipSuccess) return err;
-        hipLaunchKernelGGL(k_fcg_alpha, dim3(1), dim3(kFcgBlock), 0, s, dst, (const double *)pq, ds_grid);
-        hipLaunchKernelGGL(k_fcg_step, dim3(grid), dim3(kFcgBlock), 0, s, (const FcgState *)dst, x, r, r32,
-                           (const double2 *)p, (const double2 *)q, ne, prr);
+        hipLaunchKernelGGL(k_fcg_step_fused, dim3(grid), dim3(kFcgBlock), 0, s, dst, (const double *)pq, ds_grid, x,
+                           r, r32, (const double2 *)p, (const double2 *)q, ne, prr);
         NetArgs a = net_args(net, lat, r32, z32, nb, false);
         a.skip = skip;
         err = net_launch_forward(a, 1, mode, s);
         if (err != hipSuccess) return err;
         hipLaunchKernelGGL(k_fcg_z, dim3(grid), dim3(kFcgBlock), 0, s, (const FcgState *)dst, (const float2 *)z32, p, 0,
                            (const double2 *)r, (const double2 *)q, ne, pa, pb);
-        hipLaunchKernelGGL(k_fcg_beta, dim3(1), dim3(kFcgBlock), 0, s, dst, (const double *)prr, grid,
-                           (const double *)pa, (const double *)pb, grid);
-        hipLaunchKernelGGL(k_fcg_dir, dim3(grid), dim3(kFcgBlock), 0, s, (const FcgState *)dst, p, (const float2 *)z32,
-                           ne);
+        hipLaunchKernelGGL(k_fcg_dir_fused, dim3(grid), dim3(kFcgBlock), 0, s, dst, (const double *)prr, grid,
+                           (const double *)pa, (const double *)pb, grid, p, (const float2 *)z32, ne);
         return hipGetLastError();
     };
     int rep[2] = {0, 0};
