@@ -227,6 +227,28 @@ def rational_experiment(lat, mass, src, tol, n_poles):
     out["two_flavour"] = dict(heatbath_quarter_s=round(t_h, 4), heatbath_poles=20, heatbath_max_rel_err=herr,
                               action_s=round(t_a, 4), action_over_xi2_minus_1=action / xx - 1,
                               iters=[st1["iters"], st2["iters"]])
+    # several pseudo-fermions: the heatbath of 4 fields in one batched call
+    # against 4 single calls
+    nf = 4
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1234)
+    xis = [torch.randn(src.shape, generator=gen, dtype=torch.float64, device="cuda") * (0.5 ** 0.5) for _ in range(nf)]
+    lat.rational_apply_multi(mass, h0, hl, hs, xis, tol=tol)   # warm-up (launch shape)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rcm, stm, _ = lat.rational_apply_multi(mass, h0, hl, hs, xis, tol=tol)
+    torch.cuda.synchronize()
+    t_multi = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for xk in xis:
+        lat.rational_apply(mass, h0, hl, hs, xk, tol=tol)
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    if rcm != 0:
+        raise RuntimeError(f"batched rational application failed: {rcm}")
+    log(f"heatbath of {nf} pseudo-fermions: {t_multi:.4f} s in one call vs {t_single:.4f} s one after another")
+    out["pseudo_fermions"] = dict(fields=nf, batched_s=round(t_multi, 4), one_by_one_s=round(t_single, 4),
+                                  speedup=round(t_single / t_multi, 3))
     return out
 
 

@@ -252,6 +252,20 @@ stag_status stag_rational_apply(stag_lattice *lat, double mass, double alpha0, c
                                 const double *shifts, int n, const void *src, void *out, double tol,
                                 int max_iter, double *dot, stag_cg_stats *stats, void *stream);
 
+/* The same rational function applied to n_rhs (1..64) fields of one
+ * lattice -- several pseudo-fermions (Section 2) -- in one call: each field
+ * is a system of the batched solver, so the multi-RHS half-Dslash loads
+ * every link once for up to 8 fields.  srcs and outs are HOST arrays of
+ * n_rhs device pointers (STAG_F64 library vectors; no output may alias a
+ * source or another output); dots (host, n_rhs entries, may be NULL)
+ * receives Re <src_k, out_k>; stats (host, n_rhs entries, may be NULL) as
+ * for stag_rational_apply.  Each field stops on its own; the error bound of
+ * stag_rational_apply holds for each.  Synchronous. */
+stag_status stag_rational_apply_multi(stag_lattice *lat, double mass, double alpha0, const double *alphas,
+                                      const double *shifts, int n, const void *const *srcs, void *const *outs,
+                                      int n_rhs, double tol, int max_iter, double *dots, stag_cg_stats *stats,
+                                      void *stream);
+
 /* Zolotarev's optimal relative approximation of x^(-1/2) (power = -1) or
  * x^(1/2) = x * x^(-1/2) (power = +1) on [lo, hi] (0 < lo < hi), with n
  * poles (1..64): writes *alpha0, alphas[n], shifts[n] (HOST arrays; all

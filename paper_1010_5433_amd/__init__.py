@@ -166,6 +166,28 @@ class Lattice:
                                            _stream()), "stag_rational_apply")
         return out, rc, st.to_dict(n), dot.value
 
+    def rational_apply_multi(self, mass, alpha0, alphas, shifts, srcs, outs=None, tol=1e-10,
+                             max_iter=100000):
+        """The rational function applied to several fields in one batched
+        call.  Returns (outs, status, list of stats, list of Re <src_k, out_k>)."""
+        shifts = [float(s) for s in shifts]
+        alphas = [float(a) for a in alphas]
+        n, m = len(shifts), len(srcs)
+        if len(alphas) != n:
+            raise ValueError("alphas and shifts differ in length")
+        if outs is None:
+            outs = [torch.empty_like(v) for v in srcs]
+        sh = (ctypes.c_double * n)(*shifts)
+        al = (ctypes.c_double * n)(*alphas)
+        sp = (ctypes.c_void_p * m)(*[_ptr(v).value for v in srcs])
+        op = (ctypes.c_void_p * m)(*[_ptr(v).value for v in outs])
+        dots = (ctypes.c_double * m)()
+        st = (CgStats * m)()
+        rc = _check(_L.stag_rational_apply_multi(self._h, float(mass), float(alpha0), al, sh, n, sp, op, m,
+                                                 float(tol), int(max_iter), dots, st, _stream()),
+                    "stag_rational_apply_multi")
+        return outs, rc, [st[k].to_dict(n) for k in range(m)], list(dots)
+
     def cg(self, mass, shift, src: torch.Tensor, x: torch.Tensor, tol=1e-10, max_iter=100000,
            prec="f64"):
         """Single-shift CG for (M + shift) x = src from the given x (overwritten)."""

@@ -98,6 +98,9 @@ SIGNATURES = {
     "stag_fcg_solve": (_i, [_v, _d, _d, _v, _v, _v, _i, _d, _i, ctypes.POINTER(CgStats), _v]),
     "stag_rational_apply": (_i, [_v, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d), _i, _v, _v, _d, _i,
                                  ctypes.POINTER(_d), ctypes.POINTER(CgStats), _v]),
+    "stag_rational_apply_multi": (_i, [_v, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d), _i,
+                                       ctypes.POINTER(_v), ctypes.POINTER(_v), _i, _d, _i, ctypes.POINTER(_d),
+                                       ctypes.POINTER(CgStats), _v]),
     "stag_zolotarev": (_i, [_i, _d, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
                             ctypes.POINTER(_d)]),
     "stag_rational_power": (_i, [_d, _d, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),

@@ -293,6 +293,35 @@ stag_status stag_rational_apply(stag_lattice *lat, double mass, double alpha0, c
     }
 }
 
+stag_status stag_rational_apply_multi(stag_lattice *lat, double mass, double alpha0, const double *alphas,
+                                      const double *shifts, int n, const void *const *srcs, void *const *outs,
+                                      int n_rhs, double tol, int max_iter, double *dots, stag_cg_stats *stats,
+                                      void *stream) {
+    try {
+        STAG_TRY(check_lattice(lat, true));
+        STAG_TRY(check_solver_args(mass, tol, max_iter, STAG_F64));
+        if (!alphas || !shifts || !srcs || !outs) return invalid("null argument");
+        if (n < 1 || n > STAG_MAX_SHIFTS) return invalid("n must be in [1, 64]");
+        if (n_rhs < 1 || n_rhs > 64) return invalid("n_rhs must be in [1, 64]");
+        if (!std::isfinite(alpha0)) return invalid("alpha0 must be finite");
+        for (int i = 0; i < n; ++i) {
+            if (!(shifts[i] >= 0) || !std::isfinite(shifts[i])) return invalid("shifts must be >= 0 and finite");
+            if (!std::isfinite(alphas[i])) return invalid("alphas must be finite");
+        }
+        for (int k = 0; k < n_rhs; ++k) {
+            if (!srcs[k] || !outs[k]) return invalid("null field pointer");
+            for (int j = 0; j < n_rhs; ++j)
+                if (outs[k] == srcs[j] || (j != k && outs[k] == outs[j]))
+                    return invalid("an output aliases a source or another output");
+        }
+        return rational_apply_multi(lat, mass, alpha0, alphas, shifts, n, srcs, outs, n_rhs, tol, max_iter, dots,
+                                    stats, static_cast<hipStream_t>(stream));
+    } catch (...) {
+        set_error("host allocation failed");
+        return STAG_ENOMEM;
+    }
+}
+
 stag_status stag_zolotarev(int power, double lo, double hi, int n, double *alpha0, double *alphas, double *shifts,
                            double *max_rel_err) {
     if (power != -1 && power != 1) return invalid("power must be -1 (x^-1/2) or +1 (x^1/2)");

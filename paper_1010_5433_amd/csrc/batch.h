@@ -35,7 +35,7 @@ struct BSys {
     int nchunk_bl;         // vector partials: ceil(3 Vh / kBChunk)
     int x_init;            // start from xhi[0] (single shift) instead of zero
     int dlen;              // deferred shift updates in blocks of dlen iterations (0: every iteration)
-    int pad;
+    int rat;               // rational application: the pass sums the weighted increments into out
     double m2;             // mass^2
     double shifts[kMaxShifts];
     MsState *st;
@@ -43,6 +43,8 @@ struct BSys {
     double *part_bl;
     const double2 *src;
     void *r, *ap, *t;      // iteration precision
+    double2 *out;          // rational application output (double precision)
+    double w0;             // its weight of src
     void *ring;            // deferred: dlen residual vectors, r^k in slot k mod dlen
     void *pd;              // deferred: the base direction the operator acts on
     DeferHist *hist;       // deferred: recorded scalars and pass coefficients
@@ -106,6 +108,11 @@ struct BSpec {
     const void *src;        // double library vector
     void *const *sols;      // double library vectors: outputs (and the start when x_init)
     bool x_init;
+    // rational application (double precision, zero start): rat_out =
+    // rat_w0 src + sum_i rat_w[i] (M + shifts[i])^-1 src, sols unused
+    const double *rat_w = nullptr;
+    double rat_w0 = 0.0;
+    void *rat_out = nullptr;
 };
 
 struct BOut {
@@ -113,6 +120,7 @@ struct BOut {
     int iters_shift[kMaxShifts];
     double resid_iter[kMaxShifts];
     double resid_true[kMaxShifts];
+    double dot;             // rational application: Re <src, out>
 };
 
 struct BOptions {
@@ -130,6 +138,9 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
 stag_status refine_batched(const BSpec *spec, int nsys, const BOptions &opt, stag_cg_stats *stats, hipStream_t s);
 stag_status batched_solve(const BSpec *spec, int nsys, const BOptions &opt, bool mixed, stag_cg_stats *stats,
                           hipStream_t s);
+stag_status rational_apply_multi(stag_lattice *lat, double mass, double alpha0, const double *alphas,
+                                 const double *shifts, int n, const void *const *srcs, void *const *outs, int n_rhs,
+                                 double tol, int max_iter, double *dots, stag_cg_stats *stats, hipStream_t s);
 // launch shape chosen by the last batched solve on this thread
 BDslashCfg last_batch_cfg();
 

@@ -51,6 +51,11 @@ __global__ void __launch_bounds__(kBBlock) kb_vec(BView v, int op, int it) {
             const T2<R> bv = mk2<R>(R(b.x), R(b.y));
             r[j] = bv;
             if (s.dlen) pd[j] = bv;
+            if (s.rat) {   // out = w0 src; no solution vectors
+                s.out[j] = make_double2(s.w0 * b.x, s.w0 * b.y);
+                for (int i = 0; i < s.n; ++i) static_cast<T2<R> *>(s.p[i])[j] = bv;
+                continue;
+            }
             for (int i = 0; i < s.n; ++i) {
                 static_cast<T2<R> *>(s.p[i])[j] = bv;
                 static_cast<T2<R> *>(s.x[i])[j] = mk2<R>(R(0), R(0));
@@ -186,16 +191,23 @@ __global__ void __launch_bounds__(kBBlock) kb_vec(BView v, int op, int it) {
             T2<R> rr[kDefer];
 #pragma unroll
             for (int m = 0; m < kDefer; ++m) rr[m] = m < nv ? ring[m * n + j] : mk2<R>(R(0), R(0));
+            T2<R> acc;
+            if (s.rat) acc = mk2<R>(R(s.out[j].x), R(s.out[j].y));
             for (int i = 0; i < s.n; ++i) {
                 if (!h->act[i]) continue;
                 T2<R> *pi = static_cast<T2<R> *>(s.p[i]);
-                T2<R> *xi = static_cast<T2<R> *>(s.x[i]);
                 T2<R> pv = pi[j];
-                T2<R> xv = xi[j];
-                defer_combine<T2<R>, R>(h, i, rr, xv, pv);
-                xi[j] = xv;
+                if (s.rat) {   // weighted increments of every shift into out
+                    defer_combine<T2<R>, R>(h, i, rr, acc, pv);
+                } else {
+                    T2<R> *xi = static_cast<T2<R> *>(s.x[i]);
+                    T2<R> xv = xi[j];
+                    defer_combine<T2<R>, R>(h, i, rr, xv, pv);
+                    xi[j] = xv;
+                }
                 pi[j] = pv;
             }
+            if (s.rat) s.out[j] = make_double2(double(acc.x), double(acc.y));
         }
     } else if (op == BV_DEMOTE) {
         if (st->rel_skip) return;
@@ -225,7 +237,7 @@ hipError_t launch_bvec(bool dbl, BView v, int op, int max_blocks, hipStream_t s,
 __global__ void __launch_bounds__(kWave) kb_defer_coef(BView v) {
     const BSys &s = v.sys[blockIdx.x];
     if (!s.dlen) return;
-    defer_coef_step(s.n, s.hist);
+    defer_coef_step(s.n, s.hist, s.st->rat ? s.st->wgt : nullptr);
 }
 
 hipError_t launch_bdefer_coef(BView v, hipStream_t s) {

@@ -70,6 +70,53 @@ stag_status refine_batched(const BSpec *spec, int nsys, const BOptions &opt, sta
     return worst;
 }
 
+// One rational function applied to n_rhs fields of one lattice (several
+// pseudo-fermions): every field is a deferred system of the batch, so the
+// multi-RHS Dslash loads each link once for up to 8 of them.
+stag_status rational_apply_multi(stag_lattice *lat, double mass, double alpha0, const double *alphas,
+                                 const double *shifts, int n, const void *const *srcs, void *const *outs, int n_rhs,
+                                 double tol, int max_iter, double *dots, stag_cg_stats *stats, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<BSpec> spec(n_rhs);
+    for (int k = 0; k < n_rhs; ++k) {
+        spec[k].lat = lat;
+        spec[k].mass = mass;
+        spec[k].n = n;
+        spec[k].shifts = shifts;
+        spec[k].src = srcs[k];
+        spec[k].sols = nullptr;
+        spec[k].x_init = false;
+        spec[k].rat_w = alphas;
+        spec[k].rat_w0 = alpha0;
+        spec[k].rat_out = outs[k];
+    }
+    BOptions opt;
+    std::memset(&opt, 0, sizeof(opt));
+    opt.tol = tol;
+    opt.max_iter = max_iter;
+    opt.dbl = true;
+    std::vector<BOut> out(n_rhs);
+    STAG_TRY(run_batched(spec.data(), n_rhs, opt, out.data(), s));
+    stag_status rc = STAG_OK;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int k = 0; k < n_rhs; ++k) {
+        if (dots) dots[k] = out[k].dot;
+        if (stats) {
+            stag_cg_stats &st = stats[k];
+            std::memset(&st, 0, sizeof(st));
+            st.iters = out[k].iters;
+            for (int i = 0; i < n; ++i) {
+                st.iters_shift[i] = out[k].iters_shift[i];
+                st.resid_iter[i] = out[k].resid_iter[i];
+            }
+            st.seconds = secs;
+        }
+        const stag_status sk = status_of_ms(out[k].status);
+        if (sk == STAG_EBREAKDOWN || (sk != STAG_OK && rc == STAG_OK)) rc = sk;
+    }
+    return rc;
+}
+
 stag_status batched_solve(const BSpec *spec, int nsys, const BOptions &opt0, bool mixed, stag_cg_stats *stats,
                           hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();

@@ -174,8 +174,11 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
     const bool any_init = std::any_of(spec, spec + nsys, [](const BSpec &p) { return p.x_init; });
     const bool all_init = std::all_of(spec, spec + nsys, [](const BSpec &p) { return p.x_init; });
     if (any_init && !all_init) return invalid("a batch is either all zero-start or all warm-start");
-    for (int k = 0; k < nsys; ++k)
+    for (int k = 0; k < nsys; ++k) {
         if (spec[k].x_init && spec[k].n != 1) return invalid("a warm-started system has exactly one shift");
+        if (spec[k].rat_out && (!opt.dbl || spec[k].x_init))
+            return invalid("rational applications run in double precision from a zero start");
+    }
 
     // ---- lattices and their systems
     std::vector<stag_lattice *> lats;
@@ -204,11 +207,14 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
     const int dlen_all = dbl ? kDefer : 8;
     if (!dbl && opt.reliable_every > 0 && opt.reliable_every % dlen_all != 0)
         return invalid("reliable updates must fall on deferred passes");
-    auto dlen_of = [&](int k) { return (spec[k].n >= 2 && !spec[k].x_init) ? dlen_all : 0; };
+    auto dlen_of = [&](int k) {
+        return ((spec[k].n >= 2 && !spec[k].x_init) || spec[k].rat_out) ? dlen_all : 0;
+    };
 
     // ---- work arena (carved from the first lattice's handle)
-    int max_ds = 1;
-    for (int l = 0; l < nlat; ++l) max_ds = std::max(max_ds, dslash_grid(lats[l]->g, kDslashBlock));
+    int max_ds = 1;   // partials of the single-system residual and dot kernels
+    for (int l = 0; l < nlat; ++l)
+        max_ds = std::max(max_ds, std::max(dslash_grid(lats[l]->g, kDslashBlock), blas_grid(3 * (int64_t)lats[l]->Vh)));
     size_t bytes = al256(sizeof(BLat) * nlat) + al256(sizeof(BSys) * nsys) + al256(sizeof(MsState) * nsys) + 256;
     for (int k = 0; k < nsys; ++k) {
         const int64_t vh = spec[k].lat->Vh;
@@ -274,9 +280,13 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
         y.rhi = reinterpret_cast<double2 *>(take(v64));
         for (int i = 0; i < sp.n; ++i) {
             y.p[i] = take(vb);
+            if (sp.rat_out) continue;   // no solution vectors
             y.xhi[i] = static_cast<double2 *>(sp.sols[i]);
             y.x[i] = dbl ? sp.sols[i] : take(vb);
         }
+        y.rat = sp.rat_out ? 1 : 0;
+        y.out = static_cast<double2 *>(sp.rat_out);
+        y.w0 = sp.rat_w0;
         if (y.dlen) {
             y.ring = take((size_t)y.dlen * al256(vb));
             y.pd = take(vb);
@@ -290,6 +300,9 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
         st.max_iter = opt.max_iter;
         st.rel_delta2 = (!dbl && opt.reliable_every > 0) ? 0.01 : 0.0;
         st.hist = y.hist;   // emptied by the start step
+        st.rat = y.rat;
+        if (y.rat)
+            for (int i = 0; i < sp.n; ++i) st.wgt[i] = sp.rat_w[i];
         for (int i = 0; i < sp.n; ++i) st.shift_rel[i] = sp.shifts[i] - sp.shifts[y.base];
         max_n = std::max(max_n, sp.n);
         max_blocks = std::max(max_blocks, (y.nchunk_bl + kBBlock / kWave - 1) / (kBBlock / kWave));
@@ -510,18 +523,29 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
         STAG_HIP(launch_bvec(dbl, v, BV_DEFER_APPLY, max_blocks, s));
     }
     if (!dbl) STAG_HIP(launch_bvec(dbl, v, BV_FLUSH_FINAL, max_blocks, s));
-    for (int k = 0; k < nsys; ++k)
+    for (int k = 0; k < nsys; ++k) {
+        if (spec[k].rat_out) {
+            // no solutions are kept: Re <src, out> instead of true residuals
+            const int64_t ne = 3 * spec[k].lat->Vh;
+            const int g = blas_grid(ne);
+            STAG_HIP(launch_dot_re(static_cast<const double2 *>(spec[k].src),
+                                   static_cast<const double2 *>(spec[k].rat_out), ne, pres[k], g, s));
+            STAG_HIP(launch_reduce_tail(d_st + k, pres[k], g, TAIL_SCRATCH, 0, s));
+            continue;
+        }
         for (int i = 0; i < spec[k].n; ++i) {
             STAG_HIP(residual(k, i, nullptr, nullptr));
             STAG_HIP(launch_reduce_tail(d_st + k, pres[k], dslash_grid(spec[k].lat->g, kDslashBlock), TAIL_TRUE_RESID,
                                         i, s));
         }
+    }
     STAG_HIP(hipMemcpyAsync(h_st.data(), d_st, sizeof(MsState) * nsys, hipMemcpyDeviceToHost, s));
     STAG_HIP(hipStreamSynchronize(s));
     for (int k = 0; k < nsys; ++k) {
         const MsState &st = h_st[k];
         BOut &o = out[k];
         o.status = st.status;
+        o.dot = st.scratch[0];
         o.iters = st.iter;
         o.n_reliable = st.n_reliable;
         for (int i = 0; i < st.n; ++i) {

@@ -156,6 +156,53 @@ def test_quarter_power_four_times_is_the_operator():
     assert rel(unpack(lat, v), mb) <= 4 * herr + 1e-9
 
 
+@pytest.mark.parametrize("dims,nf", [((4, 4, 4, 4), 3), ((8, 8, 8, 8), 10)])
+def test_rational_apply_multi(orc, dims, nf):
+    """Several pseudo-fermion fields in one batched call (multi-RHS Dslash,
+    groups of up to 8): each equals the single-field application to the
+    stopping bound, matches the oracle, and carries its own Re <src, out>; a
+    zero field among them gives zero."""
+    import torch
+    import paper_1010_5433_amd as stag
+    log(f"rational multi {dims} x {nf}")
+    m = 0.05
+    U = links_np(dims, "smooth", 0.5, 91)
+    lat = lattice_with_links(dims, U, "12")
+    a0, al, sh, err = stag.zolotarev(-1, m * m, m * m + 16.0, 12)
+    bs = [syn.gaussian_source(dims, 900 + k) for k in range(nf)]
+    bs[1] = np.zeros_like(bs[1])
+    srcs = [pack(lat, b) for b in bs]
+    outs, rc, stats, dots = lat.rational_apply_multi(m, a0, al, sh, srcs)
+    torch.cuda.synchronize()
+    assert rc == 0
+    bound = lambda b: _bound(b, m, al, sh, 1e-10)
+    for k in range(nf):
+        got = unpack(lat, outs[k])
+        if k == 1:
+            assert float(np.abs(got).max()) == 0.0 and dots[k] == 0.0 and stats[k]["iters"] == 0
+            continue
+        one, rc1, st1, dot1 = lat.rational_apply(m, a0, al, sh, srcs[k])
+        assert np.linalg.norm(got - unpack(lat, one)) <= 2 * bound(bs[k]) + 1e-13 * np.linalg.norm(got)
+        assert abs(stats[k]["iters"] - st1["iters"]) <= 1
+        if k in (0, nf - 1):
+            want, rco, info = orc.rational_apply(dims, U, m, a0, al, sh, bs[k], tol=1e-10)
+            assert np.linalg.norm(got - want) <= 2 * bound(bs[k]) + 1e-13 * np.linalg.norm(want)
+            assert abs(dots[k] - info["dot"]) <= 1e-9 * abs(info["dot"])
+
+
+def test_rational_apply_multi_rejects_aliases():
+    import paper_1010_5433_amd as stag
+    dims = (4, 4, 4, 4)
+    lat = lattice_with_links(dims, syn.haar_links(dims, 1))
+    a = pack(lat, syn.gaussian_source(dims, 2))
+    b = pack(lat, syn.gaussian_source(dims, 3))
+    with pytest.raises(stag.StagError):
+        lat.rational_apply_multi(0.1, 0.0, [1.0], [0.0], [a, b], outs=[b, a])
+    with pytest.raises(stag.StagError):
+        out = pack(lat, np.zeros((128, 3), np.complex128))
+        lat.rational_apply_multi(0.1, 0.0, [1.0], [0.0], [a, b], outs=[out, out])
+
+
 def test_rational_apply_edge_cases():
     import torch
     import paper_1010_5433_amd as stag
