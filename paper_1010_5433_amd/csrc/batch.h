@@ -93,9 +93,10 @@ hipError_t launch_bdefer_coef(BView v, hipStream_t s);
 enum BTail {
     BT_INIT = 0,       // zero start: rho = |b|^2 from part_bl
     BT_ALPHA = 1,      // <p, A p> from part_ds
-    BT_BETA = 2        // |r|^2 from part_bl
+    BT_BETA = 2,       // |r|^2 from part_bl
+    BT_TRUE_RESID = 3  // |b - (M + sigma_idx) x_idx|^2 from part_ds (systems with a shift idx, no rational ones)
 };
-hipError_t launch_btail(BView v, int kind, hipStream_t s);
+hipError_t launch_btail(BView v, int kind, hipStream_t s, int idx = 0);
 hipError_t launch_ball_done(BView v, int *flag, hipStream_t s);
 
 // ---------------------------------------------------------------- host side

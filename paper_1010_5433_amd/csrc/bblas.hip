@@ -249,10 +249,18 @@ hipError_t launch_bdefer_coef(BView v, hipStream_t s) {
 // One workgroup per system: sum the partials in a fixed order, then apply
 // the step of the shifted recursion.
 constexpr int kBTailBlock = 256;
-__global__ void __launch_bounds__(kBTailBlock) kb_tail(BView v, int kind) {
+__global__ void __launch_bounds__(kBTailBlock) kb_tail(BView v, int kind, int idx) {
     __shared__ double red[kBTailBlock / kWave];
     const BSys &s = v.sys[blockIdx.x];
     MsState *st = s.st;
+    if (kind == BT_TRUE_RESID) {
+        if (s.rat || idx >= s.n) return;
+        double t = 0.0;
+        for (int k = threadIdx.x; k < s.nchunk_ds; k += kBTailBlock) t += s.part_ds[k];
+        const double total = block_sum(t, red);
+        if (threadIdx.x == 0) st->resid_true[idx] = st->bnorm2 > 0.0 ? sqrt(total / st->bnorm2) : sqrt(total);
+        return;
+    }
     if (kind == BT_ALPHA) {
         if (threadIdx.x == 0) st->upd_valid = 0;  // retire the previous update
         if (st->done) return;
@@ -269,9 +277,9 @@ __global__ void __launch_bounds__(kBTailBlock) kb_tail(BView v, int kind) {
     else ms_beta_step(st, total);
 }
 
-hipError_t launch_btail(BView v, int kind, hipStream_t s) {
+hipError_t launch_btail(BView v, int kind, hipStream_t s, int idx) {
     if (v.nsys <= 0) return hipSuccess;
-    hipLaunchKernelGGL(kb_tail, dim3(v.nsys), dim3(kBTailBlock), 0, s, v, kind);
+    hipLaunchKernelGGL(kb_tail, dim3(v.nsys), dim3(kBTailBlock), 0, s, v, kind, idx);
     return hipGetLastError();
 }
 

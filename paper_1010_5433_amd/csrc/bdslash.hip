@@ -39,14 +39,17 @@ struct BDArgs {
     int pad;
     const void *in[kMaxRpt];     // OE: p_base; EO: t
     void *out[kMaxRpt];          // OE: t; EO: ap
-    const void *aux[kMaxRpt];    // EO: p_base
-    double c[kMaxRpt];           // EO: m^2 + sigma_base
+    const void *aux[kMaxRpt];    // EO: p_base; RESID: x
+    const void *rhs[kMaxRpt];    // RESID: b
+    double c[kMaxRpt];           // EO: m^2 + sigma_base; RESID: m^2 + sigma
     double *part[kMaxRpt];       // EO: one partial of <p, ap> per 64 consecutive sites
     int nchunk[kMaxRpt];         // partials of each system (ceil(V/2 / 64))
-    const int *done[kMaxRpt];    // a system whose solve ended is skipped
+    const int *done[kMaxRpt];    // a system whose solve ended is skipped (null: never)
 };
 
-enum BDRole { BD_OE = 0, BD_EO = 1 };
+// OE: t = D_oe p; EO: q = c p - D_eo t with <p, q> partials; RESID: r = b - (c x - D_eo t)
+// with |r|^2 partials (double precision; r stored only where out is non-null)
+enum BDRole { BD_OE = 0, BD_EO = 1, BD_RESID = 2 };
 
 template <typename R, int NROW, int RPT, int ROLE>
 __global__ void __launch_bounds__(256) kb_dslash(BDArgs a) {
@@ -55,7 +58,7 @@ __global__ void __launch_bounds__(256) kb_dslash(BDArgs a) {
     bool any = false;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        live[r] = r < a.nrhs && !*a.done[r];
+        live[r] = r < a.nrhs && !(a.done[r] && *a.done[r]);
         any = any || live[r];
     }
     if (!any) return;
@@ -101,6 +104,17 @@ __global__ void __launch_bounds__(256) kb_dslash(BDArgs a) {
             if (ROLE == BD_OE) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) o.c[c] = half * acc[r].c[c];
+            } else if (ROLE == BD_RESID) {
+                const vec3<R> xv = load_vec<R>(a.aux[r], vh, i);
+                const vec3<R> bv = load_vec<R>(a.rhs[r], vh, i);
+                const R cc = R(a.c[r]);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    o.c[k] = bv.c[k] - (cc * xv.c[k] - half * acc[r].c[k]);
+                    part[r] += double(o.c[k].re) * double(o.c[k].re) + double(o.c[k].im) * double(o.c[k].im);
+                }
+                if (a.out[r]) store_vec<R>(a.out[r], vh, i, o);
+                continue;
             } else {
                 const vec3<R> pv = load_vec<R>(a.aux[r], vh, i);
                 const R cc = R(a.c[r]);
@@ -113,7 +127,7 @@ __global__ void __launch_bounds__(256) kb_dslash(BDArgs a) {
             store_vec<R>(a.out[r], vh, i, o);
         }
     }
-    if (ROLE == BD_EO) {
+    if (ROLE == BD_EO || ROLE == BD_RESID) {
         // one partial per 64 consecutive sites, whatever the block size
         const int chunk = (i - (threadIdx.x & (kWave - 1))) >> 6;
 #pragma unroll
@@ -129,7 +143,9 @@ template <typename R, int NROW, int RPT>
 static hipError_t bd_launch_rpt(int role, int block, const BDArgs &a, hipStream_t s) {
     const dim3 grid((a.g.Vh + block - 1) / block), blk(block);
     if (role == BD_OE) hipLaunchKernelGGL((kb_dslash<R, NROW, RPT, BD_OE>), grid, blk, 0, s, a);
-    else hipLaunchKernelGGL((kb_dslash<R, NROW, RPT, BD_EO>), grid, blk, 0, s, a);
+    else if (role == BD_EO) hipLaunchKernelGGL((kb_dslash<R, NROW, RPT, BD_EO>), grid, blk, 0, s, a);
+    else if (sizeof(R) == sizeof(double)) hipLaunchKernelGGL((kb_dslash<double, NROW, RPT, BD_RESID>), grid, blk, 0, s, a);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -524,20 +540,48 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
     }
     if (!dbl) STAG_HIP(launch_bvec(dbl, v, BV_FLUSH_FINAL, max_blocks, s));
     for (int k = 0; k < nsys; ++k) {
-        if (spec[k].rat_out) {
-            // no solutions are kept: Re <src, out> instead of true residuals
-            const int64_t ne = 3 * spec[k].lat->Vh;
-            const int g = blas_grid(ne);
-            STAG_HIP(launch_dot_re(static_cast<const double2 *>(spec[k].src),
-                                   static_cast<const double2 *>(spec[k].rat_out), ne, pres[k], g, s));
-            STAG_HIP(launch_reduce_tail(d_st + k, pres[k], g, TAIL_SCRATCH, 0, s));
-            continue;
+        if (!spec[k].rat_out) continue;
+        // no solutions are kept: Re <src, out> instead of true residuals
+        const int64_t ne = 3 * spec[k].lat->Vh;
+        const int g = blas_grid(ne);
+        STAG_HIP(launch_dot_re(static_cast<const double2 *>(spec[k].src),
+                               static_cast<const double2 *>(spec[k].rat_out), ne, pres[k], g, s));
+        STAG_HIP(launch_reduce_tail(d_st + k, pres[k], g, TAIL_SCRATCH, 0, s));
+    }
+    // FP64 true residuals of every (system, shift): round i takes shift i of
+    // every system that has one, through the multi-RHS kernels (links loaded
+    // once for up to 8 systems of a lattice), then one tail for all systems
+    for (int i = 0; i < max_n; ++i) {
+        for (int l = 0; l < nlat; ++l) {
+            std::vector<int> in_round;
+            for (int k : members[l])
+                if (!spec[k].rat_out && i < spec[k].n) in_round.push_back(k);
+            const BDslashCfg rc8 = {cfg[l].block, 8};
+            for (size_t k0 = 0; k0 < in_round.size(); k0 += 8) {
+                BDArgs oe, eo;
+                std::memset(&oe, 0, sizeof(oe));
+                oe.g = lats[l]->g;
+                oe.links = h_lat[l].links64;
+                oe.nrhs = (int)std::min<size_t>(8, in_round.size() - k0);
+                eo = oe;
+                for (int r = 0; r < oe.nrhs; ++r) {
+                    const int k = in_round[k0 + r];
+                    const BSys &y = h_sys[k];
+                    oe.in[r] = y.xhi[i];
+                    oe.out[r] = y.t64;
+                    eo.in[r] = y.t64;
+                    eo.out[r] = nullptr;
+                    eo.aux[r] = y.xhi[i];
+                    eo.rhs[r] = spec[k].src;
+                    eo.c[r] = y.m2 + spec[k].shifts[i];
+                    eo.part[r] = y.part_ds;
+                    eo.nchunk[r] = y.nchunk_ds;
+                }
+                STAG_HIP(bd_launch(true, nrow, BD_OE, rc8, oe, s));
+                STAG_HIP(bd_launch(true, nrow, BD_RESID, rc8, eo, s));
+            }
         }
-        for (int i = 0; i < spec[k].n; ++i) {
-            STAG_HIP(residual(k, i, nullptr, nullptr));
-            STAG_HIP(launch_reduce_tail(d_st + k, pres[k], dslash_grid(spec[k].lat->g, kDslashBlock), TAIL_TRUE_RESID,
-                                        i, s));
-        }
+        STAG_HIP(launch_btail(v, BT_TRUE_RESID, s, i));
     }
     STAG_HIP(hipMemcpyAsync(h_st.data(), d_st, sizeof(MsState) * nsys, hipMemcpyDeviceToHost, s));
     STAG_HIP(hipStreamSynchronize(s));
