@@ -132,20 +132,6 @@ __global__ void __launch_bounds__(kBlasBlock) k_shift_update(const MsState *st, 
     }
 }
 
-// Base direction of a deferred solve: pd = r + beta pd (skipped once done).
-template <typename R>
-__global__ void __launch_bounds__(kBlasBlock) k_dir_update(const MsState *st, const T2<R> *r, T2<R> *pd, int64_t n) {
-    if (st->done) return;
-    const R beta = R(st->beta);
-    for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
-        const T2<R> rv = r[j];
-        T2<R> pv = pd[j];
-        pv.x = rv.x + beta * pv.x;
-        pv.y = rv.y + beta * pv.y;
-        pd[j] = pv;
-    }
-}
-
 // Fused forms (see solver.h).  Every block reduces the partials in the order
 // of k_reduce_tail (threads stride kBlasBlock, then block_sum), so alpha and
 // beta equal the tail kernel's bit for bit.
@@ -374,12 +360,6 @@ hipError_t launch_r_update(bool dbl, MsState *st, const void *rin, void *r, cons
                            int grid, hipStream_t s) {
     if (dbl) hipLaunchKernelGGL(k_r_update<double>, dim3(grid), dim3(kBlasBlock), 0, s, st, static_cast<const double2 *>(rin), static_cast<double2 *>(r), static_cast<const double2 *>(ap), n, partial);
     else hipLaunchKernelGGL(k_r_update<float>, dim3(grid), dim3(kBlasBlock), 0, s, st, static_cast<const float2 *>(rin), static_cast<float2 *>(r), static_cast<const float2 *>(ap), n, partial);
-    return hipGetLastError();
-}
-
-hipError_t launch_dir_update(bool dbl, MsState *st, const void *r, void *pd, int64_t n, int grid, hipStream_t s) {
-    if (dbl) hipLaunchKernelGGL(k_dir_update<double>, dim3(grid), dim3(kBlasBlock), 0, s, st, static_cast<const double2 *>(r), static_cast<double2 *>(pd), n);
-    else hipLaunchKernelGGL(k_dir_update<float>, dim3(grid), dim3(kBlasBlock), 0, s, st, static_cast<const float2 *>(r), static_cast<float2 *>(pd), n);
     return hipGetLastError();
 }
 

@@ -84,12 +84,9 @@ hipError_t launch_scalar_init(MsState *st, const double *partial_r, int nparts_r
 // r = rin - alpha A p (rin may equal r), and the partials of ||r||^2.
 hipError_t launch_r_update(bool dbl, MsState *st, const void *rin, void *r, const void *ap, int64_t n, double *partial,
                            int grid, hipStream_t s);
-// Deferred updates: pd = r + beta pd every iteration (the base direction the
-// operator acts on), and at the end of a block the coefficients and the pass
-// over every shift changed in it.  ring: one residual vector per iteration
-// of the block, slot m holding r^{k0+1+m}.
-hipError_t launch_dir_update(bool dbl, MsState *st, const void *r, void *pd, int64_t n, int grid, hipStream_t s);
-// The same two steps with the scalar recursion folded in: every block sums
+// Deferred updates, every iteration: r = rin - alpha A p into the next ring
+// slot and pd = r + beta pd (the base direction the operator acts on), with
+// the scalar recursion folded in: every block sums
 // the partials of the previous reduction itself (the fixed order of the
 // one-workgroup tail, so the scalars are bit for bit those of the separate
 // tail kernel) and block 0 also advances the recursion.
@@ -99,6 +96,9 @@ hipError_t launch_r_update_fused(bool dbl, MsState *st, const double *pq_part, i
                                  const void *ap, int64_t n, double *partial, int grid, hipStream_t s);
 hipError_t launch_dir_update_fused(bool dbl, MsState *st, const double *r_part, int nr, const void *r, void *pd,
                                    int64_t n, int grid, hipStream_t s);
+// At the end of a block of deferred iterations: the coefficients and the
+// pass over every shift changed in it.  ring: one residual vector per
+// iteration of the block, slot m holding r^{k0+1+m}.
 // out == nullptr: x_i += ... for every shift; otherwise (rational
 // application, double precision) out += sum_i wgt_i (x_i increment) and no
 // x_i is kept.
