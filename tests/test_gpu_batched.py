@@ -157,6 +157,29 @@ def test_batched_config4_full_size(orc):
             assert r <= 1e-10, (k, i, r)
 
 
+def test_batched_64_systems(orc):
+    """The largest batch: 64 systems (two lattices, 8 groups of 8 on one of
+    them), each against the oracle's operator; 65 are refused."""
+    import torch
+    import paper_1010_5433_amd as stag
+    log("batched 64 systems")
+    specs = [((4, 4, 4, 4), 61, 0.1, [0.0, 0.3], list(range(300, 348))),
+             ((4, 2, 2, 4), 62, 0.2, [0.01], list(range(400, 416)))]
+    lats, systems, host = _setup(specs)
+    assert len(systems) == 64
+    sols, rc, stats = stag.multishift_cg_batched(systems, prec="f64")
+    torch.cuda.synchronize()
+    assert rc == 0
+    for k in (0, 17, 47, 48, 63):
+        dims, U, mass, shifts, b = host[k]
+        for i, s in enumerate(shifts):
+            r = orc.true_residual(dims, U, mass, s, b, unpack(systems[k]["lat"], sols[k][i]))
+            assert r <= 1e-10, (k, i, r)
+            assert abs(stats[k]["resid_true"][i] - r) <= 1e-3 * r + 1e-16
+    with pytest.raises(stag.StagError):
+        stag.multishift_cg_batched(systems + systems[:1])
+
+
 def test_batched_errors():
     import paper_1010_5433_amd as stag
     log("batched errors")
