@@ -49,7 +49,7 @@ stag_status refine_batched(const BSpec *spec, int nsys, const BOptions &opt, sta
             }
             BOptions ro_opt = opt;
             ro_opt.dbl = false;
-            ro_opt.reliable_every = 8;
+            ro_opt.reliable_every = kDefer;
             ro_opt.force_block = ro_opt.force_rpt = 0;
             STAG_TRY(run_batched(rs.data(), m, ro_opt, ro.data(), s));
             for (int j = 0; j < m; ++j) {

@@ -218,9 +218,9 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
         if (lats[l]->nrow != nrow) return invalid("all lattices of a batch must use the same link format");
 
     // ---- deferred shift updates for multi-shift systems from a zero start
-    // (blocks of kDefer iterations in double precision, 8 in single
-    // precision so that passes fall on the reliable-update checks)
-    const int dlen_all = dbl ? kDefer : 8;
+    // (blocks of kDefer iterations; in single precision the reliable-update
+    // checks fall on the block ends)
+    const int dlen_all = kDefer;
     if (!dbl && opt.reliable_every > 0 && opt.reliable_every % dlen_all != 0)
         return invalid("reliable updates must fall on deferred passes");
     auto dlen_of = [&](int k) {

@@ -19,13 +19,12 @@
 // the base system of the shifted family) and replaces the single precision
 // residual.
 //
-// Double precision multi-shift solves (two or more shifts, zero start) defer
-// the shifted systems' vector updates: the operator acts on the base
-// direction only, so the x_i and p_i of every shift are brought up to date
-// once per block of iterations (16 in double precision; 8 in single
-// precision, where the reliable-update checks need the solutions current
-// every 8 iterations) from the block's base residuals, kept in a ring, and
-// the recorded scalars.
+// Multi-shift solves (two or more shifts, zero start) defer the shifted
+// systems' vector updates: the operator acts on the base direction only, so
+// the x_i and p_i of every shift are brought up to date once per block of 16
+// iterations from the block's base residuals, kept in a ring, and the
+// recorded scalars.  In single precision the reliable-update checks fall on
+// the same block ends, where the solutions are current.
 #include <chrono>
 #include <cstring>
 #include <vector>
@@ -66,7 +65,7 @@ struct ShiftedResult {
 
 static constexpr int kChunk = 8;   // iterations enqueued between flag reads
 static constexpr double kReliableDelta = 0.1;   // reliable update after |r| fell 10x
-static constexpr int kReliableCheck = 8;        // iterations between reliable-update checks
+static constexpr int kReliableCheck = kDefer;   // iterations between reliable-update checks
 
 stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult *res, hipStream_t s) {
     const int n = sp.n;
@@ -88,8 +87,8 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
         return STAG_EINVAL;
     }
     const bool defer = rat || (!sp.x_init && n >= 2);
-    const int dlen = dbl ? kDefer : 8;   // iterations per deferred block
-    static_assert(kDefer >= 8 && kReliableCheck % 8 == 0, "deferred block lengths");
+    const int dlen = kDefer;   // iterations per deferred block
+    static_assert(kChunk % 8 == 0 && kReliableCheck % kDefer == 0, "deferred block lengths");
     if (defer && sp.reliable_every % dlen != 0) {
         set_error("reliable updates must fall on deferred passes");
         return STAG_EINVAL;
