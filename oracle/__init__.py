@@ -48,8 +48,9 @@ def _bind(L):
     L.orc_cg.argtypes = [_c, _i, _c, _d, _d, _c, _c, _d, _i, _c, _c, _c]
     L.orc_multishift_cg.argtypes = [_c, _i, _c, _d, _i, _c, _c, _c, _d, _i,
                                     _c, _c, _c, _c]
+    L.orc_fermion_force.argtypes = [_c, _i, _c, _i, _c, _c, _c]
     for f in (L.orc_dhop_full, L.orc_dslash_eo, L.orc_normal_op, L.orc_tables,
-              L.orc_cg, L.orc_multishift_cg):
+              L.orc_cg, L.orc_multishift_cg, L.orc_fermion_force):
         f.restype = _i
     if hasattr(L, "orc_net_forward"):
         L.orc_net_forward.argtypes = [_c, _i, _c, _c, _c, _c]
@@ -167,6 +168,20 @@ class Oracle:
         info = dict(info, dot=float(np.vdot(b, out).real))
         return out, rc, info
 
+    def fermion_force(self, dims, links, alphas, x, antiperiodic_t=True):
+        """Pseudo-fermion force F_mu(x) = TA(U_mu(x) W_mu(x)) of the action
+        sum_i alpha_i <phi, (M + sigma_i)^-1 phi>, from the solutions
+        x [n, V/2, 3] (Section 2: the molecular dynamics force from the
+        multi-shift solutions).  W collects the outer products of X_i and
+        Y_i = -D_oe X_i at the two ends of each link; for U -> exp(i eps T) U
+        the action changes at the rate i tr(T F).  Returns (4, V, 3, 3)."""
+        links = _cplx(links)
+        x = _cplx(np.asarray(x).reshape(len(alphas), int(np.prod(dims)) // 2, 3))
+        alphas = np.ascontiguousarray(alphas, dtype=np.float64)
+        force = np.empty(links.shape, np.complex128)
+        _check(self.L.orc_fermion_force(_dims(dims), int(antiperiodic_t), _p(links), int(alphas.size),
+                                        _p(alphas), _p(x), _p(force)), "fermion_force")
+        return force
 
     # ---------------------------------------------------------------- learned preconditioner
     NET_NPARAM = 656

@@ -413,3 +413,75 @@ int orc_multishift_cg(const int *dims, int antiperiodic_t, const cplx *U,
     free(r); free(q); free(ps); free(z); free(active);
     return status;
 }
+
+/* Pseudo-fermion force of the RHMC (Section 2: the molecular dynamics needs
+ * the derivative of the fermion action, built from the multi-shift
+ * solutions; Section 4 runs it in single precision).  The paper prints no
+ * formula; this is the derivative written out from the operator above.
+ *
+ * For the action S = sum_i alpha_i <phi, (M + sigma_i)^-1 phi> with
+ * X_i = (M + sigma_i)^-1 phi (even sites) and M = m^2 + D_eo D_eo^dag
+ * (D_oe = -D_eo^dag), a variation dU of the links changes S by
+ *   dS = -sum_i alpha_i 2 Re <X_i, dD_eo Y_i>,   Y_i = D_eo^dag X_i = -D_oe X_i.
+ * Link U_mu(x) enters D_eo forward at an even x, with X_i(x) and
+ * Y_i(x+mu), and backward (as U^dag) at an odd x, with X_i(x+mu) and
+ * Y_i(x).  Collecting dS = Re sum tr(dU_mu(x) W_mu(x)):
+ *   x even: W = sum_i (-2 alpha_i) (1/2) eta s  Y_i(x+mu) X_i(x)^dag
+ *   x odd : W = sum_i (-2 alpha_i) (-1/2) eta s X_i(x+mu) Y_i(x)^dag
+ * with eta s = eta_mu(x) s_mu(x), the sign the link carries.  For a move
+ * U -> exp(i eps T) U with T Hermitian and traceless, dS/deps = i tr(T F)
+ * where F_mu(x) = TA(U_mu(x) W_mu(x)), TA(A) = (A - A^dag)/2 - tr(A - A^dag)/6.
+ *
+ * x: n_shifts even vectors (V/2,3) one after another; force: (4,V,3,3)
+ * in the layout of the links.  Returns 0, or -1 for bad dims. */
+int orc_fermion_force(const int *dims, int antiperiodic_t, const cplx *U, int n_shifts,
+                      const double *alphas, const cplx *x, cplx *force)
+{
+    geo g;
+    if (geo_init(&g, dims, antiperiodic_t) || n_shifts < 0) return -1;
+    const int64_t n = g.Vh * 3;
+    cplx *y = malloc(sizeof(cplx) * (n_shifts > 0 ? n_shifts : 1) * n);
+    if (!y) return -2;
+    for (int i = 0; i < n_shifts; ++i) {
+        orc_dslash_eo(dims, antiperiodic_t, U, 1, x + i * n, y + i * n);
+        for (int64_t k = 0; k < n; ++k) y[i * n + k] = -y[i * n + k];
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t lex = 0; lex < g.V; ++lex) {
+        int c[4];
+        lex_to_coord(&g, lex, c);
+        const int odd = site_parity(c);
+        for (int mu = 0; mu < 4; ++mu) {
+            int up[4];
+            hop(&g, c, mu, +1, up);
+            const int64_t here = lex >> 1, there = coord_to_lex(&g, up) >> 1;
+            const double es = eta(mu, c) * bc_sign(&g, mu, c);
+            cplx W[9] = {0};
+            for (int i = 0; i < n_shifts; ++i) {
+                const cplx *xi = x + i * n, *yi = y + i * n;
+                /* even x: W += k Y(x+mu) X(x)^dag; odd x: W += k X(x+mu) Y(x)^dag */
+                const cplx *left = odd ? xi + there * 3 : yi + there * 3;
+                const cplx *right = odd ? yi + here * 3 : xi + here * 3;
+                const double k = -2.0 * alphas[i] * (odd ? -0.5 : 0.5) * es;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) W[a * 3 + b] += k * left[a] * conj(right[b]);
+            }
+            const cplx *u = link_at(&g, U, mu, lex);
+            cplx A[9];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    cplx s = 0;
+                    for (int e = 0; e < 3; ++e) s += u[a * 3 + e] * W[e * 3 + b];
+                    A[a * 3 + b] = s;
+                }
+            cplx tr = 0;
+            for (int a = 0; a < 3; ++a) tr += A[a * 4] - conj(A[a * 4]);
+            cplx *f = force + ((int64_t)mu * g.V + lex) * 9;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    f[a * 3 + b] = 0.5 * (A[a * 3 + b] - conj(A[b * 3 + a])) - (a == b ? tr / 6.0 : 0);
+        }
+    }
+    free(y);
+    return 0;
+}

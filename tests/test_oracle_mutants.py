@@ -1,7 +1,8 @@
 """The oracle's pins must catch plausible mistakes.
 
 Each case plants one mistake in a copy of the oracle source (on the CPU),
-builds it, and checks that at least one pin of test_oracle_pins fails
+builds it, and checks that at least one pin of test_oracle_pins or
+test_oracle_force fails
 against the broken build.  Only memory-safe mutations are planted."""
 import os
 
@@ -9,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import test_oracle_force as force_pins
 from tests import test_oracle_pins as pins
 
 MUTANTS = {
@@ -31,6 +33,14 @@ MUTANTS = {
     "beta_i_unsquared": ("bi = beta * ratio * ratio", "bi = beta * ratio"),
     "alpha_i_inverted": ("double ai = alpha * ratio,", "double ai = alpha / ratio,"),
     "x_update_uses_r": ("xi[j] += ai * pi[j];", "xi[j] += ai * r[j];"),
+    "force_odd_end_sign": ("(odd ? -0.5 : 0.5)", "(odd ? 0.5 : 0.5)"),
+    "force_outer_swapped": ("W[a * 3 + b] += k * left[a] * conj(right[b]);",
+                            "W[a * 3 + b] += k * right[a] * conj(left[b]);"),
+    "force_no_eta": ("const double es = eta(mu, c) * bc_sign(&g, mu, c);",
+                     "const double es = bc_sign(&g, mu, c);"),
+    "force_w_times_u": ("s += u[a * 3 + e] * W[e * 3 + b];", "s += W[a * 3 + e] * u[e * 3 + b];"),
+    "force_y_unsigned": ("y[i * n + k] = -y[i * n + k];", "y[i * n + k] = y[i * n + k];"),
+    "force_trace_kept": ("(a == b ? tr / 6.0 : 0)", "(a == b ? 0.0 * tr : 0)"),
 }
 
 
@@ -44,6 +54,8 @@ def _pin_cases(o):
     yield lambda: pins.test_multishift_free_field_closed_form(o, (4, 4, 4, 4))
     yield lambda: pins.test_multishift_dense_solve(o, (2, 2, 2, 2), 1)
     yield lambda: pins.test_multishift_iterated_equals_true_residual_early(o)
+    yield lambda: force_pins.test_force_is_the_action_derivative(o, (4, 2, 2, 4), True)
+    yield lambda: force_pins.test_force_is_in_the_algebra_and_linear_in_alpha(o)
 
 
 def _failures(o):
