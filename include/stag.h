@@ -287,6 +287,25 @@ stag_status stag_zolotarev(int power, double lo, double hi, int n, double *alpha
 stag_status stag_rational_power(double power, double lo, double hi, int n, double *alpha0, double *alphas,
                                 double *shifts, double *max_rel_err);
 
+/* Pseudo-fermion force of the RHMC (Section 2: the molecular dynamics force
+ * of the rational action, from the multi-shift solutions).  For
+ * S = sum_i alphas[i] <phi, (M + sigma_i)^-1 phi> with the solutions
+ * x[i] = (M + sigma_i)^-1 phi (n DEVICE pointers in a HOST array, even-site
+ * vectors in the library layout, double precision), writes
+ *   force[mu][lex] = TA(U_mu(x) W_mu(x))
+ * where W_mu(x) = sum_i alphas[i] eta_mu(x) s_mu(x) (D_oe x_i)(x+mu) x_i(x)^dag
+ * for even x and -sum_i alphas[i] eta_mu(x) s_mu(x) x_i(x+mu) (D_oe x_i)(x)^dag
+ * for odd x, and TA(A) = (A - A^dag)/2 - tr(A - A^dag)/6.  Moving one link
+ * U -> exp(i eps T) U (T Hermitian, traceless) changes S at the rate
+ * i tr(T F).  force: DEVICE buffer of 4*V*9 complex doubles in the layout of
+ * stag_links_set's input (mu, lex, row, col), overwritten.  0 <= n <= 64
+ * (n = 0 writes zeros); alphas finite.  Uses the double precision link field
+ * of any format.  Asynchronous on `stream`; x and force must stay valid
+ * until the stream reaches this point.  STAG_EINVAL on a null pointer, n out
+ * of range, a non-finite alpha or links not set. */
+stag_status stag_fermion_force(stag_lattice *lat, int n, const double *alphas, const void *const *x, void *force,
+                               void *stream);
+
 /* ------------------------------------------------------------------ learned preconditioner
  * Not part of the paper: an extension that preconditions the double
  * precision single-shift solve of the Metropolis step (Section 4 keeps that

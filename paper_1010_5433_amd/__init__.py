@@ -166,6 +166,26 @@ class Lattice:
                                            _stream()), "stag_rational_apply")
         return out, rc, st.to_dict(n), dot.value
 
+    def fermion_force(self, alphas, sols, out=None) -> torch.Tensor:
+        """Pseudo-fermion force TA(U W) of sum_i alphas[i] <phi, (M + sigma_i)^-1 phi>
+        from the solutions sols[i] = (M + sigma_i)^-1 phi (double precision
+        library vectors).  Returns a complex128 (4, V, 3, 3) device tensor."""
+        alphas = [float(a) for a in alphas]
+        n = len(alphas)
+        if len(sols) != n:
+            raise ValueError("alphas and sols differ in length")
+        for x in sols:
+            if x.dtype != torch.float64 or tuple(x.shape) != (3, self.Vh, 2):
+                raise ValueError("solutions must be double precision library vectors")
+        if out is None:
+            out = torch.empty((4, self.V, 3, 3), dtype=torch.complex128, device="cuda")
+        elif out.dtype != torch.complex128 or tuple(out.shape) != (4, self.V, 3, 3):
+            raise ValueError("out must be complex128 of shape (4, V, 3, 3)")
+        al = (ctypes.c_double * max(n, 1))(*alphas)
+        xp = (ctypes.c_void_p * max(n, 1))(*[_ptr(x).value for x in sols])
+        _check(_L.stag_fermion_force(self._h, n, al, xp, _ptr(out), _stream()), "stag_fermion_force")
+        return out
+
     def rational_apply_multi(self, mass, alpha0, alphas, shifts, srcs, outs=None, tol=1e-10,
                              max_iter=100000):
         """The rational function applied to several fields in one batched

@@ -96,6 +96,7 @@ SIGNATURES = {
     "stag_net_grad": (_i, [_v, _v, _v, _v, ctypes.POINTER(_d), _i, _v]),
     "stag_net_train_step": (_i, [_v, _v, _v, _v, _i, _d, _i, ctypes.POINTER(_d), _v]),
     "stag_fcg_solve": (_i, [_v, _d, _d, _v, _v, _v, _i, _d, _i, ctypes.POINTER(CgStats), _v]),
+    "stag_fermion_force": (_i, [_v, _i, ctypes.POINTER(_d), ctypes.POINTER(_v), _v, _v]),
     "stag_rational_apply": (_i, [_v, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d), _i, _v, _v, _d, _i,
                                  ctypes.POINTER(_d), ctypes.POINTER(CgStats), _v]),
     "stag_rational_apply_multi": (_i, [_v, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d), _i,

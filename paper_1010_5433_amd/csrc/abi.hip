@@ -41,6 +41,8 @@ stag_status multishift_cg(stag_lattice *lat, double mass, const double *shifts, 
                           hipStream_t s);
 stag_status single_cg(stag_lattice *lat, double mass, double shift, const void *src, void *x, double tol,
                       int max_iter, stag_prec prec, stag_cg_stats *stats, hipStream_t s);
+stag_status fermion_force(stag_lattice *lat, int n, const double *alphas, const void *const *x, void *force,
+                          hipStream_t s);
 stag_status rational_apply(stag_lattice *lat, double mass, double alpha0, const double *alphas, const double *shifts,
                            int n, const void *src, void *out, double tol, int max_iter, double *dot,
                            stag_cg_stats *stats, hipStream_t s);
@@ -316,6 +318,23 @@ stag_status stag_rational_apply_multi(stag_lattice *lat, double mass, double alp
         }
         return rational_apply_multi(lat, mass, alpha0, alphas, shifts, n, srcs, outs, n_rhs, tol, max_iter, dots,
                                     stats, static_cast<hipStream_t>(stream));
+    } catch (...) {
+        set_error("host allocation failed");
+        return STAG_ENOMEM;
+    }
+}
+
+stag_status stag_fermion_force(stag_lattice *lat, int n, const double *alphas, const void *const *x, void *force,
+                               void *stream) {
+    try {
+        STAG_TRY(check_lattice(lat, true));
+        if (n < 0 || n > STAG_MAX_SHIFTS) return invalid("n must be in [0, 64]");
+        if (!force || (n > 0 && (!alphas || !x))) return invalid("null argument");
+        for (int i = 0; i < n; ++i) {
+            if (!x[i]) return invalid("null solution pointer");
+            if (!std::isfinite(alphas[i])) return invalid("alphas must be finite");
+        }
+        return fermion_force(lat, n, alphas, x, force, static_cast<hipStream_t>(stream));
     } catch (...) {
         set_error("host allocation failed");
         return STAG_ENOMEM;

@@ -1,0 +1,151 @@
+// Pseudo-fermion force of the RHMC from the multi-shift solutions (Section 2:
+// the molecular dynamics integrates the force of the rational action, built
+// from the same shifted solves as the heatbath and the Metropolis step).
+//
+// For S = sum_i alpha_i <phi, (M + sigma_i)^-1 phi>, X_i = (M + sigma_i)^-1 phi
+// on even sites and Z_i = D_oe X_i on odd sites (M = m^2 - D_eo D_oe with
+// D_oe = -D_eo^dag), a variation dU of the links changes S by
+// Re sum tr(dU_mu(x) W_mu(x)) with
+//   x even: W = sum_i alpha_i eta s          Z_i(x+mu) X_i(x)^dag
+//   x odd : W = sum_i alpha_i (-eta s)       X_i(x+mu) Z_i(x)^dag
+// (eta s = eta_mu(x) s_mu(x), the sign carried by the link U_mu(x)).  The
+// force is F_mu(x) = TA(U_mu(x) W_mu(x)), the traceless anti-Hermitian part:
+// moving U -> exp(i eps T) U changes S at the rate i tr(T F).
+//
+// One lane per site x of one parity writes the four F_mu(x).  Per link and
+// shift it reads two colour vectors (the one at x, the one at x+mu); the
+// link is read once.  The output goes to the (4, V, 3, 3) complex layout in
+// which links are handed to the library.  Bandwidth-bound (about 70 flops
+// per shift and link against 96 bytes read), so no matrix cores.
+#include "internal.h"
+#include "links.h"
+#include "solver.h"
+
+namespace stag {
+
+constexpr int kForceBlock = 256;
+
+struct ForceArgs {
+    Geom g;
+    int p;                        // parity of the sites whose links this launch covers
+    int n;                        // shifts
+    const void *links;            // packed double precision links
+    const void *x[kMaxShifts];    // even-site solutions
+    const void *z;                // odd-site Z_i = D_oe X_i, one vector after another
+    double alpha[kMaxShifts];
+    double2 *force;               // (4, V, 3, 3) complex
+};
+
+template <int NROW>
+__global__ void __launch_bounds__(kForceBlock) k_force(ForceArgs a) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int i = tile * kForceBlock + threadIdx.x;
+    const int vh = a.g.Vh;
+    if (i >= vh) return;
+    int x[4];
+    site_coords(a.g, a.p, i, x);
+    const int64_t V = 2 * (int64_t)vh;
+    const int64_t lex = 2 * (int64_t)i + (x[0] & 1);
+    const int64_t zstride = 3 * (int64_t)vh;   // double2 entries per odd vector
+    const double2 *zb = static_cast<const double2 *>(a.z);
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+        const int j = site_nbr(a.g, i, x, mu, +1);
+        const double es = a.p ? -double(fwd_sign(a.g, x, mu)) : double(fwd_sign(a.g, x, mu));
+        cplx<double> W[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) W[r][c] = {0.0, 0.0};
+#pragma unroll 1
+        for (int s = 0; s < a.n; ++s) {
+            const void *zs = zb + s * zstride;
+            // even x: Z(x+mu) X(x)^dag; odd x: X(x+mu) Z(x)^dag
+            const vec3<double> l = load_vec<double>(a.p ? a.x[s] : zs, vh, j);
+            const vec3<double> rv = load_vec<double>(a.p ? zs : a.x[s], vh, i);
+            const double k = a.alpha[s] * es;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const cplx<double> kl = {k * l.c[r].re, k * l.c[r].im};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) W[r][c] = W[r][c] + cmul(kl, conj(rv.c[c]));
+            }
+        }
+        const su3<double> u = LinkLayout<double, NROW>::load(a.links, vh, a.p * 4 + mu, i);
+        cplx<double> A[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cplx<double> t = cmul(u.e[r][0], W[0][c]);
+                t = t + cmul(u.e[r][1], W[1][c]);
+                t = t + cmul(u.e[r][2], W[2][c]);
+                A[r][c] = t;
+            }
+        // TA(A) = (A - A^dag)/2 - tr(A - A^dag)/6; tr(A - A^dag) = 2i Im tr A
+        const double tr_im = (A[0][0].im + A[1][1].im + A[2][2].im) / 3.0;
+        double2 *f = a.force + ((int64_t)mu * V + lex) * 9;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double re = 0.5 * (A[r][c].re - A[c][r].re);
+                double im = 0.5 * (A[r][c].im + A[c][r].im);
+                if (r == c) im -= tr_im;
+                f[r * 3 + c] = make_double2(re, im);
+            }
+    }
+}
+
+template <int NROW>
+static hipError_t launch_force_nrow(const ForceArgs &a, hipStream_t s) {
+    const dim3 grid((a.g.Vh + kForceBlock - 1) / kForceBlock), block(kForceBlock);
+    hipLaunchKernelGGL((k_force<NROW>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+static hipError_t launch_force(int nrow, const ForceArgs &a, hipStream_t s) {
+    switch (nrow) {
+        case 3: return launch_force_nrow<3>(a, s);
+        case 2: return launch_force_nrow<2>(a, s);
+        case 1: return launch_force_nrow<1>(a, s);
+        case kHiLo + 2: return launch_force_nrow<kHiLo + 2>(a, s);
+        case kHiLo + 3: return launch_force_nrow<kHiLo + 3>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Z_i = D_oe X_i for every shift into a work buffer, then one force launch
+// per parity.  The caller has validated the arguments.
+stag_status fermion_force(stag_lattice *lat, int n, const double *alphas, const void *const *x, void *force,
+                          hipStream_t s) {
+    void *z = nullptr;
+    const int64_t vb = vec_bytes(lat, true);
+    STAG_TRY(ws_get(lat, WS_FORCE, (size_t)(n > 0 ? n : 1) * vb, &z));
+    for (int i = 0; i < n; ++i) {
+        DslashArgs d{};
+        d.g = lat->g;
+        d.out_parity = 1;
+        d.links = lat->links64;
+        d.in = x[i];
+        d.out = static_cast<char *>(z) + i * vb;
+        STAG_HIP(launch_dslash(true, lat->nrow, DS_PLAIN, d, s));
+    }
+    ForceArgs a{};
+    a.g = lat->g;
+    a.n = n;
+    a.links = lat->links64;
+    a.z = z;
+    a.force = static_cast<double2 *>(force);
+    for (int i = 0; i < n; ++i) {
+        a.x[i] = x[i];
+        a.alpha[i] = alphas[i];
+    }
+    for (int p = 0; p < 2; ++p) {
+        a.p = p;
+        STAG_HIP(launch_force(lat->nrow, a, s));
+    }
+    return STAG_OK;
+}
+
+}  // namespace stag

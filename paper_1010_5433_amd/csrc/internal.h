@@ -87,6 +87,7 @@ enum WsSlot {
     WS_PART,       // reduction partials
     WS_STATE,      // solver scalar state
     WS_BATCH,      // arena of the batched solver
+    WS_FORCE,      // odd-site vectors D_oe X_i of the fermion force
     WS_NSLOTS
 };
 
