@@ -169,6 +169,45 @@ def batched_experiment(args):
     return out
 
 
+def force_bytes_per_site(nrow: int, n: int) -> int:
+    """Minimum HBM traffic of the two force launches per lattice site: the
+    4 links of the site once, the 4 force matrices written once (144 B
+    each), and per shift the two vectors of each parity (X_i on even sites,
+    D_oe X_i on odd sites, 48 B per site each) read once per launch."""
+    rows = nrow - 10 if nrow > 10 else nrow
+    bl = 16 * (4 if rows == 1 else 3 * rows)
+    return 4 * bl + 4 * 144 + 96 * n
+
+
+def force_experiment(lat, sols, nrow, reps=5):
+    """Pseudo-fermion force from the headline solve's solutions (all shifts,
+    unit weights): the whole call (one D_oe per shift, then the force
+    launches of both parities) timed with events on the launch stream."""
+    import torch
+
+    n = len(sols)
+    alphas = [1.0 / n] * n
+    out = torch.empty((4, lat.V, 3, 3), dtype=torch.complex128, device="cuda")
+    lat.fermion_force(alphas, sols, out=out)   # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lat.fermion_force(alphas, sols, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    t_doe = time_dslash(lat, "f64")
+    t_force = max(t - n * t_doe, 1e-9)
+    b_force = force_bytes_per_site(nrow, n) * lat.V
+    b_all = b_force + n * dslash_bytes_per_site(True, nrow) * lat.Vh
+    return dict(shifts=n, call_ms=round(t * 1e3, 3), call_GBs=round(b_all / t / 1e9, 1),
+                d_oe_us=round(t_doe * 1e6, 2), force_kernels_us_est=round(t_force * 1e6, 1),
+                force_kernels_GBs_est=round(b_force / t_force / 1e9, 1),
+                force_algorithmic_bytes=b_force, call_algorithmic_bytes=b_all,
+                finite=bool(torch.isfinite(torch.view_as_real(out)).all()))
+
+
 def rational_experiment(lat, mass, src, tol, n_poles):
     """The RHMC's rational functions on the headline lattice: Zolotarev's
     M^(1/2) (heatbath of two flavours) and M^(-1/2) (their Metropolis
@@ -351,6 +390,7 @@ def main():
     ap.add_argument("--pairs", default="mx", choices=["mx", "solve"])
     ap.add_argument("--test-fields", type=int, default=4, help="held-out fields of --learned-only")
     ap.add_argument("--no-rational", action="store_true")
+    ap.add_argument("--no-force", action="store_true", help="skip the fermion-force measurement")
     ap.add_argument("--rational-poles", type=int, default=24)
     ap.add_argument("--learned-fmt", default=None, choices=["18", "12", "8"],
                     help="link storage of the held-out fields of the learned experiment (default: --fmt)")
@@ -487,6 +527,9 @@ def main():
     lat.set_links(torch.from_numpy(U).cuda(), args.fmt)
     log(f"dslash: {dsl}")
 
+    if args.prec == "f64" and not args.no_force:
+        extra["force"] = force_experiment(lat, sols, nrow)
+        log(f"force: {extra['force']}")
     if not args.no_rational:
         extra["rational"] = rational_experiment(lat, mass, src, tol, args.rational_poles)
     if not args.no_batched:

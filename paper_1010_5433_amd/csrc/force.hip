@@ -12,7 +12,7 @@
 // force is F_mu(x) = TA(U_mu(x) W_mu(x)), the traceless anti-Hermitian part:
 // moving U -> exp(i eps T) U changes S at the rate i tr(T F).
 //
-// One lane per site x of one parity writes the four F_mu(x).  Per link and
+// One lane per eo index writes the four F_mu(x) of both its sites.  Per link and
 // shift it reads two colour vectors (the one at x, the one at x+mu); the
 // link is read once.  The output goes to the (4, V, 3, 3) complex layout in
 // which links are handed to the library.  Bandwidth-bound (about 70 flops
@@ -27,7 +27,6 @@ constexpr int kForceBlock = 256;
 
 struct ForceArgs {
     Geom g;
-    int p;                        // parity of the sites whose links this launch covers
     int n;                        // shifts
     const void *links;            // packed double precision links
     const void *x[kMaxShifts];    // even-site solutions
@@ -42,58 +41,67 @@ __global__ void __launch_bounds__(kForceBlock) k_force(ForceArgs a) {
     const int i = tile * kForceBlock + threadIdx.x;
     const int vh = a.g.Vh;
     if (i >= vh) return;
-    int x[4];
-    site_coords(a.g, a.p, i, x);
+    // eo index i names the two sites lex = 2i and 2i + 1, one of each
+    // parity: the lane writes both, so a wave's force stores of one
+    // direction cover one contiguous range.
+    int xs[2][4];
+    site_coords(a.g, 0, i, xs[0]);
+    site_coords(a.g, 1, i, xs[1]);
     const int64_t V = 2 * (int64_t)vh;
-    const int64_t lex = 2 * (int64_t)i + (x[0] & 1);
     const int64_t zstride = 3 * (int64_t)vh;   // double2 entries per odd vector
     const double2 *zb = static_cast<const double2 *>(a.z);
 #pragma unroll 1
     for (int mu = 0; mu < 4; ++mu) {
-        const int j = site_nbr(a.g, i, x, mu, +1);
-        const double es = a.p ? -double(fwd_sign(a.g, x, mu)) : double(fwd_sign(a.g, x, mu));
-        cplx<double> W[3][3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) W[r][c] = {0.0, 0.0};
 #pragma unroll 1
-        for (int s = 0; s < a.n; ++s) {
-            const void *zs = zb + s * zstride;
-            // even x: Z(x+mu) X(x)^dag; odd x: X(x+mu) Z(x)^dag
-            const vec3<double> l = load_vec<double>(a.p ? a.x[s] : zs, vh, j);
-            const vec3<double> rv = load_vec<double>(a.p ? zs : a.x[s], vh, i);
-            const double k = a.alpha[s] * es;
+        for (int p = 0; p < 2; ++p) {
+            const int *x = xs[p];
+            const int64_t lex = 2 * (int64_t)i + (x[0] & 1);
+            const int j = site_nbr(a.g, i, x, mu, +1);
+            const double es = p ? -double(fwd_sign(a.g, x, mu)) : double(fwd_sign(a.g, x, mu));
+            cplx<double> W[3][3];
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const cplx<double> kl = {k * l.c[r].re, k * l.c[r].im};
+            for (int r = 0; r < 3; ++r)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) W[r][c] = W[r][c] + cmul(kl, conj(rv.c[c]));
+                for (int c = 0; c < 3; ++c) W[r][c] = {0.0, 0.0};
+            // four shifts per step keep 24 vector loads in flight per lane
+#pragma unroll 4
+            for (int s = 0; s < a.n; ++s) {
+                const void *zs = zb + s * zstride;
+                // even x: Z(x+mu) X(x)^dag; odd x: X(x+mu) Z(x)^dag
+                const vec3<double> l = load_vec<double>(p ? a.x[s] : zs, vh, j);
+                const vec3<double> rv = load_vec<double>(p ? zs : a.x[s], vh, i);
+                const double k = a.alpha[s] * es;
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const cplx<double> kl = {k * l.c[r].re, k * l.c[r].im};
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) W[r][c] = W[r][c] + cmul(kl, conj(rv.c[c]));
+                }
             }
+            const su3<double> u = LinkLayout<double, NROW>::load(a.links, vh, p * 4 + mu, i);
+            cplx<double> A[3][3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    cplx<double> t = cmul(u.e[r][0], W[0][c]);
+                    t = t + cmul(u.e[r][1], W[1][c]);
+                    t = t + cmul(u.e[r][2], W[2][c]);
+                    A[r][c] = t;
+                }
+            // TA(A) = (A - A^dag)/2 - tr(A - A^dag)/6; tr(A - A^dag) = 2i Im tr A
+            const double tr_im = (A[0][0].im + A[1][1].im + A[2][2].im) / 3.0;
+            double2 *f = a.force + ((int64_t)mu * V + lex) * 9;
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double re = 0.5 * (A[r][c].re - A[c][r].re);
+                    double im = 0.5 * (A[r][c].im + A[c][r].im);
+                    if (r == c) im -= tr_im;
+                    f[r * 3 + c] = make_double2(re, im);
+                }
         }
-        const su3<double> u = LinkLayout<double, NROW>::load(a.links, vh, a.p * 4 + mu, i);
-        cplx<double> A[3][3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                cplx<double> t = cmul(u.e[r][0], W[0][c]);
-                t = t + cmul(u.e[r][1], W[1][c]);
-                t = t + cmul(u.e[r][2], W[2][c]);
-                A[r][c] = t;
-            }
-        // TA(A) = (A - A^dag)/2 - tr(A - A^dag)/6; tr(A - A^dag) = 2i Im tr A
-        const double tr_im = (A[0][0].im + A[1][1].im + A[2][2].im) / 3.0;
-        double2 *f = a.force + ((int64_t)mu * V + lex) * 9;
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                double re = 0.5 * (A[r][c].re - A[c][r].re);
-                double im = 0.5 * (A[r][c].im + A[c][r].im);
-                if (r == c) im -= tr_im;
-                f[r * 3 + c] = make_double2(re, im);
-            }
     }
 }
 
@@ -115,8 +123,7 @@ static hipError_t launch_force(int nrow, const ForceArgs &a, hipStream_t s) {
     }
 }
 
-// Z_i = D_oe X_i for every shift into a work buffer, then one force launch
-// per parity.  The caller has validated the arguments.
+// Z_i = D_oe X_i for every shift into a work buffer, then the force launch.  The caller has validated the arguments.
 stag_status fermion_force(stag_lattice *lat, int n, const double *alphas, const void *const *x, void *force,
                           hipStream_t s) {
     void *z = nullptr;
@@ -141,10 +148,7 @@ stag_status fermion_force(stag_lattice *lat, int n, const double *alphas, const 
         a.x[i] = x[i];
         a.alpha[i] = alphas[i];
     }
-    for (int p = 0; p < 2; ++p) {
-        a.p = p;
-        STAG_HIP(launch_force(lat->nrow, a, s));
-    }
+    STAG_HIP(launch_force(lat->nrow, a, s));
     return STAG_OK;
 }
 
