@@ -376,6 +376,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--only-dslash", type=int, default=0,
                     help="profiling aid: run N half-Dslash launches of the bench's precision and exit")
+    ap.add_argument("--only-force", type=int, default=0,
+                    help="profiling aid: run N fermion-force calls (16 shifts) and exit")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner experiment")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-solver experiment")
     ap.add_argument("--batched-only", action="store_true", help="run only the batched-solver experiment")
@@ -430,9 +432,16 @@ def main():
     torch.cuda.synchronize()
 
     it_prec = "f64" if args.prec == "f64" else "f32"
-    if args.only_dslash:
-        log(f"profiling aid: {args.only_dslash} half-Dslash launches ({it_prec}, {args.fmt}-real)")
-        time_dslash(lat, it_prec, n_warm=2, n_time=args.only_dslash)
+    if args.only_dslash or args.only_force:
+        if args.only_dslash:
+            log(f"profiling aid: {args.only_dslash} half-Dslash launches ({it_prec}, {args.fmt}-real)")
+            time_dslash(lat, it_prec, n_warm=2, n_time=args.only_dslash)
+        if args.only_force:
+            log(f"profiling aid: {args.only_force} fermion-force calls, 16 random solutions ({args.fmt}-real)")
+            xs = [torch.randn(3, lat.Vh, 2, dtype=torch.float64, device="cuda") for _ in range(16)]
+            out = torch.empty((4, lat.V, 3, 3), dtype=torch.complex128, device="cuda")
+            for _ in range(args.only_force):
+                lat.fermion_force([1.0 / 16] * 16, xs, out=out)
         # calibration of the byte counters: the probe copy reads and writes
         # exactly 2 GiB per launch
         x = torch.zeros(256 << 20, dtype=torch.float64, device="cuda")
