@@ -302,7 +302,8 @@ stag_status stag_rational_power(double power, double lo, double hi, int n, doubl
  * (n = 0 writes zeros); alphas finite.  Uses the double precision link field
  * of any format.  Asynchronous on `stream`; x and force must stay valid
  * until the stream reaches this point.  STAG_EINVAL on a null pointer, n out
- * of range, a non-finite alpha or links not set. */
+ * of range, a non-finite alpha, force equal to a solution pointer, or links
+ * not set. */
 stag_status stag_fermion_force(stag_lattice *lat, int n, const double *alphas, const void *const *x, void *force,
                                void *stream);
 

@@ -332,6 +332,7 @@ stag_status stag_fermion_force(stag_lattice *lat, int n, const double *alphas, c
         if (!force || (n > 0 && (!alphas || !x))) return invalid("null argument");
         for (int i = 0; i < n; ++i) {
             if (!x[i]) return invalid("null solution pointer");
+            if (x[i] == force) return invalid("force aliases a solution");
             if (!std::isfinite(alphas[i])) return invalid("alphas must be finite");
         }
         return fermion_force(lat, n, alphas, x, force, static_cast<hipStream_t>(stream));

@@ -71,6 +71,7 @@ def test_validation_before_device_use(lib):
     assert lib.stag_net_train_step(None, None, None, None, 1, 1e-3, 0, None, None) == -1
     assert lib.stag_fcg_solve(None, 0.1, 0.0, None, None, None, 0, 1e-10, 10, None, None) == -1
     assert lib.stag_rational_apply(None, 0.1, 0.0, None, None, 1, None, None, 1e-10, 10, None, None, None) == -1
+    assert lib.stag_fermion_force(None, 1, None, None, None, None) == -1
     for rc in (0, 1, 2, -1, -2, -3):
         assert lib.stag_status_string(rc)
 

@@ -101,6 +101,10 @@ def test_force_edge_cases():
         lat.fermion_force([float("nan")], X[:1])
     with pytest.raises(ValueError):
         lat.fermion_force([1.0, 2.0], X[:1])
+    big = torch.zeros((4, lat.V, 3, 3), dtype=torch.complex128, device="cuda")
+    alias = big.view(torch.float64).view(-1)[: 3 * lat.Vh * 2].view(3, lat.Vh, 2)
+    with pytest.raises(stag.StagError):
+        lat.fermion_force([1.0], [alias], out=big)
     bare = stag.Lattice(dims)
     with pytest.raises(stag.StagError):
         bare.fermion_force([1.0], X[:1])
