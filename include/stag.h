@@ -144,12 +144,13 @@ stag_status stag_vec_unpack(const stag_lattice *lat, const void *vec, void *cano
 /* Half hopping term.  out_parity = 0: out = D_eo in (odd -> even);
  * out_parity = 1: out = D_oe in (even -> odd).  in and out are library
  * vectors of precision prec (STAG_F64 or STAG_F32, using the matching link
- * copy); they must not overlap.  Asynchronous. */
+ * copy); they must not share any byte (STAG_EINVAL otherwise).  Asynchronous. */
 stag_status stag_dslash_eo(const stag_lattice *lat, int out_parity, const void *in, void *out,
                            stag_prec prec, void *stream);
 
 /* out = (m^2 + shift) in - D_eo D_oe in on even sites; library vectors of
- * precision prec, no overlap.  Uses a work vector inside the handle.
+ * precision prec, sharing no byte (STAG_EINVAL otherwise).  Uses a work
+ * vector inside the handle.
  * mass > 0, shift >= 0.  Asynchronous. */
 stag_status stag_normal_op(stag_lattice *lat, double mass, double shift, const void *in, void *out,
                            stag_prec prec, void *stream);
@@ -171,7 +172,8 @@ stag_status stag_normal_op(stag_lattice *lat, double mass, double shift, const v
  *                       one; checked every 8 iterations), then a mixed CG
  *                       refinement of every shift whose true residual
  *                       exceeds tol.
- * Requires mass > 0, shifts >= 0, tol > 0, 1 <= n_shifts <= 64, links set.
+ * Requires mass > 0, shifts >= 0, tol > 0, 1 <= n_shifts <= 64, links set,
+ * and no byte shared between two solutions or a solution and src.
  * ||src|| = 0 gives zero solutions and 0 iterations.  Returns STAG_ENOCONV
  * after max_iter iterations (stats filled), STAG_EBREAKDOWN on a
  * non-positive curvature.  stats may be NULL. */
@@ -180,7 +182,7 @@ stag_status stag_multishift_cg(stag_lattice *lat, double mass, const double *shi
                                stag_prec prec, stag_cg_stats *stats, void *stream);
 
 /* Single-shift CG for (M + shift) x = src starting from the x passed in
- * (STAG_F64 library vectors; x is read and overwritten).  Stops when the
+ * (STAG_F64 library vectors sharing no byte; x is read and overwritten).  Stops when the
  * FP64 true residual is <= tol ||src||.  prec = STAG_F64, or STAG_MIXED for
  * single precision iterations with double precision reliable updates. */
 stag_status stag_cg(stag_lattice *lat, double mass, double shift, const void *src, void *x,
@@ -188,7 +190,8 @@ stag_status stag_cg(stag_lattice *lat, double mass, double shift, const void *sr
 
 /* One system of a batched solve: (M + shifts[i]) x_i = src on `lat`
  * (links set), i < n_shifts.  src and sols[i] are STAG_F64 library vectors
- * of that lattice; shifts and sols are host arrays. */
+ * of that lattice; shifts and sols are host arrays.  No solution may share a
+ * byte with another solution or with any source of the batch. */
 typedef struct {
     stag_lattice *lat;
     double mass;
@@ -237,8 +240,8 @@ stag_status stag_batch_last_config(int *block, int *rpt);
  * out = alpha0 src + sum_i alpha_i (M + shifts[i])^-1 src by one double
  * precision multi-shift CG from zero (Section 6).  The weighted solutions
  * are summed into out as the solver goes: no per-shift solution vector is
- * stored or returned.  src and out are STAG_F64 library vectors (no
- * overlap); alphas and shifts are HOST arrays of n (1..64) entries.  Shift
+ * stored or returned.  src and out are STAG_F64 library vectors (sharing no
+ * byte); alphas and shifts are HOST arrays of n (1..64) entries.  Shift
  * i stops when |zeta_i| ||r|| <= tol ||src||, so in exact arithmetic
  *   ||out - r(M) src|| <= tol ||src|| sum_i |alpha_i| / (m^2 + shifts[i]).
  * *dot (host, may be NULL) receives Re <src, out> (the action when src is
@@ -256,8 +259,8 @@ stag_status stag_rational_apply(stag_lattice *lat, double mass, double alpha0, c
  * lattice -- several pseudo-fermions (Section 2) -- in one call: each field
  * is a system of the batched solver, so the multi-RHS half-Dslash loads
  * every link once for up to 8 fields.  srcs and outs are HOST arrays of
- * n_rhs device pointers (STAG_F64 library vectors; no output may alias a
- * source or another output); dots (host, n_rhs entries, may be NULL)
+ * n_rhs device pointers (STAG_F64 library vectors; no output may share a
+ * byte with a source or another output: STAG_EINVAL); dots (host, n_rhs entries, may be NULL)
  * receives Re <src_k, out_k>; stats (host, n_rhs entries, may be NULL) as
  * for stag_rational_apply.  Each field stops on its own; the error bound of
  * stag_rational_apply holds for each.  Synchronous. */
@@ -302,8 +305,8 @@ stag_status stag_rational_power(double power, double lo, double hi, int n, doubl
  * (n = 0 writes zeros); alphas finite.  Uses the double precision link field
  * of any format.  Asynchronous on `stream`; x and force must stay valid
  * until the stream reaches this point.  STAG_EINVAL on a null pointer, n out
- * of range, a non-finite alpha, force equal to a solution pointer, or links
- * not set. */
+ * of range, a non-finite alpha, a force buffer sharing a byte with a
+ * solution, or links not set. */
 stag_status stag_fermion_force(stag_lattice *lat, int n, const double *alphas, const void *const *x, void *force,
                                void *stream);
 
@@ -355,7 +358,8 @@ stag_status stag_net_destroy(stag_net *net);
 stag_status stag_net_set_params(stag_net *net, const double *theta);
 stag_status stag_net_get_params(const stag_net *net, double *theta);
 
-/* out = P(r).  Asynchronous on `stream`.  r and out must differ. */
+/* out = P(r).  Asynchronous on `stream`.  r and out must not share a byte
+ * (STAG_EINVAL). */
 stag_status stag_net_apply(stag_net *net, stag_lattice *lat, const void *r, void *out, int mode,
                            void *stream);
 
@@ -374,7 +378,8 @@ stag_status stag_net_train_step(stag_net *net, stag_lattice *lat, const void *b,
                                 double lr, int mode, double *loss, void *stream);
 
 /* Flexible CG with P as preconditioner (Polak-Ribiere beta) for
- * (M + shift) x = src from the x passed in (STAG_F64 library vectors; sol
+ * (M + shift) x = src from the x passed in (STAG_F64 library vectors sharing
+ * no byte; sol
  * is read and overwritten).  The network is evaluated in `mode` (0 to 3)
  * on a single precision copy of the residual; everything else is double
  * precision.  net == NULL runs plain double precision CG.  The residual is

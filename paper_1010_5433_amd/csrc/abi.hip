@@ -1,6 +1,7 @@
 // The C ABI (include/stag.h): argument validation, handle and work-buffer
 // management, and dispatch to the kernels and solver drivers.  No C++
 // exception crosses this boundary.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -14,6 +15,24 @@
 #include "solver.h"
 
 namespace stag {
+
+bool outputs_disjoint(const ByteRange *outs, int n_out, const ByteRange *ins, int n_in) {
+    std::vector<ByteRange> o(outs, outs + n_out);
+    std::sort(o.begin(), o.end(), [](const ByteRange &a, const ByteRange &b) {
+        return reinterpret_cast<uintptr_t>(a.p) < reinterpret_cast<uintptr_t>(b.p);
+    });
+    for (size_t k = 1; k < o.size(); ++k)
+        if (ranges_overlap(o[k - 1], o[k])) return false;
+    for (int j = 0; j < n_in; ++j) {
+        // the only outputs that can overlap ins[j] start before its end: check the last of them
+        const uintptr_t end = reinterpret_cast<uintptr_t>(ins[j].p) + ins[j].n;
+        auto it = std::lower_bound(o.begin(), o.end(), end, [](const ByteRange &a, uintptr_t e) {
+            return reinterpret_cast<uintptr_t>(a.p) < e;
+        });
+        if (it != o.begin() && ranges_overlap(*(it - 1), ins[j])) return false;
+    }
+    return true;
+}
 
 static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
@@ -184,6 +203,8 @@ stag_status stag_vec_pack(const stag_lattice *lat, const void *canonical, void *
     STAG_TRY(check_lattice(lat, false));
     if (!canonical || !vec) return invalid("null vector");
     if (!prec_ok(prec)) return invalid("vector precision must be STAG_F64 or STAG_F32");
+    if (ranges_overlap({canonical, (size_t)vec_bytes(lat, true)}, {vec, (size_t)vec_bytes(lat, prec == STAG_F64)}))
+        return invalid("canonical and library vectors must not overlap");
     STAG_HIP(launch_pack_vec(lat->g, canonical, vec, prec == STAG_F64, static_cast<hipStream_t>(stream)));
     return STAG_OK;
 }
@@ -192,6 +213,8 @@ stag_status stag_vec_unpack(const stag_lattice *lat, const void *vec, void *cano
     STAG_TRY(check_lattice(lat, false));
     if (!canonical || !vec) return invalid("null vector");
     if (!prec_ok(prec)) return invalid("vector precision must be STAG_F64 or STAG_F32");
+    if (ranges_overlap({canonical, (size_t)vec_bytes(lat, true)}, {vec, (size_t)vec_bytes(lat, prec == STAG_F64)}))
+        return invalid("canonical and library vectors must not overlap");
     STAG_HIP(launch_unpack_vec(lat->g, vec, canonical, prec == STAG_F64, static_cast<hipStream_t>(stream)));
     return STAG_OK;
 }
@@ -200,10 +223,11 @@ stag_status stag_dslash_eo(const stag_lattice *lat, int out_parity, const void *
                            void *stream) {
     STAG_TRY(check_lattice(lat, true));
     if (!in || !out) return invalid("null vector");
-    if (in == out) return invalid("in and out must not overlap");
     if (out_parity != 0 && out_parity != 1) return invalid("out_parity must be 0 or 1");
     if (!prec_ok(prec)) return invalid("precision must be STAG_F64 or STAG_F32");
     const bool dbl = prec == STAG_F64;
+    if (ranges_overlap({in, (size_t)vec_bytes(lat, dbl)}, {out, (size_t)vec_bytes(lat, dbl)}))
+        return invalid("in and out must not overlap");
     DslashArgs a;
     std::memset(&a, 0, sizeof(a));
     a.g = lat->g;
@@ -219,11 +243,12 @@ stag_status stag_normal_op(stag_lattice *lat, double mass, double shift, const v
                            void *stream) {
     STAG_TRY(check_lattice(lat, true));
     if (!in || !out) return invalid("null vector");
-    if (in == out) return invalid("in and out must not overlap");
     if (!(mass > 0) || !std::isfinite(mass)) return invalid("mass must be > 0");
     if (!(shift >= 0) || !std::isfinite(shift)) return invalid("shift must be >= 0");
     if (!prec_ok(prec)) return invalid("precision must be STAG_F64 or STAG_F32");
     const bool dbl = prec == STAG_F64;
+    if (ranges_overlap({in, (size_t)vec_bytes(lat, dbl)}, {out, (size_t)vec_bytes(lat, dbl)}))
+        return invalid("in and out must not overlap");
     void *t = nullptr;
     STAG_TRY(ws_get(lat, WS_E, (size_t)vec_bytes(lat, dbl), &t));
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -260,11 +285,16 @@ stag_status stag_multishift_cg(stag_lattice *lat, double mass, const double *shi
         STAG_TRY(check_solver_args(mass, tol, max_iter, prec));
         if (!shifts || !src || !sols) return invalid("null argument");
         if (n_shifts < 1 || n_shifts > STAG_MAX_SHIFTS) return invalid("n_shifts must be in [1, 64]");
+        const size_t vb = (size_t)vec_bytes(lat, true);
+        std::vector<ByteRange> outs(n_shifts);
         for (int i = 0; i < n_shifts; ++i) {
             if (!(shifts[i] >= 0) || !std::isfinite(shifts[i])) return invalid("shifts must be >= 0 and finite");
             if (!sols[i]) return invalid("null solution pointer");
-            if (sols[i] == src) return invalid("a solution aliases the source");
+            outs[i] = {sols[i], vb};
         }
+        const ByteRange in{src, vb};
+        if (!outputs_disjoint(outs.data(), n_shifts, &in, 1))
+            return invalid("the solutions must not overlap each other or the source");
         return multishift_cg(lat, mass, shifts, n_shifts, src, sols, tol, max_iter, prec, stats,
                              static_cast<hipStream_t>(stream));
     } catch (...) {
@@ -280,7 +310,8 @@ stag_status stag_rational_apply(stag_lattice *lat, double mass, double alpha0, c
         STAG_TRY(check_lattice(lat, true));
         STAG_TRY(check_solver_args(mass, tol, max_iter, STAG_F64));
         if (!alphas || !shifts || !src || !out) return invalid("null argument");
-        if (out == src) return invalid("out aliases the source");
+        if (ranges_overlap({out, (size_t)vec_bytes(lat, true)}, {src, (size_t)vec_bytes(lat, true)}))
+            return invalid("out overlaps the source");
         if (n < 1 || n > STAG_MAX_SHIFTS) return invalid("n must be in [1, 64]");
         if (!std::isfinite(alpha0)) return invalid("alpha0 must be finite");
         for (int i = 0; i < n; ++i) {
@@ -310,12 +341,15 @@ stag_status stag_rational_apply_multi(stag_lattice *lat, double mass, double alp
             if (!(shifts[i] >= 0) || !std::isfinite(shifts[i])) return invalid("shifts must be >= 0 and finite");
             if (!std::isfinite(alphas[i])) return invalid("alphas must be finite");
         }
+        const size_t vb = (size_t)vec_bytes(lat, true);
+        std::vector<ByteRange> ro(n_rhs), ri(n_rhs);
         for (int k = 0; k < n_rhs; ++k) {
             if (!srcs[k] || !outs[k]) return invalid("null field pointer");
-            for (int j = 0; j < n_rhs; ++j)
-                if (outs[k] == srcs[j] || (j != k && outs[k] == outs[j]))
-                    return invalid("an output aliases a source or another output");
+            ro[k] = {outs[k], vb};
+            ri[k] = {srcs[k], vb};
         }
+        if (!outputs_disjoint(ro.data(), n_rhs, ri.data(), n_rhs))
+            return invalid("an output overlaps a source or another output");
         return rational_apply_multi(lat, mass, alpha0, alphas, shifts, n, srcs, outs, n_rhs, tol, max_iter, dots,
                                     stats, static_cast<hipStream_t>(stream));
     } catch (...) {
@@ -330,11 +364,14 @@ stag_status stag_fermion_force(stag_lattice *lat, int n, const double *alphas, c
         STAG_TRY(check_lattice(lat, true));
         if (n < 0 || n > STAG_MAX_SHIFTS) return invalid("n must be in [0, 64]");
         if (!force || (n > 0 && (!alphas || !x))) return invalid("null argument");
+        const ByteRange fr{force, (size_t)(4 * 9 * 16) * (size_t)lat->V};
+        std::vector<ByteRange> xr(n > 0 ? n : 1);
         for (int i = 0; i < n; ++i) {
             if (!x[i]) return invalid("null solution pointer");
-            if (x[i] == force) return invalid("force aliases a solution");
             if (!std::isfinite(alphas[i])) return invalid("alphas must be finite");
+            xr[i] = {x[i], (size_t)vec_bytes(lat, true)};
         }
+        if (!outputs_disjoint(&fr, 1, xr.data(), n)) return invalid("force overlaps a solution");
         return fermion_force(lat, n, alphas, x, force, static_cast<hipStream_t>(stream));
     } catch (...) {
         set_error("host allocation failed");
@@ -379,7 +416,8 @@ stag_status stag_cg(stag_lattice *lat, double mass, double shift, const void *sr
         if (prec == STAG_F32) return invalid("stag_cg takes STAG_F64 or STAG_MIXED");
         if (!(shift >= 0) || !std::isfinite(shift)) return invalid("shift must be >= 0");
         if (!src || !x) return invalid("null vector");
-        if (src == x) return invalid("x aliases the source");
+        if (ranges_overlap({src, (size_t)vec_bytes(lat, true)}, {x, (size_t)vec_bytes(lat, true)}))
+            return invalid("x overlaps the source");
         return single_cg(lat, mass, shift, src, x, tol, max_iter, prec, stats, static_cast<hipStream_t>(stream));
     } catch (...) {
         set_error("host allocation failed");
@@ -396,6 +434,7 @@ stag_status stag_multishift_cg_batched(const stag_system *systems, int n_systems
         if (max_iter < 1) return invalid("max_iter must be >= 1");
         if (prec != STAG_F64 && prec != STAG_F32 && prec != STAG_MIXED) return invalid("unknown precision");
         std::vector<BSpec> spec(n_systems);
+        std::vector<ByteRange> b_outs, b_ins;
         int device = -1;
         for (int k = 0; k < n_systems; ++k) {
             const stag_system &y = systems[k];
@@ -406,12 +445,17 @@ stag_status stag_multishift_cg_batched(const stag_system *systems, int n_systems
             if (!(y.mass > 0) || !std::isfinite(y.mass)) return invalid("mass must be > 0");
             if (y.n_shifts < 1 || y.n_shifts > STAG_MAX_SHIFTS) return invalid("n_shifts must be in [1, 64]");
             if (!y.shifts || !y.src || !y.sols) return invalid("null argument in a system");
+            const size_t vb = (size_t)vec_bytes(y.lat, true);
             for (int i = 0; i < y.n_shifts; ++i) {
                 if (!(y.shifts[i] >= 0) || !std::isfinite(y.shifts[i])) return invalid("shifts must be >= 0 and finite");
-                if (!y.sols[i] || y.sols[i] == y.src) return invalid("bad solution pointer");
+                if (!y.sols[i]) return invalid("null solution pointer");
+                b_outs.push_back({y.sols[i], vb});
             }
+            b_ins.push_back({y.src, vb});
             spec[k] = {y.lat, y.mass, y.n_shifts, y.shifts, y.src, y.sols, false};
         }
+        if (!outputs_disjoint(b_outs.data(), (int)b_outs.size(), b_ins.data(), (int)b_ins.size()))
+            return invalid("the solutions of a batch must not overlap each other or any source");
         BOptions opt;
         opt.tol = tol;
         opt.max_iter = max_iter;

@@ -35,6 +35,19 @@ inline stag_status invalid(const std::string &msg) {
     return STAG_EINVAL;
 }
 
+// A device buffer the caller passes: its first byte and its length.
+struct ByteRange {
+    const void *p;
+    size_t n;
+};
+inline bool ranges_overlap(const ByteRange &a, const ByteRange &b) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a.p), y = reinterpret_cast<uintptr_t>(b.p);
+    return a.n && b.n && x < y + b.n && y < x + a.n;
+}
+// True when the outputs are pairwise disjoint and none overlaps an input
+// (inputs may overlap each other: they are only read).  O(n log n).
+bool outputs_disjoint(const ByteRange *outs, int n_out, const ByteRange *ins, int n_in);
+
 // ---------------------------------------------------------------- kernels
 enum DslashMode {
     DS_PLAIN = 0,       // out = D in

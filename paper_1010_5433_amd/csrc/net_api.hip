@@ -176,7 +176,9 @@ static stag_status check_net_lat(const stag_net *net, const stag_lattice *lat, i
 
 stag_status stag_net_apply(stag_net *net, stag_lattice *lat, const void *r, void *out, int mode, void *stream) {
     STAG_TRY(check_net_lat(net, lat, mode));
-    if (!r || !out || r == out) return invalid("bad vector");
+    if (!r || !out) return invalid("bad vector");
+    if (ranges_overlap({r, (size_t)vec_bytes(lat, false)}, {out, (size_t)vec_bytes(lat, false)}))
+        return invalid("r and out must not overlap");
     hipStream_t s = static_cast<hipStream_t>(stream);
     NetBufs b;
     STAG_TRY(net_work(net, lat, 1, &b));
@@ -236,7 +238,9 @@ stag_status stag_net_train_step(stag_net *net, stag_lattice *lat, const void *b,
 stag_status stag_fcg_solve(stag_lattice *lat, double mass, double shift, const void *src, void *sol, stag_net *net,
                            int mode, double tol, int max_iter, stag_cg_stats *stats, void *stream) {
     if (!lat || !lat->nrow) return invalid("lattice with links required");
-    if (!src || !sol || src == sol) return invalid("bad vector");
+    if (!src || !sol) return invalid("bad vector");
+    if (ranges_overlap({src, (size_t)vec_bytes(lat, true)}, {sol, (size_t)vec_bytes(lat, true)}))
+        return invalid("sol overlaps the source");
     if (!(mass > 0) || !(shift >= 0) || !(tol > 0) || max_iter < 1) return invalid("bad solver parameter");
     if (net && !net_mode_ok(mode)) return invalid(kModeError);
     return fcg_solve(lat, mass, shift, src, sol, net, mode, tol, max_iter, stats, static_cast<hipStream_t>(stream));

@@ -45,6 +45,24 @@ def test_force_vs_oracle(orc, dims, fmt):
         assert _max_rel(F.cpu().numpy(), ref) <= 1e-12, (n, _max_rel(F.cpu().numpy(), ref))
 
 
+def test_force_full_size(orc):
+    """The force at the benchmark's shape: 32^4, 8-real links, 16 shifts,
+    element by element against the oracle."""
+    import torch
+    dims = (32, 32, 32, 32)
+    log("force 32^4, 16 shifts, 8-real links")
+    U = links_np(dims, "smooth", 0.5, 301)
+    lat = lattice_with_links(dims, U, "8")
+    X = _random_solutions(dims, 16, 7)
+    alphas = list(np.random.default_rng(8).uniform(0.1, 2, 16))
+    F = lat.fermion_force(alphas, [pack(lat, x) for x in X])
+    torch.cuda.synchronize()
+    ref = orc.fermion_force(dims, U, alphas, X)
+    e = _max_rel(F.cpu().numpy(), ref)
+    log(f"  largest entry error {e:.2e}")
+    assert e <= 1e-12
+
+
 @pytest.mark.parametrize("antiperiodic", [True, False])
 def test_force_boundary_and_64_shifts(orc, antiperiodic):
     import torch
@@ -105,6 +123,10 @@ def test_force_edge_cases():
     alias = big.view(torch.float64).view(-1)[: 3 * lat.Vh * 2].view(3, lat.Vh, 2)
     with pytest.raises(stag.StagError):
         lat.fermion_force([1.0], [alias], out=big)
+    # a solution lying inside the force buffer at an offset
+    inner = big.view(torch.float64).view(-1)[40: 40 + 3 * lat.Vh * 2].view(3, lat.Vh, 2)
+    with pytest.raises(stag.StagError):
+        lat.fermion_force([1.0], [inner], out=big)
     bare = stag.Lattice(dims)
     with pytest.raises(stag.StagError):
         bare.fermion_force([1.0], X[:1])

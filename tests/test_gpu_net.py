@@ -24,6 +24,7 @@ import pytest
 
 import stag_synth as syn
 from tests import lattice_np as ln
+from tests.entrywise import max_entry_err
 from tests.gpu_common import lattice_with_links, links_np, log, pack, rel, to_dev, unpack
 
 pytestmark = pytest.mark.gpu
@@ -76,6 +77,7 @@ def test_net_forward_fp32_vs_oracle(orc, dims, kind, fmt):
     got = unpack(lat, net.apply(lat, pack(lat, r, "f32"), mode="fp32"))
     want = orc.net_forward(dims, U, th, r)
     assert rel(got, want) <= 1e-5
+    assert max_entry_err(got, want) <= 1e-5
 
 
 @pytest.mark.parametrize("dims,kind,fmt", CASES)
@@ -89,7 +91,9 @@ def test_net_forward_folded_vs_oracle(orc, dims, kind, fmt):
     r = syn.gaussian_source(dims, 14)
     net = stag.Net(th)
     got = unpack(lat, net.apply(lat, pack(lat, r, "f32"), mode="folded"))
-    assert rel(got, orc.net_forward(dims, U, th, r)) <= 1e-5
+    want = orc.net_forward(dims, U, th, r)
+    assert rel(got, want) <= 1e-5
+    assert max_entry_err(got, want) <= 1e-5
 
 
 @pytest.mark.parametrize("dims,kind,fmt", CASES + [((4, 4, 2, 6), "smooth", "8")])
@@ -148,6 +152,35 @@ def test_net_forward_bf16_matrix_cores(orc, dims, kind, fmt):
     # the error is spread over sites, not concentrated in a tile
     per_site = np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1).mean()
     assert per_site.max() <= 5e-2
+
+
+_FULL_REF = {}
+
+
+@pytest.mark.parametrize("fmt", ["18", "12", "8"])
+def test_net_forward_full_size_every_format(orc, fmt):
+    """Every evaluation mode at 32^4 (the held-out lattice size) on every
+    link format, entry by entry against the oracle's layered network: FP32
+    and folded forms to 1e-5 of the largest output entry, the bfloat16 forms
+    to 2e-2 (inputs or links rounded to 8-bit significands, 2^-9, summed over
+    ~10^2 terms per entry)."""
+    import paper_1010_5433_amd as stag
+    dims = (32, 32, 32, 32)
+    log(f"net forward 32^4 fmt={fmt}")
+    U = links_np(dims, "smooth", 0.5, 550)
+    th = rand_theta(19)
+    r = syn.gaussian_source(dims, 20)
+    if "want" not in _FULL_REF:
+        _FULL_REF["want"] = orc.net_forward(dims, U, th, r)
+    want = _FULL_REF["want"]
+    lat = lattice_with_links(dims, U, fmt)
+    net = stag.Net(th)
+    r32 = pack(lat, r, "f32")
+    for mode, bound in (("fp32", 1e-5), ("folded", 1e-5), ("bf16", 2e-2), ("folded_bf16", 2e-2)):
+        got = unpack(lat, net.apply(lat, r32, mode=mode))
+        e = max_entry_err(got, want)
+        log(f"  {mode}: largest entry error {e:.2e} (norm {rel(got, want):.2e})")
+        assert e <= bound, (mode, e)
 
 
 @pytest.mark.parametrize("dims,kind,fmt", CASES)

@@ -3,14 +3,16 @@
 Tolerances (derived from the arithmetic; the problem fixes 1e-10 for the
 solver):
   * tables: bit-exact.
-  * FP64 half Dslash: each output is a sum of 8 products of unit-norm
-    links with the input; with a different summation order and FMA
-    contraction the rounding differs by a few ulp of the inputs, so
-    ||gpu - orc|| / ||orc|| <= 1e-14.
-  * FP32 half Dslash vs the FP64 oracle: inputs and links rounded to single
-    (2^-24 relative each) plus ~8 rounded terms: <= 3e-7 norm-relative.
-  * 8-real links: the rebuild (phases, two square roots, one reciprocal) adds
-    a few ulp per entry; the same bounds hold.
+  * operators, entry by entry: |gpu - orc| of every output entry within the
+    forward error bound of tests/entrywise.py -- 128 unit roundoffs of the
+    entry's magnitude sum (the same hop with |U| and |v|) plus the stored
+    format's per-link reconstruction error carried through the same hop.
+    A wrong slice of the lattice fails it even where a norm ratio would not.
+  * and in norm: FP64 half Dslash ||gpu - orc|| / ||orc|| <= 1e-14 (each
+    output is a sum of 8 products of unit-norm links with the input; a
+    different summation order and FMA contraction differ by a few ulp);
+    FP32 against the FP64 oracle <= 3e-7 (inputs and links rounded to single,
+    2^-24 relative each, plus ~8 rounded terms).
   * solvers: the FP64 true relative residual of every shift, computed by the
     ORACLE's operator on the GPU's solution, <= 1e-10 (the requested tol);
     solutions agree with the oracle's within kappa_i * 2e-10.
@@ -19,6 +21,7 @@ import numpy as np
 import pytest
 
 import stag_synth as syn
+from tests import entrywise as ew
 from tests import lattice_np as ln
 from tests.gpu_common import lattice_with_links, links_np, log, pack, rel, to_dev, unpack
 
@@ -62,6 +65,7 @@ def test_dslash_f64(orc, dims, fmt):
         got = unpack(lat, lat.dslash_eo(out_parity, pack(lat, v)))
         want = orc.dslash_eo(dims, U, out_parity, v)
         assert rel(got, want) <= 1e-14, (out_parity, rel(got, want))
+        ew.check_entrywise(got, want, ew.dslash_bound(dims, U, fmt, "f64", out_parity, v), f"f64 {fmt} p{out_parity}")
 
 
 @pytest.mark.parametrize("dims", SMALL + FULL)
@@ -77,6 +81,7 @@ def test_dslash_f32(orc, dims, fmt):
         got = unpack(lat, lat.dslash_eo(out_parity, pack(lat, v, "f32")))
         want = orc.dslash_eo(dims, U, out_parity, v)
         assert rel(got, want) <= 3e-7, (out_parity, rel(got, want))
+        ew.check_entrywise(got, want, ew.dslash_bound(dims, U, fmt, "f32", out_parity, v), f"f32 {fmt} p{out_parity}")
 
 
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 8), (32, 32, 32, 32)])
@@ -98,16 +103,22 @@ def test_free_field_plane_wave_on_gpu(dims):
         assert rel(got, lam * psi) <= 1e-14
 
 
-@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 8), (32, 32, 32, 8)])
-@pytest.mark.parametrize("fmt", ["18", "12", "8"])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 8), (32, 32, 32, 8), (32, 32, 32, 32)])
+@pytest.mark.parametrize("fmt", ["18", "12", "8", "18p", "12p"])
 def test_normal_op(orc, dims, fmt):
+    """(m^2 + s) v - D_eo D_oe v entry by entry, both precisions."""
     log(f"normal op {dims} fmt={fmt}")
     U = links_np(dims, "smooth", 0.5, 3)
     lat = lattice_with_links(dims, U, fmt)
     v = syn.gaussian_source(dims, 4)
-    got = unpack(lat, lat.normal_op(0.02, 0.3, pack(lat, v)))
     want = orc.normal_op(dims, U, 0.02, 0.3, v)
+    c = 0.02 ** 2 + 0.3
+    got = unpack(lat, lat.normal_op(0.02, 0.3, pack(lat, v)))
     assert rel(got, want) <= 1e-14
+    ew.check_entrywise(got, want, ew.normal_op_bound(dims, U, fmt, "f64", c, v), f"normal f64 {fmt}")
+    got32 = unpack(lat, lat.normal_op(0.02, 0.3, pack(lat, v, "f32")))
+    assert rel(got32, want) <= 1e-6      # two single precision half-Dslashes in sequence
+    ew.check_entrywise(got32, want, ew.normal_op_bound(dims, U, fmt, "f32", c, v), f"normal f32 {fmt}")
 
 
 def test_vec_pack_roundtrip():
@@ -174,9 +185,39 @@ def test_multishift_small_vs_oracle_and_dense(orc, dims, seed):
         assert rel(xs[i].ravel(), xd) <= 2 * (ev[-1] / ev[0]) * 1e-10
 
 
+def _lanczos_extremes(apply, b, steps=80):
+    """Extreme Ritz values of the Hermitian operator `apply` after `steps`
+    Lanczos steps from b (plain three-term recurrence; the extreme values
+    converge first and are not disturbed by the loss of orthogonality)."""
+    q_prev = np.zeros_like(b)
+    q = b / np.linalg.norm(b)
+    alphas, betas = [], []
+    beta = 0.0
+    for _ in range(steps):
+        w = apply(q) - beta * q_prev
+        a = float(np.vdot(q, w).real)
+        w = w - a * q
+        alphas.append(a)
+        beta = float(np.linalg.norm(w))
+        if beta == 0.0:
+            break
+        betas.append(beta)
+        q_prev, q = q, w / beta
+    T = np.diag(alphas) + np.diag(betas[:len(alphas) - 1], 1) + np.diag(betas[:len(alphas) - 1], -1)
+    ev = np.linalg.eigvalsh(T)
+    return ev[0], ev[-1]
+
+
 def test_multishift_config2_full_size(orc):
     """32^3x8 smoothed links, m = 0.02, 12 shifts in [1e-5, 2]: every shift's
-    FP64 true residual, computed by the oracle's operator, <= 1e-10."""
+    FP64 true residual, computed by the oracle's operator, <= 1e-10, and
+    every shift's solution against the oracle's own multi-shift solution,
+    entry by entry and in norm, within kappa_i (r_gpu + r_orc) <= kappa_i 2 tol:
+    ||x - x*|| <= ||A_i^-1|| r ||b|| for either solution, so
+    ||x_gpu - x_orc|| <= (r_gpu + r_orc) ||b|| / lambda_min, and relative to
+    ||x_orc|| >= ||b|| / lambda_max that is kappa_i (r_gpu + r_orc), with
+    kappa_i the condition number of M + sigma_i from Lanczos extreme Ritz
+    values."""
     c = syn.config("c2_32x32x32x8_smooth")
     log("multishift config 2 (32^3x8)")
     U = syn.make_links(c["links"], c["dims"])
@@ -186,10 +227,26 @@ def test_multishift_config2_full_size(orc):
     xs, rc, st = _solve(lat, c["mass"], shifts, b)
     log(f"  iters {st['iters']} seconds {st['seconds']:.3f}")
     assert rc == 0
+    xo, rco, io = orc.multishift_cg(c["dims"], U, c["mass"], shifts, b, tol=c["tol"])
+    assert rco == 0 and abs(io["iters"] - st["iters"]) <= 1
+    lo, hi = _lanczos_extremes(lambda v: orc.normal_op(c["dims"], U, c["mass"], 0.0, v), b)
+    log(f"  Lanczos spectrum estimate [{lo:.4g}, {hi:.4g}]")
+    assert c["mass"] ** 2 <= lo and hi <= c["mass"] ** 2 + 16.0
     for i, s in enumerate(shifts):
         r = orc.true_residual(c["dims"], U, c["mass"], s, b, xs[i])
         assert r <= 1e-10, (i, s, r)
         assert abs(st["resid_true"][i] - r) <= 1e-3 * r + 1e-16
+        kappa = (hi + s) / (lo + s)
+        r_orc = io["resid_true"][i]
+        assert r_orc <= 1.1e-10
+        bound = kappa * (r + r_orc)
+        e_norm = rel(xs[i], xo[i])
+        e_max = float(np.abs(xs[i] - xo[i]).max() / np.abs(xo[i]).max())
+        log(f"  shift {s:.3g}: resid {r:.2e}, |x - x_orc|/|x_orc| {e_norm:.2e}, largest entry {e_max:.2e}, "
+            f"bound {bound:.2e}")
+        assert e_norm <= bound, (i, e_norm, bound)
+        # entry by entry: |x_gpu - x_orc|_k <= ||x_gpu - x_orc||_2 <= bound ||x_orc||
+        assert np.abs(xs[i] - xo[i]).max() <= bound * np.linalg.norm(xo[i])
     # iterations are monotone in the shift: larger shifts freeze earlier
     its = np.array(st["iters_shift"])
     assert np.all(np.diff(its) <= 0)
@@ -209,9 +266,10 @@ def test_multishift_config3_full_size(orc, prec):
         f"seconds {st['seconds']:.3f}")
     log(f"  unrefined {np.array(st['resid_unrefined'])}")
     assert rc == 0
-    for i in (0, 5, 10, 15):
+    for i in range(len(shifts)):
         r = orc.true_residual(c["dims"], U, c["mass"], shifts[i], b, xs[i])
         assert r <= 1e-10, (i, r)
+        assert abs(st["resid_true"][i] - r) <= 1e-3 * r + 1e-16
     assert max(st["resid_true"]) <= 1e-10
 
 
@@ -308,7 +366,8 @@ def test_multishift_config3_float_pair_links(orc, prec):
     xs, rc, st = _solve(lat, c["mass"], shifts, b, prec=prec)
     log(f"  iters {st['iters']} refine {st['refine_iters']} seconds {st['seconds']:.3f}")
     assert rc == 0
-    for i in (0, 7, 15):
+    assert max(st["resid_true"]) <= 1e-10
+    for i in range(len(shifts)):
         r = orc.true_residual(c["dims"], U, c["mass"], shifts[i], b, xs[i])
         assert r <= 1e-10, (i, r)
 
@@ -326,7 +385,8 @@ def test_multishift_config3_8real_links(orc, prec):
     xs, rc, st = _solve(lat, c["mass"], shifts, b, prec=prec)
     log(f"  iters {st['iters']} refine {st['refine_iters']} seconds {st['seconds']:.3f}")
     assert rc == 0
-    for i in (0, 7, 15):
+    assert max(st["resid_true"]) <= 1e-10
+    for i in range(len(shifts)):
         r = orc.true_residual(c["dims"], U, c["mass"], shifts[i], b, xs[i])
         assert r <= 1e-10, (i, r)
 
@@ -398,6 +458,37 @@ def test_solver_edge_cases():
     bad = pack(lat, np.full((128, 3), np.nan + 0j))
     sols, rc, st = lat.multishift_cg(0.1, [0.0], bad)
     assert rc == stag._abi.STAG_EBREAKDOWN
+
+
+def test_partial_overlaps_rejected():
+    """Buffers that share some bytes without being equal are rejected as
+    well as equal ones: input/output of the operator, two solutions, a
+    solution and the source."""
+    import torch
+    import paper_1010_5433_amd as stag
+    log("partial overlaps")
+    dims = (4, 4, 4, 4)
+    lat = lattice_with_links(dims, syn.haar_links(dims, 1))
+    n = 3 * lat.Vh * 2
+    big = torch.zeros(2 * n + 64, dtype=torch.float64, device="cuda")
+    a = big[:n].view(3, lat.Vh, 2)
+    a_shift = big[16:16 + n].view(3, lat.Vh, 2)        # 128 bytes further on
+    b = big[n + 64:2 * n + 64].view(3, lat.Vh, 2)
+    a.copy_(pack(lat, syn.gaussian_source(dims, 2)))
+    with pytest.raises(stag.StagError):
+        lat.dslash_eo(0, a, a_shift)
+    with pytest.raises(stag.StagError):
+        lat.normal_op(0.1, 0.0, a, a_shift)
+    with pytest.raises(stag.StagError):          # two solutions overlapping
+        lat.multishift_cg(0.1, [0.0, 0.5], b, sols=[a, a_shift])
+    with pytest.raises(stag.StagError):          # a solution overlapping the source
+        lat.multishift_cg(0.1, [0.0], a, sols=[a_shift])
+    with pytest.raises(stag.StagError):
+        lat.cg(0.1, 0.0, a, a_shift)
+    # disjoint neighbours in one allocation are fine
+    d = lat.dslash_eo(0, a, b)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(d).all())
 
 
 def test_side_stream_gives_the_same_results():

@@ -1,8 +1,8 @@
 """The oracle's pins must catch plausible mistakes.
 
 Each case plants one mistake in a copy of the oracle source (on the CPU),
-builds it, and checks that at least one pin of test_oracle_pins or
-test_oracle_force fails
+builds it, and checks that at least one pin of test_oracle_pins,
+test_oracle_force or test_oracle_tables fails
 against the broken build.  Only memory-safe mutations are planted."""
 import os
 
@@ -12,6 +12,7 @@ import pytest
 import oracle
 from tests import test_oracle_force as force_pins
 from tests import test_oracle_pins as pins
+from tests import test_oracle_tables as table_pins
 
 MUTANTS = {
     "eta_all_one": ("return (s & 1) ? -1.0 : 1.0;", "return 1.0;"),
@@ -41,6 +42,13 @@ MUTANTS = {
     "force_w_times_u": ("s += u[a * 3 + e] * W[e * 3 + b];", "s += W[a * 3 + e] * u[e * 3 + b];"),
     "force_y_unsigned": ("y[i * n + k] = -y[i * n + k];", "y[i * n + k] = y[i * n + k];"),
     "force_trace_kept": ("(a == b ? tr / 6.0 : 0)", "(a == b ? 0.0 * tr : 0)"),
+    "tables_bwd_sign_at_x": ("sign[(p * 8 + 4 + mu) * g.Vh + i] = (int32_t)(eta(mu, x) * bc_sign(&g, mu, z));",
+                             "sign[(p * 8 + 4 + mu) * g.Vh + i] = (int32_t)(eta(mu, x) * bc_sign(&g, mu, x));"),
+    "tables_fwd_slot_gets_bwd": ("nbr[(p * 8 + mu) * g.Vh + i] = (int32_t)(coord_to_lex(&g, y) >> 1);",
+                                 "nbr[(p * 8 + mu) * g.Vh + i] = (int32_t)(coord_to_lex(&g, z) >> 1);"),
+    "tables_coord_reversed": ("coord[(p * g.Vh + i) * 4 + mu] = x[mu];",
+                              "coord[(p * g.Vh + i) * 4 + mu] = x[3 - mu];"),
+    "tables_parity_from_x0": ("int p = site_parity(x);", "int p = x[0] & 1;"),
 }
 
 
@@ -56,6 +64,7 @@ def _pin_cases(o):
     yield lambda: pins.test_multishift_iterated_equals_true_residual_early(o)
     yield lambda: force_pins.test_force_is_the_action_derivative(o, (4, 2, 2, 4), True)
     yield lambda: force_pins.test_force_is_in_the_algebra_and_linear_in_alpha(o)
+    yield lambda: table_pins.test_tables_match_numpy_geometry(o, (6, 4, 2, 8), True)
 
 
 def _failures(o):
