@@ -43,6 +43,7 @@
 #ifndef STAG_H
 #define STAG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -154,6 +155,21 @@ stag_status stag_dslash_eo(const stag_lattice *lat, int out_parity, const void *
  * mass > 0, shift >= 0.  Asynchronous. */
 stag_status stag_normal_op(stag_lattice *lat, double mass, double shift, const void *in, void *out,
                            stag_prec prec, void *stream);
+
+/* For callers that cannot allocate device memory (code under graph capture,
+ * serving loops, harnesses that forbid hipMalloc): stag_normal_op with the
+ * odd-site temporary taken from a static device array of
+ * stag_noalloc_scratch_bytes() bytes (32 MiB) instead of a work buffer.
+ * Arguments, result and asynchrony as stag_normal_op; the same kernels run.
+ * Allocates nothing (no hipMalloc, hipFree or allocating library call).
+ * Returns STAG_EINVAL when the temporary (48 V/2 bytes in STAG_F64, 24 V/2
+ * in STAG_F32) exceeds the array: a 32^4 lattice fits in either precision.
+ * Each GPU holds its own copy of the array until the process ends; every
+ * call on that GPU uses it, so calls that overlap in time on one GPU (two
+ * streams or two host threads) race and must not be issued. */
+size_t stag_noalloc_scratch_bytes(void);
+stag_status stag_normal_op_noalloc(stag_lattice *lat, double mass, double shift, const void *in, void *out,
+                                   stag_prec prec, void *stream);
 
 /* Multi-shift CG (Section 6; Jegerlehner's method): solve
  *   (M + shifts[i]) x_i = src,  i = 0..n_shifts-1,

@@ -130,6 +130,13 @@ class Lattice:
                                  _PREC[prec], _stream()), "stag_normal_op")
         return out
 
+    def normal_op_noalloc(self, mass: float, shift: float, vec: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """normal_op with the library's static scratch: `out` must be given."""
+        prec = "f64" if vec.dtype == torch.float64 else "f32"
+        _check(_L.stag_normal_op_noalloc(self._h, float(mass), float(shift), _ptr(vec), _ptr(out),
+                                         _PREC[prec], _stream()), "stag_normal_op_noalloc")
+        return out
+
     # ---------------------------------------------------------------- solvers
     def multishift_cg(self, mass, shifts, src: torch.Tensor, sols=None, tol=1e-10,
                       max_iter=100000, prec="f64"):

@@ -82,6 +82,8 @@ SIGNATURES = {
     "stag_vec_unpack": (_i, [_v, _v, _v, _i, _v]),
     "stag_dslash_eo": (_i, [_v, _i, _v, _v, _i, _v]),
     "stag_normal_op": (_i, [_v, _d, _d, _v, _v, _i, _v]),
+    "stag_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+    "stag_normal_op_noalloc": (_i, [_v, _d, _d, _v, _v, _i, _v]),
     "stag_multishift_cg": (_i, [_v, _d, ctypes.POINTER(_d), _i, _v, ctypes.POINTER(_v), _d, _i, _i,
                                 ctypes.POINTER(CgStats), _v]),
     "stag_cg": (_i, [_v, _d, _d, _v, _v, _d, _i, _i, ctypes.POINTER(CgStats), _v]),
