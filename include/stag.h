@@ -326,6 +326,112 @@ stag_status stag_rational_power(double power, double lo, double hi, int n, doubl
 stag_status stag_fermion_force(stag_lattice *lat, int n, const double *alphas, const void *const *x, void *force,
                                void *stream);
 
+/* ------------------------------------------------------------------ RHMC trajectory
+ * Section 2 of the paper: RHMC for staggered fermions with a multi-step
+ * second order minimum norm integrator that splits the action into its
+ * gauge and fermion parts, several pseudo-fermions and rational
+ * approximations; Section 4: the gauge update in single precision with a
+ * double precision reunitarisation, single precision inversions in the
+ * molecular dynamics, double precision inversions for the Metropolis step.
+ * The paper prints no formula; the library takes:
+ *   S_g = beta sum_{x, mu<nu} (1 - Re tr P_munu(x) / 3)      (Wilson)
+ *   P_mu(x) = sum_a p_a lambda_a / 2, K = (1/2) sum p_a^2, dU/dt = i P U,
+ *   a force F (dS/deps = i tr(T F) for U -> exp(i eps T) U) kicks
+ *   p_a += h Im tr(lambda_a F) / 2,
+ *   gauge force -(beta/3) TA(U_mu(x) A_mu(x)) (A: the six staples),
+ *   S_f = sum_k <phi_k, r(M) phi_k>, heatbath phi_k = r_hb(M) xi_k.
+ * Momenta are DEVICE float64 arrays (4, V, 8) [mu][lex][a] (algebra
+ * coordinates p_a, Gell-Mann order).  The calls that change the links need
+ * them stored as STAG_LINK18_PAIRS or STAG_LINK12_PAIRS (the paper's
+ * float-pair field, Section 5): an update in single precision reads the
+ * single precision half, multiplies by exp(i h P) in single precision and
+ * reorthonormalises in double precision (rows 0 and 1 by Gram-Schmidt, row
+ * 2 = conj(row0 x row1)) before storing the new pair. */
+#define STAG_MAX_PSEUDOFERMIONS 16
+
+/* r(M) = alpha0 + sum_{i<n} alpha[i] (M + shift[i])^-1, 1 <= n <= 64. */
+typedef struct {
+    double alpha0;
+    int n;
+    double alpha[STAG_MAX_SHIFTS];
+    double shift[STAG_MAX_SHIFTS];
+} stag_rational;
+
+typedef struct {
+    double beta;        /* gauge coupling, >= 0 */
+    double mass;        /* > 0 */
+    double tau;         /* trajectory length, > 0 */
+    int n_md;           /* outer (fermion) steps of the integrator, >= 1 */
+    int n_g;            /* gauge steps per half outer step, >= 1 */
+    stag_prec md_prec;  /* STAG_F32: single precision momenta, gauge update and force
+                           inversions (the paper's choice); STAG_F64: all double */
+    int max_iter;       /* iteration limit of every inversion */
+    double tol_md;      /* relative residual of the molecular-dynamics inversions */
+    double tol_act;     /* relative residual of the heatbath and Metropolis inversions */
+    stag_rational rat_md;   /* force of the molecular dynamics */
+    stag_rational rat_act;  /* Metropolis action */
+    stag_rational rat_hb;   /* heatbath */
+} stag_rhmc_params;
+
+typedef struct {
+    double dH;          /* H(end) - H(start) */
+    double H0[3];       /* kinetic, gauge, fermion energy at the start */
+    double H1[3];       /* the same at the end of the molecular dynamics */
+    int accepted;
+    int fermion_forces; /* pseudo-fermion force evaluations (all fields) */
+    int gauge_forces;
+    int md_iters;       /* multi-shift iterations of the molecular dynamics */
+    int action_iters;   /* multi-shift iterations of the heatbath and the action */
+    double seconds;
+} stag_rhmc_info;
+
+/* Canonical complex128 (4, V, 3, 3) copy of the double precision link field
+ * (rows a compressed format does not store are rebuilt).  Asynchronous. */
+stag_status stag_links_get(const stag_lattice *lat, void *links, void *stream);
+
+/* Gauge force F_mu(x) = -(beta/3) TA(U_mu(x) A_mu(x)) into force (DEVICE,
+ * (4, V, 3, 3) complex128), computed in prec (STAG_F64: double precision
+ * links and arithmetic; STAG_F32: the single precision field and
+ * arithmetic).  Any link format.  Asynchronous. */
+stag_status stag_gauge_force(stag_lattice *lat, double beta, void *force, stag_prec prec, void *stream);
+
+/* S_g in double precision from the double precision field (any format),
+ * summed in a fixed order; *action is a HOST double.  Synchronous. */
+stag_status stag_gauge_action(stag_lattice *lat, double beta, double *action, void *stream);
+
+/* One molecular-dynamics step each, on momenta mom (DEVICE (4, V, 8)
+ * float64, converted to prec and back), in precision prec:
+ *   stag_gauge_kick : p_a += h Im tr(lambda_a F_g) / 2 (gauge force, beta);
+ *   stag_force_kick : p_a += h Im tr(lambda_a F) / 2 for a given force
+ *                     (DEVICE (4, V, 3, 3) complex128, e.g. stag_fermion_force's);
+ *   stag_link_update: U <- reunitarise(exp(i h P) U), pair formats only; mom
+ *                     is read only.
+ * Asynchronous. */
+stag_status stag_gauge_kick(stag_lattice *lat, double beta, double h, double *mom, stag_prec prec, void *stream);
+stag_status stag_force_kick(stag_lattice *lat, const void *force, double h, double *mom, stag_prec prec,
+                            void *stream);
+stag_status stag_link_update(stag_lattice *lat, const double *mom, double h, stag_prec prec, void *stream);
+
+/* Molecular dynamics for a time prm->tau from the lattice's links and the
+ * momenta mom (both updated in place) with the n_pf pseudo-fermion fields
+ * phis (HOST array of DEVICE double precision library vectors, fixed during
+ * the integration), in prm->md_prec.  info (HOST, may be NULL) receives the
+ * force and iteration counts.  Synchronous.  STAG_EINVAL on invalid
+ * parameters or links not stored as float pairs. */
+stag_status stag_md_integrate(stag_lattice *lat, const stag_rhmc_params *prm, double *mom, int n_pf,
+                              const void *const *phis, stag_rhmc_info *info, void *stream);
+
+/* One RHMC trajectory: phi_k = r_hb(M) xi_k (double precision), H0 = K +
+ * S_g + sum_k |xi_k|^2, the molecular dynamics with r_md, H1 = K + S_g +
+ * sum_k <phi_k, r_act(M) phi_k> (double precision), and the Metropolis test
+ * against the uniform number u: accepted when u < 0 or u < exp(-dH).  On
+ * rejection the links return to their initial values.  mom (DEVICE (4, V,
+ * 8) float64) holds the momenta drawn by the caller on entry and the final
+ * momenta on exit; xis: HOST array of n_pf DEVICE double precision
+ * Gaussian library vectors.  Synchronous. */
+stag_status stag_rhmc_trajectory(stag_lattice *lat, const stag_rhmc_params *prm, double *mom, int n_pf,
+                                 const void *const *xis, double u, stag_rhmc_info *info, void *stream);
+
 /* ------------------------------------------------------------------ learned preconditioner
  * Not part of the paper: an extension that preconditions the double
  * precision single-shift solve of the Metropolis step (Section 4 keeps that

@@ -17,11 +17,11 @@ import os
 import torch
 
 from ._abi import (F32, F64, MIXED, LINK8, LINK12, LINK18, LINK12_PAIRS, LINK18_PAIRS, MIX_BF16, MIX_FOLDED, MIX_FOLDED_BF16, MIX_FP32, NET_NPARAM, CgStats, StagError,
-                   System, batch_flags, load_library, status_name)
+                   System, batch_flags, load_library, status_name, Rational, RhmcParams, RhmcInfo)
 
 __all__ = ["Lattice", "CgStats", "StagError", "F64", "F32", "MIXED", "LINK18", "LINK12",
            "library_path", "vec_empty", "multishift_cg_batched", "batch_last_config", "Net", "zolotarev", "rational_power",
-           "NET_NPARAM"]
+           "NET_NPARAM", "rhmc_params"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -215,6 +215,56 @@ class Lattice:
                     "stag_rational_apply_multi")
         return outs, rc, [st[k].to_dict(n) for k in range(m)], list(dots)
 
+    # ---------------------------------------------------------------- RHMC trajectory
+    def links_get(self) -> torch.Tensor:
+        """complex128 (4, V, 3, 3) copy of the double precision link field."""
+        out = torch.empty((4, self.V, 3, 3), dtype=torch.complex128, device="cuda")
+        _check(_L.stag_links_get(self._h, _ptr(out), _stream()), "stag_links_get")
+        return out
+
+    def gauge_force(self, beta: float, prec="f64", out=None) -> torch.Tensor:
+        out = torch.empty((4, self.V, 3, 3), dtype=torch.complex128, device="cuda") if out is None else out
+        _check(_L.stag_gauge_force(self._h, float(beta), _ptr(out), _PREC[prec], _stream()), "stag_gauge_force")
+        return out
+
+    def gauge_action(self, beta: float) -> float:
+        a = ctypes.c_double(0.0)
+        _check(_L.stag_gauge_action(self._h, float(beta), ctypes.byref(a), _stream()), "stag_gauge_action")
+        return a.value
+
+    def gauge_kick(self, beta: float, h: float, mom: torch.Tensor, prec="f64") -> torch.Tensor:
+        """mom: float64 (4, V, 8) device tensor, updated in place."""
+        _check(_L.stag_gauge_kick(self._h, float(beta), float(h), _ptr(mom), _PREC[prec], _stream()),
+               "stag_gauge_kick")
+        return mom
+
+    def force_kick(self, force: torch.Tensor, h: float, mom: torch.Tensor, prec="f64") -> torch.Tensor:
+        _check(_L.stag_force_kick(self._h, _ptr(force), float(h), _ptr(mom), _PREC[prec], _stream()),
+               "stag_force_kick")
+        return mom
+
+    def link_update(self, mom: torch.Tensor, h: float, prec="f64"):
+        _check(_L.stag_link_update(self._h, _ptr(mom), float(h), _PREC[prec], _stream()), "stag_link_update")
+
+    def md_integrate(self, prm: RhmcParams, mom: torch.Tensor, phis=()):
+        """Molecular dynamics in place on the links and mom; returns the info dict."""
+        info = RhmcInfo()
+        arr = (ctypes.c_void_p * max(1, len(phis)))(*[t.data_ptr() for t in phis])
+        for t in phis:
+            _ptr(t)
+        _check(_L.stag_md_integrate(self._h, ctypes.byref(prm), _ptr(mom), len(phis), arr, ctypes.byref(info),
+                                    _stream()), "stag_md_integrate")
+        return info.to_dict()
+
+    def rhmc_trajectory(self, prm: RhmcParams, mom: torch.Tensor, xis=(), u=-1.0):
+        info = RhmcInfo()
+        arr = (ctypes.c_void_p * max(1, len(xis)))(*[t.data_ptr() for t in xis])
+        for t in xis:
+            _ptr(t)
+        _check(_L.stag_rhmc_trajectory(self._h, ctypes.byref(prm), _ptr(mom), len(xis), arr, float(u),
+                                       ctypes.byref(info), _stream()), "stag_rhmc_trajectory")
+        return info.to_dict()
+
     def cg(self, mass, shift, src: torch.Tensor, x: torch.Tensor, tol=1e-10, max_iter=100000,
            prec="f64"):
         """Single-shift CG for (M + shift) x = src from the given x (overwritten)."""
@@ -302,6 +352,35 @@ class Net:
         _check(_L.stag_net_train_step(self._h, lat._h, _ptr(b), _ptr(x), int(b.shape[0]), float(lr),
                                       _MIX.get(mode, mode), ctypes.byref(loss), _stream()), "stag_net_train_step")
         return loss.value
+
+
+def _rational(r) -> Rational:
+    out = Rational()
+    if r is None:
+        return out
+    a0, al, sh = r
+    if len(al) != len(sh) or not 1 <= len(al) <= 64:
+        raise ValueError("a rational function needs 1 to 64 (weight, shift) pairs")
+    out.alpha0 = float(a0)
+    out.n = len(al)
+    for i, (a, s_) in enumerate(zip(al, sh)):
+        out.alpha[i] = float(a)
+        out.shift[i] = float(s_)
+    return out
+
+
+def rhmc_params(beta, mass, tau, n_md, n_g, prec="f32", tol_md=1e-8, tol_act=1e-10, rat_md=None,
+                rat_act=None, rat_hb=None, max_iter=100000) -> RhmcParams:
+    """Parameters of stag_md_integrate / stag_rhmc_trajectory; each rational
+    function is (alpha0, alphas, shifts)."""
+    p = RhmcParams()
+    p.beta, p.mass, p.tau = float(beta), float(mass), float(tau)
+    p.n_md, p.n_g = int(n_md), int(n_g)
+    p.md_prec = _PREC[prec]
+    p.max_iter = int(max_iter)
+    p.tol_md, p.tol_act = float(tol_md), float(tol_act)
+    p.rat_md, p.rat_act, p.rat_hb = _rational(rat_md), _rational(rat_act), _rational(rat_hb)
+    return p
 
 
 def zolotarev(power, lo, hi, n):

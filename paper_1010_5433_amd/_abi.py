@@ -65,10 +65,60 @@ class System(ctypes.Structure):
 
 
 BATCH_NO_GRAPH = 0x1
+BATCH_PER_LATTICE = 0x2
 
 
-def batch_flags(no_graph=False, rpt=0, block=0):
-    return (BATCH_NO_GRAPH if no_graph else 0) | ((rpt & 0xF) << 4) | (((block // 64) & 0xF) << 8)
+def batch_flags(no_graph=False, rpt=0, block=0, per_lattice=False):
+    return ((BATCH_NO_GRAPH if no_graph else 0) | (BATCH_PER_LATTICE if per_lattice else 0) | ((rpt & 0xF) << 4) |
+            (((block // 64) & 0xF) << 8))
+
+
+MAX_PSEUDOFERMIONS = 16
+
+
+class Rational(ctypes.Structure):
+    _fields_ = [
+        ("alpha0", _d),
+        ("n", _i),
+        ("alpha", _d * MAX_SHIFTS),
+        ("shift", _d * MAX_SHIFTS),
+    ]
+
+
+class RhmcParams(ctypes.Structure):
+    _fields_ = [
+        ("beta", _d),
+        ("mass", _d),
+        ("tau", _d),
+        ("n_md", _i),
+        ("n_g", _i),
+        ("md_prec", _i),
+        ("max_iter", _i),
+        ("tol_md", _d),
+        ("tol_act", _d),
+        ("rat_md", Rational),
+        ("rat_act", Rational),
+        ("rat_hb", Rational),
+    ]
+
+
+class RhmcInfo(ctypes.Structure):
+    _fields_ = [
+        ("dH", _d),
+        ("H0", _d * 3),
+        ("H1", _d * 3),
+        ("accepted", _i),
+        ("fermion_forces", _i),
+        ("gauge_forces", _i),
+        ("md_iters", _i),
+        ("action_iters", _i),
+        ("seconds", _d),
+    ]
+
+    def to_dict(self) -> dict:
+        return dict(dH=self.dH, H0=list(self.H0), H1=list(self.H1), accepted=bool(self.accepted),
+                    fermion_forces=self.fermion_forces, gauge_forces=self.gauge_forces,
+                    md_iters=self.md_iters, action_iters=self.action_iters, seconds=self.seconds)
 
 
 # name -> (restype, argtypes); the full set of entry points of include/stag.h
@@ -99,6 +149,16 @@ SIGNATURES = {
     "stag_net_train_step": (_i, [_v, _v, _v, _v, _i, _d, _i, ctypes.POINTER(_d), _v]),
     "stag_fcg_solve": (_i, [_v, _d, _d, _v, _v, _v, _i, _d, _i, ctypes.POINTER(CgStats), _v]),
     "stag_fermion_force": (_i, [_v, _i, ctypes.POINTER(_d), ctypes.POINTER(_v), _v, _v]),
+    "stag_links_get": (_i, [_v, _v, _v]),
+    "stag_gauge_force": (_i, [_v, _d, _v, _i, _v]),
+    "stag_gauge_action": (_i, [_v, _d, ctypes.POINTER(_d), _v]),
+    "stag_gauge_kick": (_i, [_v, _d, _d, _v, _i, _v]),
+    "stag_force_kick": (_i, [_v, _v, _d, _v, _i, _v]),
+    "stag_link_update": (_i, [_v, _v, _d, _i, _v]),
+    "stag_md_integrate": (_i, [_v, ctypes.POINTER(RhmcParams), _v, _i, ctypes.POINTER(_v),
+                               ctypes.POINTER(RhmcInfo), _v]),
+    "stag_rhmc_trajectory": (_i, [_v, ctypes.POINTER(RhmcParams), _v, _i, ctypes.POINTER(_v), _d,
+                                  ctypes.POINTER(RhmcInfo), _v]),
     "stag_rational_apply": (_i, [_v, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d), _i, _v, _v, _d, _i,
                                  ctypes.POINTER(_d), ctypes.POINTER(CgStats), _v]),
     "stag_rational_apply_multi": (_i, [_v, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d), _i,

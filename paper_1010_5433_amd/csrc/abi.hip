@@ -70,6 +70,16 @@ stag_status zolotarev(int power, double lo, double hi, int n, double *alpha0, do
 stag_status rational_power(double power, double lo, double hi, int n, double *alpha0, double *alphas, double *shifts,
                            double *delta_out);
 
+stag_status gauge_action(stag_lattice *lat, double beta, double *out, hipStream_t s);
+stag_status gauge_force_out(stag_lattice *lat, double beta, void *force, bool dbl, hipStream_t s);
+stag_status mom_step(stag_lattice *lat, double *mom_canon, int kind, double beta, const void *force, double h,
+                     bool dbl, hipStream_t s);
+stag_status check_md_params(const stag_lattice *lat, const stag_rhmc_params *prm, int n_pf, bool trajectory);
+stag_status md_integrate(stag_lattice *lat, const stag_rhmc_params *prm, double *mom_canon, int n_pf,
+                         const void *const *phis, stag_rhmc_info *info, hipStream_t s);
+stag_status rhmc_trajectory(stag_lattice *lat, const stag_rhmc_params *prm, double *mom_canon, int n_pf,
+                            const void *const *xis, double u, stag_rhmc_info *info, hipStream_t s);
+
 static stag_status use_device(const stag_lattice *lat) {
     int dev = -1;
     STAG_HIP(hipGetDevice(&dev));
@@ -373,6 +383,116 @@ stag_status stag_fermion_force(stag_lattice *lat, int n, const double *alphas, c
         }
         if (!outputs_disjoint(&fr, 1, xr.data(), n)) return invalid("force overlaps a solution");
         return fermion_force(lat, n, alphas, x, force, static_cast<hipStream_t>(stream));
+    } catch (...) {
+        set_error("host allocation failed");
+        return STAG_ENOMEM;
+    }
+}
+
+// ---------------------------------------------------------------- RHMC trajectory
+static size_t force_bytes(const stag_lattice *lat) { return (size_t)(4 * 9 * 16) * (size_t)lat->V; }
+static size_t mom_bytes(const stag_lattice *lat) { return (size_t)(4 * 8 * 8) * (size_t)lat->V; }
+static bool md_prec_ok(stag_prec p) { return p == STAG_F64 || p == STAG_F32; }
+
+stag_status stag_links_get(const stag_lattice *lat, void *links, void *stream) {
+    STAG_TRY(check_lattice(lat, true));
+    if (!links) return invalid("null links");
+    STAG_HIP(launch_unpack_links(lat->g, lat->links64, lat->nrow, links, static_cast<hipStream_t>(stream)));
+    return STAG_OK;
+}
+
+stag_status stag_gauge_force(stag_lattice *lat, double beta, void *force, stag_prec prec, void *stream) {
+    STAG_TRY(check_lattice(lat, true));
+    if (!force) return invalid("null force");
+    if (!(beta >= 0) || !std::isfinite(beta)) return invalid("beta must be >= 0 and finite");
+    if (!md_prec_ok(prec)) return invalid("precision must be STAG_F64 or STAG_F32");
+    return gauge_force_out(lat, beta, force, prec == STAG_F64, static_cast<hipStream_t>(stream));
+}
+
+stag_status stag_gauge_action(stag_lattice *lat, double beta, double *action, void *stream) {
+    try {
+        STAG_TRY(check_lattice(lat, true));
+        if (!action) return invalid("null action");
+        if (!(beta >= 0) || !std::isfinite(beta)) return invalid("beta must be >= 0 and finite");
+        return gauge_action(lat, beta, action, static_cast<hipStream_t>(stream));
+    } catch (...) {
+        set_error("host allocation failed");
+        return STAG_ENOMEM;
+    }
+}
+
+stag_status stag_gauge_kick(stag_lattice *lat, double beta, double h, double *mom, stag_prec prec, void *stream) {
+    STAG_TRY(check_lattice(lat, true));
+    if (!mom) return invalid("null momenta");
+    if (!(beta >= 0) || !std::isfinite(beta) || !std::isfinite(h)) return invalid("beta >= 0 and h must be finite");
+    if (!md_prec_ok(prec)) return invalid("precision must be STAG_F64 or STAG_F32");
+    return mom_step(lat, mom, 0, beta, nullptr, h, prec == STAG_F64, static_cast<hipStream_t>(stream));
+}
+
+stag_status stag_force_kick(stag_lattice *lat, const void *force, double h, double *mom, stag_prec prec,
+                            void *stream) {
+    STAG_TRY(check_lattice(lat, true));
+    if (!mom || !force) return invalid("null argument");
+    if (!std::isfinite(h)) return invalid("h must be finite");
+    if (!md_prec_ok(prec)) return invalid("precision must be STAG_F64 or STAG_F32");
+    if (ranges_overlap({force, force_bytes(lat)}, {mom, mom_bytes(lat)})) return invalid("force overlaps the momenta");
+    return mom_step(lat, mom, 1, 0.0, force, h, prec == STAG_F64, static_cast<hipStream_t>(stream));
+}
+
+stag_status stag_link_update(stag_lattice *lat, const double *mom, double h, stag_prec prec, void *stream) {
+    STAG_TRY(check_lattice(lat, true));
+    if (!mom) return invalid("null momenta");
+    if (!std::isfinite(h)) return invalid("h must be finite");
+    if (!md_prec_ok(prec)) return invalid("precision must be STAG_F64 or STAG_F32");
+    if (lat->nrow != kHiLo + 2 && lat->nrow != kHiLo + 3)
+        return invalid("link updates need the links stored as STAG_LINK18_PAIRS or STAG_LINK12_PAIRS");
+    return mom_step(lat, const_cast<double *>(mom), 2, 0.0, nullptr, h, prec == STAG_F64,
+                    static_cast<hipStream_t>(stream));
+}
+
+static stag_status check_fields(const stag_lattice *lat, const double *mom, int n_pf, const void *const *f) {
+    if (!mom) return invalid("null momenta");
+    if (n_pf > 0 && !f) return invalid("null field array");
+    const size_t vb = (size_t)vec_bytes(lat, true);
+    std::vector<ByteRange> in(n_pf > 0 ? n_pf : 1);
+    for (int k = 0; k < n_pf; ++k) {
+        if (!f[k]) return invalid("null pseudo-fermion field");
+        in[k] = {f[k], vb};
+    }
+    const ByteRange out{mom, mom_bytes(lat)};
+    if (!outputs_disjoint(&out, 1, in.data(), n_pf)) return invalid("the momenta overlap a pseudo-fermion field");
+    return STAG_OK;
+}
+
+stag_status stag_md_integrate(stag_lattice *lat, const stag_rhmc_params *prm, double *mom, int n_pf,
+                              const void *const *phis, stag_rhmc_info *info, void *stream) {
+    try {
+        STAG_TRY(check_lattice(lat, true));
+        STAG_TRY(check_md_params(lat, prm, n_pf, false));
+        STAG_TRY(check_fields(lat, mom, n_pf, phis));
+        stag_rhmc_info local;
+        std::memset(&local, 0, sizeof(local));
+        const stag_status rc = md_integrate(lat, prm, mom, n_pf, phis, &local, static_cast<hipStream_t>(stream));
+        if (info) *info = local;
+        return rc;
+    } catch (...) {
+        set_error("host allocation failed");
+        return STAG_ENOMEM;
+    }
+}
+
+stag_status stag_rhmc_trajectory(stag_lattice *lat, const stag_rhmc_params *prm, double *mom, int n_pf,
+                                 const void *const *xis, double u, stag_rhmc_info *info, void *stream) {
+    try {
+        STAG_TRY(check_lattice(lat, true));
+        STAG_TRY(check_md_params(lat, prm, n_pf, true));
+        STAG_TRY(check_fields(lat, mom, n_pf, xis));
+        if (!(u < 1.0) || std::isnan(u)) return invalid("u must be < 1 (u < 0 accepts unconditionally)");
+        stag_rhmc_info local;
+        std::memset(&local, 0, sizeof(local));
+        const stag_status rc = rhmc_trajectory(lat, prm, mom, n_pf, xis, u, &local, static_cast<hipStream_t>(stream));
+        if (info) *info = local;
+        return rc;
     } catch (...) {
         set_error("host allocation failed");
         return STAG_ENOMEM;

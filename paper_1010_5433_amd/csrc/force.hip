@@ -12,9 +12,11 @@
 // force is F_mu(x) = TA(U_mu(x) W_mu(x)), the traceless anti-Hermitian part:
 // moving U -> exp(i eps T) U changes S at the rate i tr(T F).
 //
-// One lane per eo index writes the four F_mu(x) of both its sites.  Per link and
-// shift it reads two colour vectors (the one at x, the one at x+mu); the
-// link is read once.  The output goes to the (4, V, 3, 3) complex layout in
+// One lane per lattice site, in lex order (even and odd sites alternate in a
+// wave, so the force stores of one direction are contiguous).  The lane
+// holds the four directions' W in registers: per shift it reads its own
+// vector once and the vectors of its four forward neighbours, and each link
+// once at the end.  The output goes to the (4, V, 3, 3) complex layout in
 // which links are handed to the library.  Bandwidth-bound (about 70 flops
 // per shift and link against 96 bytes read), so no matrix cores.
 #include "internal.h"
@@ -38,76 +40,88 @@ struct ForceArgs {
 template <int NROW>
 __global__ void __launch_bounds__(kForceBlock) k_force(ForceArgs a) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int i = tile * kForceBlock + threadIdx.x;
+    const int64_t lex = (int64_t)tile * kForceBlock + threadIdx.x;
     const int vh = a.g.Vh;
-    if (i >= vh) return;
-    // eo index i names the two sites lex = 2i and 2i + 1, one of each
-    // parity: the lane writes both, so a wave's force stores of one
-    // direction cover one contiguous range.
-    int xs[2][4];
-    site_coords(a.g, 0, i, xs[0]);
-    site_coords(a.g, 1, i, xs[1]);
     const int64_t V = 2 * (int64_t)vh;
+    if (lex >= V) return;
+    int x[4];
+    {
+        int64_t r = lex;
+#pragma unroll
+        for (int nu = 0; nu < 4; ++nu) {
+            x[nu] = (int)(r % a.g.L[nu]);
+            r /= a.g.L[nu];
+        }
+    }
+    const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+    const int i = (int)(lex >> 1);
+    int j[4];
+    double es[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        j[mu] = site_nbr(a.g, i, x, mu, +1);
+        es[mu] = p ? -double(fwd_sign(a.g, x, mu)) : double(fwd_sign(a.g, x, mu));
+    }
     const int64_t zstride = 3 * (int64_t)vh;   // double2 entries per odd vector
     const double2 *zb = static_cast<const double2 *>(a.z);
+    cplx<double> W[4][3][3];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) W[mu][r][c] = {0.0, 0.0};
 #pragma unroll 1
-    for (int mu = 0; mu < 4; ++mu) {
-#pragma unroll 1
-        for (int p = 0; p < 2; ++p) {
-            const int *x = xs[p];
-            const int64_t lex = 2 * (int64_t)i + (x[0] & 1);
-            const int j = site_nbr(a.g, i, x, mu, +1);
-            const double es = p ? -double(fwd_sign(a.g, x, mu)) : double(fwd_sign(a.g, x, mu));
-            cplx<double> W[3][3];
+    for (int s = 0; s < a.n; ++s) {
+        // even x: W += Z(x+mu) X(x)^dag; odd x: W -= X(x+mu) Z(x)^dag (the sign is in es)
+        const void *zs = zb + s * zstride;
+        const vec3<double> o = load_vec<double>(p ? zs : a.x[s], vh, i);
+        vec3<double> l[4];
 #pragma unroll
-            for (int r = 0; r < 3; ++r)
+        for (int mu = 0; mu < 4; ++mu) l[mu] = load_vec<double>(p ? a.x[s] : zs, vh, j[mu]);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) W[r][c] = {0.0, 0.0};
-            // four shifts per step keep 24 vector loads in flight per lane
-#pragma unroll 4
-            for (int s = 0; s < a.n; ++s) {
-                const void *zs = zb + s * zstride;
-                // even x: Z(x+mu) X(x)^dag; odd x: X(x+mu) Z(x)^dag
-                const vec3<double> l = load_vec<double>(p ? a.x[s] : zs, vh, j);
-                const vec3<double> rv = load_vec<double>(p ? zs : a.x[s], vh, i);
-                const double k = a.alpha[s] * es;
+        for (int mu = 0; mu < 4; ++mu) {
+            const double k = a.alpha[s] * es[mu];
 #pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const cplx<double> kl = {k * l.c[r].re, k * l.c[r].im};
+            for (int r = 0; r < 3; ++r) {
+                const cplx<double> kl = {k * l[mu].c[r].re, k * l[mu].c[r].im};
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) W[r][c] = W[r][c] + cmul(kl, conj(rv.c[c]));
-                }
+                for (int c = 0; c < 3; ++c) W[mu][r][c] = W[mu][r][c] + cmul(kl, conj(o.c[c]));
             }
-            const su3<double> u = LinkLayout<double, NROW>::load(a.links, vh, p * 4 + mu, i);
-            cplx<double> A[3][3];
-#pragma unroll
-            for (int r = 0; r < 3; ++r)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    cplx<double> t = cmul(u.e[r][0], W[0][c]);
-                    t = t + cmul(u.e[r][1], W[1][c]);
-                    t = t + cmul(u.e[r][2], W[2][c]);
-                    A[r][c] = t;
-                }
-            // TA(A) = (A - A^dag)/2 - tr(A - A^dag)/6; tr(A - A^dag) = 2i Im tr A
-            const double tr_im = (A[0][0].im + A[1][1].im + A[2][2].im) / 3.0;
-            double2 *f = a.force + ((int64_t)mu * V + lex) * 9;
-#pragma unroll
-            for (int r = 0; r < 3; ++r)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    double re = 0.5 * (A[r][c].re - A[c][r].re);
-                    double im = 0.5 * (A[r][c].im + A[c][r].im);
-                    if (r == c) im -= tr_im;
-                    f[r * 3 + c] = make_double2(re, im);
-                }
         }
+    }
+    // fully unrolled, so W stays in registers (a dynamic index puts it in scratch)
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const su3<double> u = LinkLayout<double, NROW>::load(a.links, vh, p * 4 + mu, i);
+        cplx<double> A[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cplx<double> t = cmul(u.e[r][0], W[mu][0][c]);
+                t = t + cmul(u.e[r][1], W[mu][1][c]);
+                t = t + cmul(u.e[r][2], W[mu][2][c]);
+                A[r][c] = t;
+            }
+        // TA(A) = (A - A^dag)/2 - tr(A - A^dag)/6; tr(A - A^dag) = 2i Im tr A
+        const double tr_im = (A[0][0].im + A[1][1].im + A[2][2].im) / 3.0;
+        double2 *f = a.force + ((int64_t)mu * V + lex) * 9;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double re = 0.5 * (A[r][c].re - A[c][r].re);
+                double im = 0.5 * (A[r][c].im + A[c][r].im);
+                if (r == c) im -= tr_im;
+                f[r * 3 + c] = make_double2(re, im);
+            }
     }
 }
 
 template <int NROW>
 static hipError_t launch_force_nrow(const ForceArgs &a, hipStream_t s) {
-    const dim3 grid((a.g.Vh + kForceBlock - 1) / kForceBlock), block(kForceBlock);
+    const dim3 grid((2 * a.g.Vh + kForceBlock - 1) / kForceBlock), block(kForceBlock);
     hipLaunchKernelGGL((k_force<NROW>), grid, block, 0, s, a);
     return hipGetLastError();
 }

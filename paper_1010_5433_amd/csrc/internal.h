@@ -80,6 +80,8 @@ hipError_t launch_pack_links16(const Geom &g, const void *links32, int nrow, voi
 int check_links_blocks(const Geom &g);
 hipError_t launch_check_links(const Geom &g, const void *canon, const void *packed64, int nrow, double *partial,
                               hipStream_t s);
+// packed double precision field -> canonical complex128 (4,V,3,3)
+hipError_t launch_unpack_links(const Geom &g, const void *packed64, int nrow, void *canon, hipStream_t s);
 hipError_t launch_pack_vec(const Geom &g, const void *canon, void *dst, bool dbl, hipStream_t s);
 hipError_t launch_unpack_vec(const Geom &g, const void *src, void *canon, bool dbl, hipStream_t s);
 hipError_t launch_tables(const Geom &g, int32_t *nbr, int32_t *coord, int32_t *sign, hipStream_t s);
@@ -101,6 +103,13 @@ enum WsSlot {
     WS_STATE,      // solver scalar state
     WS_BATCH,      // arena of the batched solver
     WS_FORCE,      // odd-site vectors D_oe X_i of the fermion force
+    WS_MD_MOM,     // momenta of the molecular dynamics (library layout)
+    WS_MD_SOLS,    // multi-shift solutions of the molecular-dynamics force
+    WS_MD_FORCE,   // pseudo-fermion force (4, V, 3, 3)
+    WS_MD_LINKS,   // copy of the links at the start of a trajectory (rejection)
+    WS_MD_PHI,     // pseudo-fermion fields of a trajectory
+    WS_MD_OUT,     // output vector of the Metropolis action
+    WS_MD_PART,    // reduction partials of the energies
     WS_NSLOTS
 };
 

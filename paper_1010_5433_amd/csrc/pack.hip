@@ -32,6 +32,28 @@ __global__ void __launch_bounds__(kPackBlock) k_pack_links(Geom g, const double2
     LinkLayout<R, NROW>::store(dst, g.Vh, p * 4 + mu, lex >> 1, u);
 }
 
+// Packed double precision field (any format) -> canonical complex128
+// (4,V,3,3), rebuilding the rows a compressed format does not store.
+template <int NROW>
+__global__ void __launch_bounds__(kPackBlock) k_unpack_links(Geom g, const void *packed, double2 *canon) {
+    const int64_t vol = 2 * (int64_t)g.Vh;
+    const int64_t k = (int64_t)blockIdx.x * kPackBlock + threadIdx.x;
+    if (k >= 4 * vol) return;
+    const int mu = (int)(k / vol);
+    const int64_t lex = k - mu * vol;
+    int64_t r = lex;
+    int x[4];
+    for (int nu = 0; nu < 4; ++nu) {
+        x[nu] = (int)(r % g.L[nu]);
+        r /= g.L[nu];
+    }
+    const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+    const su3<double> u = LinkLayout<double, NROW>::load(packed, g.Vh, p * 4 + mu, lex >> 1);
+    double2 *dst = canon + k * 9;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) dst[e] = make_double2(u.e[e / 3][e % 3].re, u.e[e / 3][e % 3].im);
+}
+
 // Largest entry-wise difference between the canonical links and the links
 // rebuilt from a packed double precision field (one partial per block).
 template <int NROW>
@@ -163,6 +185,21 @@ hipError_t launch_check_links(const Geom &g, const void *canon, const void *pack
     if (nrow == 1) hipLaunchKernelGGL(k_check_links<1>, dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, packed64, partial);
     else if (nrow == 2) hipLaunchKernelGGL(k_check_links<2>, dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, packed64, partial);
     else hipLaunchKernelGGL(k_check_links<3>, dim3(blocks_for(n)), dim3(kPackBlock), 0, s, g, c, packed64, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_links(const Geom &g, const void *packed64, int nrow, void *canon, hipStream_t s) {
+    const int64_t n = 8 * (int64_t)g.Vh;
+    double2 *c = static_cast<double2 *>(canon);
+    const dim3 grid(blocks_for(n)), block(kPackBlock);
+    switch (nrow) {
+        case 1: hipLaunchKernelGGL(k_unpack_links<1>, grid, block, 0, s, g, packed64, c); break;
+        case 2: hipLaunchKernelGGL(k_unpack_links<2>, grid, block, 0, s, g, packed64, c); break;
+        case 3: hipLaunchKernelGGL(k_unpack_links<3>, grid, block, 0, s, g, packed64, c); break;
+        case kHiLo + 2: hipLaunchKernelGGL(k_unpack_links<kHiLo + 2>, grid, block, 0, s, g, packed64, c); break;
+        case kHiLo + 3: hipLaunchKernelGGL(k_unpack_links<kHiLo + 3>, grid, block, 0, s, g, packed64, c); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
