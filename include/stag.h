@@ -218,7 +218,8 @@ typedef struct {
 } stag_system;
 
 /* flags of stag_multishift_cg_batched */
-#define STAG_BATCH_NO_GRAPH 0x1                 /* accepted for compatibility: iterations are always launched directly */
+#define STAG_BATCH_NO_GRAPH 0x1                 /* launch every kernel of every iteration instead of replaying graphs */
+#define STAG_BATCH_PER_LATTICE 0x2              /* one multi-RHS Dslash launch per lattice instead of one for all */
 #define STAG_BATCH_RPT(r) (((r) & 0xF) << 4)   /* force r right-hand sides per thread (1, 2, 4, 8) ... */
 #define STAG_BATCH_BLOCK(b) ((((b) / 64) & 0xF) << 8) /* ... and b sites per block (64, 128, 256) */
 
@@ -226,13 +227,19 @@ typedef struct {
  * several pseudo-fermions on one gauge field and/or lattices of different
  * sizes -- advanced together (Section 2 lists multiple pseudo-fermions among
  * the algorithm's tricks).  Systems whose `lat` is the same handle share
- * link loads in a multi-RHS Dslash (up to 8 right-hand sides per launch,
- * one launch per lattice and phase); the vector updates and the scalar
+ * link loads in a multi-RHS Dslash (up to 8 right-hand sides per group);
+ * the groups of every lattice run in one launch per phase, each group on
+ * its own range of workgroups (STAG_BATCH_PER_LATTICE: one launch per
+ * lattice and group instead); the vector updates and the scalar
  * recursions of all systems, whatever their lattice, run in one launch per
  * phase.  The launch shape of the multi-RHS Dslash (sites per block,
  * right-hand sides per launch) is timed on the first batch of each layout
- * and cached in the process, unless forced through flags.  Everything runs
- * on `stream`; a done flag is read every 8 iterations, one chunk behind.
+ * and cached in the process, unless forced through flags.  The kernels of
+ * a block of 16 iterations are captured once per call as a HIP graph (on a
+ * private stream, where nothing executes) and the graph is replayed on
+ * `stream` for every block; STAG_BATCH_NO_GRAPH launches them one by one
+ * instead (same kernels, bit-identical results).  A done flag is read
+ * after every block (every 8 iterations without graphs), one block behind.
  * Every shift of every system freezes on its own; each system has its own
  * recursion, mass and shifts; tol and max_iter are shared.
  * prec as for stag_multishift_cg (STAG_MIXED refines every shift that

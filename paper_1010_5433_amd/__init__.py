@@ -409,12 +409,14 @@ def rational_power(power, lo, hi, n):
 
 
 def multishift_cg_batched(systems, tol=1e-10, max_iter=100000, prec="f64", no_graph=False,
-                          rpt=0, block=0):
+                          rpt=0, block=0, per_lattice=False):
     """Batched multi-shift CG.  systems: list of dicts with keys lat (Lattice),
     mass, shifts, src (library vector) and optionally sols.  Systems on the
     same Lattice share link loads.  Returns (list of sols, status, list of
-    stats dicts).  rpt/block force a launch shape (0: autotune); no_graph is
-    accepted and changes nothing (iterations are launched directly)."""
+    stats dicts).  rpt/block force a launch shape (0: autotune); no_graph
+    launches every kernel instead of replaying the captured block of 16
+    iterations; per_lattice makes one multi-RHS Dslash launch per lattice
+    and group instead of one for all lattices."""
     n = len(systems)
     keep = []
     arr = (System * n)()
@@ -434,7 +436,7 @@ def multishift_cg_batched(systems, tol=1e-10, max_iter=100000, prec="f64", no_gr
         arr[k].sols = sp
     st = (CgStats * n)()
     rc = _check(_L.stag_multishift_cg_batched(arr, n, float(tol), int(max_iter), _PREC[prec],
-                                              batch_flags(no_graph, rpt, block), st, _stream()),
+                                              batch_flags(no_graph, rpt, block, per_lattice), st, _stream()),
                 "stag_multishift_cg_batched")
     return all_sols, rc, [st[k].to_dict(len(systems[k]["shifts"])) for k in range(n)]
 

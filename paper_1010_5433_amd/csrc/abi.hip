@@ -581,6 +581,8 @@ stag_status stag_multishift_cg_batched(const stag_system *systems, int n_systems
         opt.max_iter = max_iter;
         opt.dbl = prec == STAG_F64;
         opt.reliable_every = prec == STAG_MIXED ? kDefer : 0;
+        opt.use_graph = !(flags & STAG_BATCH_NO_GRAPH);
+        opt.merge_lattices = !(flags & STAG_BATCH_PER_LATTICE);
         opt.force_rpt = (flags >> 4) & 0xF;
         opt.force_block = ((flags >> 8) & 0xF) * 64;
         if (opt.force_rpt || opt.force_block) {

@@ -131,6 +131,8 @@ struct BOptions {
     int reliable_every;     // 0: none
     int force_block;        // 0: autotune
     int force_rpt;
+    bool use_graph = true;  // replay captured blocks of iterations (false: launch every kernel)
+    bool merge_lattices = true;   // one multi-RHS Dslash launch per phase for all lattices
 };
 
 // per-lattice multi-RHS Dslash with arguments by value; everything on stream s

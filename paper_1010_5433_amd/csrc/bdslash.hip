@@ -51,8 +51,10 @@ struct BDArgs {
 // with |r|^2 partials (double precision; r stored only where out is non-null)
 enum BDRole { BD_OE = 0, BD_EO = 1, BD_RESID = 2 };
 
+// The multi-RHS half-Dslash of one workgroup: `tile` numbers the group of
+// blockDim.x consecutive output sites it covers.
 template <typename R, int NROW, int RPT, int ROLE>
-__global__ void __launch_bounds__(256) kb_dslash(BDArgs a) {
+__device__ __forceinline__ void bd_tile(const BDArgs &a, int tile) {
     const int vh = a.g.Vh;
     bool live[RPT];
     bool any = false;
@@ -63,7 +65,7 @@ __global__ void __launch_bounds__(256) kb_dslash(BDArgs a) {
     }
     if (!any) return;
     const int p = ROLE == BD_OE ? 1 : 0;
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int i = tile * blockDim.x + threadIdx.x;
     vec3<R> acc[RPT];
     double part[RPT];
 #pragma unroll
@@ -139,6 +141,28 @@ __global__ void __launch_bounds__(256) kb_dslash(BDArgs a) {
     }
 }
 
+template <typename R, int NROW, int RPT, int ROLE>
+__global__ void __launch_bounds__(256) kb_dslash(BDArgs a) {
+    bd_tile<R, NROW, RPT, ROLE>(a, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Every lattice of a batch in one launch: group g (a lattice and up to RPT
+// of its systems) owns workgroups [blk0[g], blk0[g+1]); each group's range
+// starts at a multiple of 8, so the XCD-aware tile order holds inside it.
+// The groups' arguments are read from device memory (written once per solve).
+struct BDGroups {
+    int ngroups;
+    int blk0[kMaxBatch + 1];
+};
+
+template <typename R, int NROW, int RPT, int ROLE>
+__global__ void __launch_bounds__(256) kb_dslash_multi(const BDArgs *groups, BDGroups m) {
+    int g = 0;
+    while (g + 1 < m.ngroups && (int)blockIdx.x >= m.blk0[g + 1]) ++g;
+    const int local = (int)blockIdx.x - m.blk0[g];
+    bd_tile<R, NROW, RPT, ROLE>(groups[g], xcd_tile(local, m.blk0[g + 1] - m.blk0[g]));
+}
+
 template <typename R, int NROW, int RPT>
 static hipError_t bd_launch_rpt(int role, int block, const BDArgs &a, hipStream_t s) {
     const dim3 grid((a.g.Vh + block - 1) / block), blk(block);
@@ -172,6 +196,43 @@ static hipError_t bd_launch(bool dbl, int nrow, int role, BDslashCfg cfg, const 
     nrow = nrow_single(nrow);   // a float-pair field: its hi half
     if (nrow == 1) return bd_launch_nrow<float, 1>(role, cfg, a, s);
     return nrow == 2 ? bd_launch_nrow<float, 2>(role, cfg, a, s) : bd_launch_nrow<float, 3>(role, cfg, a, s);
+}
+
+template <typename R, int NROW, int RPT>
+static hipError_t bdm_launch_rpt(int role, int block, const BDArgs *groups, const BDGroups &m, hipStream_t s) {
+    const dim3 grid(m.blk0[m.ngroups]), blk(block);
+    if (role == BD_OE) hipLaunchKernelGGL((kb_dslash_multi<R, NROW, RPT, BD_OE>), grid, blk, 0, s, groups, m);
+    else hipLaunchKernelGGL((kb_dslash_multi<R, NROW, RPT, BD_EO>), grid, blk, 0, s, groups, m);
+    return hipGetLastError();
+}
+
+template <typename R, int NROW>
+static hipError_t bdm_launch_nrow(int role, BDslashCfg cfg, const BDArgs *groups, const BDGroups &m, hipStream_t s) {
+    switch (cfg.rpt) {
+        case 1: return bdm_launch_rpt<R, NROW, 1>(role, cfg.block, groups, m, s);
+        case 2: return bdm_launch_rpt<R, NROW, 2>(role, cfg.block, groups, m, s);
+        case 4: return bdm_launch_rpt<R, NROW, 4>(role, cfg.block, groups, m, s);
+        case 8: return bdm_launch_rpt<R, NROW, 8>(role, cfg.block, groups, m, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// One launch for every group of the batch (roles OE and EO).
+static hipError_t bdm_launch(bool dbl, int nrow, int role, BDslashCfg cfg, const BDArgs *groups, const BDGroups &m,
+                             hipStream_t s) {
+    if (m.ngroups < 1 || m.ngroups > kMaxBatch || role == BD_RESID) return hipErrorInvalidValue;
+    if (cfg.block != 64 && cfg.block != 128 && cfg.block != 256) return hipErrorInvalidValue;
+    if (dbl) {
+        if (nrow == kHiLo + 2) return bdm_launch_nrow<double, kHiLo + 2>(role, cfg, groups, m, s);
+        if (nrow == kHiLo + 3) return bdm_launch_nrow<double, kHiLo + 3>(role, cfg, groups, m, s);
+        if (nrow == 1) return bdm_launch_nrow<double, 1>(role, cfg, groups, m, s);
+        return nrow == 2 ? bdm_launch_nrow<double, 2>(role, cfg, groups, m, s)
+                         : bdm_launch_nrow<double, 3>(role, cfg, groups, m, s);
+    }
+    nrow = nrow_single(nrow);
+    if (nrow == 1) return bdm_launch_nrow<float, 1>(role, cfg, groups, m, s);
+    return nrow == 2 ? bdm_launch_nrow<float, 2>(role, cfg, groups, m, s)
+                     : bdm_launch_nrow<float, 3>(role, cfg, groups, m, s);
 }
 
 // ---------------------------------------------------------------- launch-shape cache
@@ -231,7 +292,8 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
     int max_ds = 1;   // partials of the single-system residual and dot kernels
     for (int l = 0; l < nlat; ++l)
         max_ds = std::max(max_ds, std::max(dslash_grid(lats[l]->g, kDslashBlock), blas_grid(3 * (int64_t)lats[l]->Vh)));
-    size_t bytes = al256(sizeof(BLat) * nlat) + al256(sizeof(BSys) * nsys) + al256(sizeof(MsState) * nsys) + 256;
+    size_t bytes = al256(sizeof(BLat) * nlat) + al256(sizeof(BSys) * nsys) + al256(sizeof(MsState) * nsys) + 256 +
+                   al256(sizeof(BDArgs) * 2 * kMaxBatch);
     for (int k = 0; k < nsys; ++k) {
         const int64_t vh = spec[k].lat->Vh;
         const size_t vb = (size_t)(dbl ? 48 : 24) * vh, v64 = (size_t)48 * vh;
@@ -254,6 +316,7 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
     BSys *d_sys = reinterpret_cast<BSys *>(take(sizeof(BSys) * nsys));
     MsState *d_st = reinterpret_cast<MsState *>(take(sizeof(MsState) * nsys));
     int *d_flag = reinterpret_cast<int *>(take(256));
+    BDArgs *d_groups = reinterpret_cast<BDArgs *>(take(sizeof(BDArgs) * 2 * kMaxBatch));
 
     std::vector<BLat> h_lat(nlat);
     for (int l = 0; l < nlat; ++l) {
@@ -336,7 +399,7 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
     v.nsys = nsys;
 
     // b - (M + shift_i) x_i of system k in double precision, single-system kernels
-    auto residual = [&](int k, int i, void *rout, const int *skip) -> hipError_t {
+    auto residual = [&](int k, int i, void *rout, const int *skip, hipStream_t s) -> hipError_t {
         stag_lattice *lat = spec[k].lat;
         DslashArgs d;
         std::memset(&d, 0, sizeof(d));
@@ -360,7 +423,7 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
 
     // ---- start
     if (all_init) {
-        for (int k = 0; k < nsys; ++k) STAG_HIP(residual(k, 0, h_sys[k].rhi, nullptr));
+        for (int k = 0; k < nsys; ++k) STAG_HIP(residual(k, 0, h_sys[k].rhi, nullptr, s));
         STAG_HIP(launch_bvec(dbl, v, BV_RESTART, max_blocks, s));
         STAG_HIP(launch_bvec(dbl, v, BV_NORM_SRC, max_blocks, s));
         for (int k = 0; k < nsys; ++k)
@@ -455,9 +518,82 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
     }
     g_last_cfg = cfg[0];
     std::vector<std::vector<std::pair<BDArgs, BDArgs>>> args(nlat);
+    int ngroups = 0;
     for (int l = 0; l < nlat; ++l)
-        for (const auto &grp : groups_of(l, cfg[l].rpt))
+        for (const auto &grp : groups_of(l, cfg[l].rpt)) {
             args[l].push_back({make_args(l, grp, BD_OE), make_args(l, grp, BD_EO)});
+            ++ngroups;
+        }
+
+    // ---- one launch per phase for all lattices: every group gets its own
+    // range of workgroups (a multiple of 8 each), the groups' arguments go
+    // to device memory once; the right-hand sides per thread are the largest
+    // of the lattices' tuned values, the block size is timed on this layout
+    const bool merged = opt.merge_lattices && nlat > 1;
+    BDGroups mg;
+    std::memset(&mg, 0, sizeof(mg));
+    BDslashCfg mcfg = {0, 0};
+    std::vector<BDArgs> h_groups;
+    if (merged) {
+        if (ngroups > kMaxBatch) return invalid("too many multi-RHS groups");
+        for (int l = 0; l < nlat; ++l) {
+            mcfg.rpt = std::max(mcfg.rpt, cfg[l].rpt);
+            for (const auto &pa : args[l]) h_groups.push_back(pa.first);
+        }
+        for (int l = 0; l < nlat; ++l)
+            for (const auto &pa : args[l]) h_groups.push_back(pa.second);
+        STAG_HIP(hipMemcpyAsync(d_groups, h_groups.data(), sizeof(BDArgs) * h_groups.size(), hipMemcpyHostToDevice,
+                                s));
+        STAG_HIP(hipStreamSynchronize(s));   // h_groups must outlive the copy
+        mg.ngroups = ngroups;
+        auto layout = [&](int block) {
+            int g = 0;
+            mg.blk0[0] = 0;
+            for (int l = 0; l < nlat; ++l)
+                for (size_t k = 0; k < args[l].size(); ++k, ++g) {
+                    const int nb = (lats[l]->g.Vh + block - 1) / block;
+                    mg.blk0[g + 1] = mg.blk0[g] + ((nb + 7) & ~7);
+                }
+        };
+        std::ostringstream key;
+        key << "multi " << (dbl ? "f64" : "f32") << " nrow" << nrow << " rpt" << mcfg.rpt;
+        for (int l = 0; l < nlat; ++l)
+            key << " " << lats[l]->dims[0] << "x" << lats[l]->dims[1] << "x" << lats[l]->dims[2] << "x"
+                << lats[l]->dims[3] << ":" << members[l].size();
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune.find(key.str());
+            if (it != g_tune.end()) mcfg = it->second;
+        }
+        if (opt.force_block) mcfg.block = opt.force_block;
+        if (!mcfg.block) {
+            hipEvent_t e0, e1;
+            STAG_HIP(hipEventCreate(&e0));
+            STAG_HIP(hipEventCreate(&e1));
+            float best = 1e30f;
+            for (int blk : {64, 128, 256}) {
+                layout(blk);
+                const BDslashCfg cc = {blk, mcfg.rpt};
+                for (int w = 0; w < 7; ++w) {
+                    if (w == 2) STAG_HIP(hipEventRecord(e0, s));
+                    STAG_HIP(bdm_launch(dbl, nrow, BD_OE, cc, d_groups, mg, s));
+                }
+                STAG_HIP(hipEventRecord(e1, s));
+                STAG_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                STAG_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    mcfg.block = blk;
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune[key.str()] = mcfg;
+        }
+        layout(mcfg.block);
+    }
 
     // ---- iterations
     bool any_defer = false, all_defer = true;
@@ -467,15 +603,21 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
     }
     const bool use_rel = !dbl && opt.reliable_every > 0;
     const int check = use_rel ? opt.reliable_every : 0;
-    auto iteration = [&](int it) -> hipError_t {
+    auto iteration = [&](int it, hipStream_t s) -> hipError_t {
         hipError_t e = hipSuccess;
-        for (int l = 0; l < nlat && e == hipSuccess; ++l)
-            for (const auto &pa : args[l]) {
-                e = bd_launch(dbl, nrow, BD_OE, cfg[l], pa.first, s);
-                if (e != hipSuccess) return e;
-                e = bd_launch(dbl, nrow, BD_EO, cfg[l], pa.second, s);
-                if (e != hipSuccess) return e;
-            }
+        if (merged) {
+            e = bdm_launch(dbl, nrow, BD_OE, mcfg, d_groups, mg, s);
+            if (e == hipSuccess) e = bdm_launch(dbl, nrow, BD_EO, mcfg, d_groups + ngroups, mg, s);
+            if (e != hipSuccess) return e;
+        } else {
+            for (int l = 0; l < nlat && e == hipSuccess; ++l)
+                for (const auto &pa : args[l]) {
+                    e = bd_launch(dbl, nrow, BD_OE, cfg[l], pa.first, s);
+                    if (e != hipSuccess) return e;
+                    e = bd_launch(dbl, nrow, BD_EO, cfg[l], pa.second, s);
+                    if (e != hipSuccess) return e;
+                }
+        }
         if (all_defer) {
             if (e == hipSuccess) e = launch_bvec(dbl, v, BV_R_UPDATE_FUSED, max_blocks, s, it);
             if (e == hipSuccess) e = launch_bvec(dbl, v, BV_DIR_FUSED, max_blocks, s, it);
@@ -493,7 +635,7 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
             // reliable update of every system whose residual fell tenfold since its last one
             e = launch_bvec(dbl, v, BV_FLUSH, max_blocks, s);
             for (int k = 0; k < nsys && e == hipSuccess; ++k) {
-                e = residual(k, h_sys[k].base, h_sys[k].rhi, &d_st[k].rel_skip);
+                e = residual(k, h_sys[k].base, h_sys[k].rhi, &d_st[k].rel_skip, s);
                 if (e == hipSuccess)
                     e = launch_reduce_tail(d_st + k, pres[k], dslash_grid(spec[k].lat->g, kDslashBlock), TAIL_RELIABLE,
                                            0, s);
@@ -502,16 +644,57 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
         }
         return e;
     };
+    // Every kernel of an iteration depends on the iteration index only
+    // through it mod kDefer (ring slots, deferred passes, reliable-update
+    // checks every kDefer iterations), so one block of kDefer iterations,
+    // captured once as a graph, is replayed for every block of the solve.
+    // The capture runs on a private stream (nothing executes there); the
+    // replays run on the caller's stream, which is drained before the
+    // executable is destroyed.
+    const int period = kDefer;
+    if (check > 0 && check != period) return invalid("reliable updates must come every kDefer iterations");
+    struct GraphExec {
+        hipGraphExec_t exec = nullptr;
+        hipStream_t replay = nullptr;
+        ~GraphExec() {
+            if (exec) {
+                (void)hipStreamSynchronize(replay);
+                (void)hipGraphExecDestroy(exec);
+            }
+        }
+    } graph;
+    graph.replay = s;
+    if (opt.use_graph) {
+        hipStream_t cs = nullptr;
+        STAG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int k = 0; k < period && e == hipSuccess; ++k) e = iteration(k, cs);
+            const hipError_t e2 = hipStreamEndCapture(cs, &g);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&graph.exec, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) {
+            graph.exec = nullptr;
+            set_error(std::string("capture of the batched iterations failed: ") + hipGetErrorString(e));
+            return STAG_EHIP;
+        }
+    }
     volatile int *flags = lats[0]->host_flags;
     flags[0] = flags[1] = 0;
     hipEvent_t ev[2];
     STAG_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     STAG_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-    constexpr int K = 8;
+    const int K = graph.exec ? period : 8;
     stag_status rc = STAG_OK;
     for (int chunk = 0;; ++chunk) {
         hipError_t e = hipSuccess;
-        for (int k = 0; k < K && e == hipSuccess; ++k) e = iteration(chunk * K + k);
+        if (graph.exec) e = hipGraphLaunch(graph.exec, s);
+        else
+            for (int k = 0; k < K && e == hipSuccess; ++k) e = iteration(chunk * K + k, s);
         if (e == hipSuccess) e = launch_ball_done(v, d_flag, s);
         const int slot = chunk & 1;
         if (e == hipSuccess)

@@ -113,15 +113,23 @@ def test_launch_shapes_agree():
 
 @pytest.mark.parametrize("prec", ["f64", "mixed"])
 def test_repeated_calls_bit_identical(prec):
-    """Three calls (the no-graph flag is accepted and changes nothing): the
-    reductions have a fixed order, so every result is equal bit for bit."""
+    """Graph replays against direct launches: a call that replays its
+    captured block of 16 iterations (many replays per solve), one that
+    launches every kernel, and a second replaying call, with eager work and
+    synchronisations between them.  The reductions have a fixed order and
+    the kernels are the same, so every result is equal bit for bit."""
     import torch
     import paper_1010_5433_amd as stag
     log(f"repeated batched calls prec={prec}")
     lats, systems, host = _setup(SMALL_BATCH)
     a, rca, sa = stag.multishift_cg_batched(systems, prec=prec, rpt=2, block=128)
     a = [[x.clone() for x in s] for s in a]
+    junk = torch.randn(1 << 20, device="cuda").sum()
+    torch.cuda.synchronize()
     b, rcb, sb = stag.multishift_cg_batched(systems, prec=prec, rpt=2, block=128, no_graph=True)
+    b = [[x.clone() for x in s] for s in b]
+    junk = junk + torch.randn(1 << 20, device="cuda").sum()
+    torch.cuda.synchronize()
     c, rcc, sc = stag.multishift_cg_batched(systems, prec=prec, rpt=2, block=128)
     torch.cuda.synchronize()
     assert rca == rcb == rcc == 0
