@@ -38,9 +38,39 @@ __global__ void __launch_bounds__(kDslashBlock) k_dslash(DslashArgs a) {
             acc_mul(acc, R(fwd_sign(a.g, x, mu)), uf, vf);
             acc_mul_dag(acc, R(-bwd_sign(a.g, x, mu)), ub, vb);
         };
-        if (NROW == 1) {
-            // the 8-real rebuild is long: one direction at a time keeps the
-            // registers (and so the waves in flight) of the stored forms
+        if constexpr (NROW == 1 && sizeof(R) == sizeof(double)) {
+            // The 8-real double precision rebuild is long (two phases, two
+            // square roots, a reciprocal): one hop per loop trip, with the next
+            // hop's stored words and neighbour vector loaded before the
+            // current link is rebuilt, so that the rebuild runs while the
+            // next loads are in flight (144 VGPRs, three waves per SIMD).
+            using L8 = LinkLayout<double, 1>;
+            L8::Raw rw;
+            vec3<R> vw;
+            auto fetch = [&](int h) {
+                const int mu = h >> 1;
+                if (h & 1) {
+                    const int jb = site_nbr(a.g, i, x, mu, -1);
+                    rw = L8::load_raw(a.links, vh, (1 - p) * 4 + mu, jb);
+                    vw = load_vec<R>(a.in, vh, jb);
+                } else {
+                    rw = L8::load_raw(a.links, vh, p * 4 + mu, i);
+                    vw = load_vec<R>(a.in, vh, site_nbr(a.g, i, x, mu, +1));
+                }
+            };
+            fetch(0);
+#pragma unroll 1
+            for (int h = 0; h < 8; ++h) {
+                const L8::Raw cw = rw;
+                const vec3<R> cv = vw;
+                if (h < 7) fetch(h + 1);
+                const int mu = h >> 1;
+                if (h & 1) acc_mul_dag(acc, R(-bwd_sign(a.g, x, mu)), L8::build(cw), cv);
+                else acc_mul(acc, R(fwd_sign(a.g, x, mu)), L8::build(cw), cv);
+            }
+        } else if constexpr (NROW == 1) {
+            // single precision: one direction at a time (the prefetching
+            // form measured slower here)
 #pragma unroll 1
             for (int mu = 0; mu < 4; ++mu) hop(mu);
         } else {

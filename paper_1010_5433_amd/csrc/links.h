@@ -200,15 +200,22 @@ __device__ __forceinline__ void pack8_column(const su3<R> &u, cplx<R> &c, R &t) 
 
 template <> struct LinkLayout<double, 1> {
     static constexpr int64_t kBytesPerLink = 64;
-    __device__ static __forceinline__ su3<double> load(const void *base, int64_t vh, int blk, int64_t i) {
+    // the stored words of one link; load_raw issues the loads, build rebuilds
+    // (split so that a kernel can issue the next link's loads first)
+    struct Raw { double2 a, d, c, t; };
+    __device__ static __forceinline__ Raw load_raw(const void *base, int64_t vh, int blk, int64_t i) {
         const double2 *b = static_cast<const double2 *>(base) + (int64_t)blk * 4 * vh;
+        return {ld_nt(&b[0 * vh + i]), ld_nt(&b[1 * vh + i]), ld_nt(&b[2 * vh + i]), ld_nt(&b[3 * vh + i])};
+    }
+    __device__ static __forceinline__ su3<double> build(const Raw &w) {
         su3<double> u;
-        const double2 a = ld_nt(&b[0 * vh + i]), d = ld_nt(&b[1 * vh + i]), c = ld_nt(&b[2 * vh + i]),
-                      t = ld_nt(&b[3 * vh + i]);
-        u.e[0][1] = {a.x, a.y};
-        u.e[0][2] = {d.x, d.y};
-        rebuild8(u, cplx<double>{c.x, c.y}, t.x, t.y);
+        u.e[0][1] = {w.a.x, w.a.y};
+        u.e[0][2] = {w.d.x, w.d.y};
+        rebuild8(u, cplx<double>{w.c.x, w.c.y}, w.t.x, w.t.y);
         return u;
+    }
+    __device__ static __forceinline__ su3<double> load(const void *base, int64_t vh, int blk, int64_t i) {
+        return build(load_raw(base, vh, blk, i));
     }
     __device__ static __forceinline__ void store(void *base, int64_t vh, int blk, int64_t i, const su3<double> &u) {
         double2 *b = static_cast<double2 *>(base) + (int64_t)blk * 4 * vh;
@@ -223,14 +230,20 @@ template <> struct LinkLayout<double, 1> {
 };
 template <> struct LinkLayout<float, 1> {
     static constexpr int64_t kBytesPerLink = 32;
-    __device__ static __forceinline__ su3<float> load(const void *base, int64_t vh, int blk, int64_t i) {
+    struct Raw { float4 a, t; };
+    __device__ static __forceinline__ Raw load_raw(const void *base, int64_t vh, int blk, int64_t i) {
         const float4 *q = reinterpret_cast<const float4 *>(static_cast<const char *>(base) + (int64_t)blk * kBytesPerLink * vh);
+        return {q[0 * vh + i], q[1 * vh + i]};
+    }
+    __device__ static __forceinline__ su3<float> build(const Raw &w) {
         su3<float> u;
-        const float4 a = q[0 * vh + i], t = q[1 * vh + i];
-        u.e[0][1] = {a.x, a.y};
-        u.e[0][2] = {a.z, a.w};
-        rebuild8(u, cplx<float>{t.x, t.y}, t.z, t.w);
+        u.e[0][1] = {w.a.x, w.a.y};
+        u.e[0][2] = {w.a.z, w.a.w};
+        rebuild8(u, cplx<float>{w.t.x, w.t.y}, w.t.z, w.t.w);
         return u;
+    }
+    __device__ static __forceinline__ su3<float> load(const void *base, int64_t vh, int blk, int64_t i) {
+        return build(load_raw(base, vh, blk, i));
     }
     __device__ static __forceinline__ void store(void *base, int64_t vh, int blk, int64_t i, const su3<float> &u) {
         float4 *q = reinterpret_cast<float4 *>(static_cast<char *>(base) + (int64_t)blk * kBytesPerLink * vh);
