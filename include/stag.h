@@ -56,14 +56,18 @@ typedef enum {
     STAG_EBREAKDOWN = 2,  /* non-positive or non-finite curvature <p, A p> */
     STAG_EINVAL = -1,     /* invalid argument (see each call) */
     STAG_ENOMEM = -2,     /* device allocation failed */
-    STAG_EHIP = -3        /* a HIP runtime call failed */
+    STAG_EHIP = -3,       /* a HIP runtime call failed */
+    STAG_STATUS_INT_RANGE_ = 0x7fffffff   /* not a status: makes every int a valid value of the
+                                            type, so a status received as an int can be checked */
 } stag_status;
 
 typedef enum {
     STAG_F64 = 0,    /* double precision vectors and links */
     STAG_F32 = 1,    /* single precision vectors and links, double reductions */
-    STAG_MIXED = 2   /* solvers only: single precision iterations with double
+    STAG_MIXED = 2,  /* solvers only: single precision iterations with double
                         precision reliable updates and per-shift refinement */
+    STAG_PREC_INT_RANGE_ = 0x7fffffff   /* not a precision: every int is a valid value of the type
+                                           (callers pass ints; unknown ones get STAG_EINVAL) */
 } stag_prec;
 
 typedef enum {
@@ -78,7 +82,8 @@ typedef enum {
                         2^-48 |a|), as the only device copy: the single
                         precision kernels read the b half, the double
                         precision ones b + c.  All 9 entries */
-    STAG_LINK12_PAIRS = 4  /* the same for the first two rows (SU(3) links) */
+    STAG_LINK12_PAIRS = 4, /* the same for the first two rows (SU(3) links) */
+    STAG_LINK_FMT_INT_RANGE_ = 0x7fffffff  /* not a format: every int is a valid value of the type */
 } stag_link_fmt;
 
 #define STAG_MAX_SHIFTS 64

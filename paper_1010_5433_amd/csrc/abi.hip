@@ -618,6 +618,7 @@ const char *stag_status_string(stag_status s) {
         case STAG_EINVAL: return "invalid argument";
         case STAG_ENOMEM: return "out of memory";
         case STAG_EHIP: return "HIP runtime error";
+        default: break;
     }
     return "unknown status";
 }
