@@ -13,7 +13,6 @@ field and the source already resident in HBM.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -24,11 +23,19 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 PROFILES = os.path.join(ROOT, "profiles")
-# the sources of the dominant kernel (k_dslash); the committed byte counts
-# are dropped as soon as any of them changes
-KERNEL_SOURCES = ["paper_1010_5433_amd/csrc/dslash.hip", "paper_1010_5433_amd/csrc/common.h",
-                  "paper_1010_5433_amd/csrc/links.h", "paper_1010_5433_amd/csrc/geom.h",
-                  "paper_1010_5433_amd/csrc/internal.h"]
+# instruction hashes of the kernels of this build, written by the build
+KERNEL_HASHES = os.path.join(ROOT, "paper_1010_5433_amd", "libstag.kernels.json")
+# byte counters are committed per kernel together with the hash of its
+# instructions: they are reported only while the built kernel is that one
+KERNEL_SYMBOL = {
+    "k_dslash<double,1,PLAIN>": "void stag::k_dslash<double, 1, 0>(stag::DslashArgs)",
+    "k_dslash<double,2,PLAIN>": "void stag::k_dslash<double, 2, 0>(stag::DslashArgs)",
+    "k_dslash<double,3,PLAIN>": "void stag::k_dslash<double, 3, 0>(stag::DslashArgs)",
+    "k_dslash<float,1,PLAIN>": "void stag::k_dslash<float, 1, 0>(stag::DslashArgs)",
+    "k_dslash<float,2,PLAIN>": "void stag::k_dslash<float, 2, 0>(stag::DslashArgs)",
+    "k_dslash<float,3,PLAIN>": "void stag::k_dslash<float, 3, 0>(stag::DslashArgs)",
+    "k_force<1>": "void stag::k_force<1>(stag::ForceArgs)",
+}
 
 
 def log(msg):
@@ -36,6 +43,18 @@ def log(msg):
 
 
 FMT_NROW = {"18": 3, "12": 2, "8": 1, "18p": 13, "12p": 12}   # "p": one field of float pairs
+
+
+MALL_MB = 256.0   # Infinity Cache
+
+
+def link_field_bytes(dbl: bool, nrow: int, vh: int) -> int:
+    """Bytes of the packed link field the half-Dslash of this precision
+    reads (8 links per even site pair: 4 V links); a float-pair field is read
+    whole in double precision and its single precision half otherwise."""
+    rows = nrow - 10 if nrow > 10 else nrow
+    per_link = (16 if dbl else 8) * (4 if rows == 1 else 3 * rows)
+    return 8 * vh * per_link
 
 
 def dslash_bytes_per_site(dbl: bool, nrow: int, mode: str = "plain") -> int:
@@ -51,18 +70,19 @@ def dslash_bytes_per_site(dbl: bool, nrow: int, mode: str = "plain") -> int:
     return 8 * bl + (3 if mode == "epilogue" else 2) * bv
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+def built_kernel_hash(kernel: str):
+    try:
+        with open(KERNEL_HASHES) as fh:
+            return json.load(fh).get(KERNEL_SYMBOL.get(kernel, kernel))
+    except (OSError, ValueError):
+        return None
 
 
-def read_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    or None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(PROFILES, "dslash_traffic_32x32x32x32.txt")
+def read_traffic(kernel: str, summary: str = "dslash_traffic_32x32x32x32.txt"):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or
+    None when the built kernel's instructions differ from the ones the
+    counters were taken on (or no counters exist for it)."""
+    path = os.path.join(PROFILES, summary)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -70,7 +90,8 @@ def read_traffic(kernel: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_hash") != kernel_source_hash():
+    h = built_kernel_hash(kernel)
+    if h is None or vals.get(f"kernel_isa_hash[{kernel}]") != h:
         return None
     key = f"traffic_bytes_per_launch[{kernel}]"
     return float(vals[key]) if key in vals else None
@@ -100,24 +121,82 @@ def time_dslash(lat, prec, n_warm=5, n_time=50):
     return e0.elapsed_time(e1) / n_time * 1e-3
 
 
-def cpu_baseline(dims, U, b, mass, shifts, gpu_iters, sample_iters):
-    """The FP64 oracle as it stands, on the host cores: the first
-    `sample_iters` iterations of the same solve, scaled to the GPU's
-    iteration count (every shift is still active in the sample, so the
-    extrapolation is an upper bound of the oracle's time to solution)."""
+def _omp_set_threads(n: int):
+    """Thread count of the oracle's OpenMP loops from now on (the loops run
+    on the calling thread's team)."""
+    import ctypes
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
+def cpu_baseline(dims, U, b, mass, shifts, tol, one_core_iters=5):
+    """The FP64 oracle as it stands, on the host cores: the whole multi-shift
+    solve of the same workload (every shift to 1e-10, the 16 final true
+    residuals included), then the time of one iteration on one core (the
+    first `one_core_iters` iterations of the same solve on one thread)."""
     import oracle
     cores = len(os.sched_getaffinity(0))
-    os.environ.setdefault("OMP_NUM_THREADS", str(cores))
-    threads = int(os.environ["OMP_NUM_THREADS"])
     oracle.default()
+    _omp_set_threads(cores)
     t0 = time.perf_counter()
-    oracle.multishift_cg(dims, U, mass, shifts, b, tol=1e-10, max_iter=sample_iters)
+    _, rc, info = oracle.multishift_cg(dims, U, mass, shifts, b, tol=tol)
     dt = time.perf_counter() - t0
-    per_iter = dt / sample_iters
-    return dict(value=round(per_iter * gpu_iters, 3), unit="s", cores=threads, kind="oracle",
-                sample=f"first {sample_iters} multi-shift iterations of the same 32^4 solve "
-                       f"({dt:.1f} s incl. 16 final true residuals), scaled by the GPU's "
-                       f"{gpu_iters} iterations; {per_iter * 1e3:.1f} ms per iteration")
+    if rc != 0:
+        raise RuntimeError(f"oracle solve failed ({rc})")
+    _omp_set_threads(1)
+    t0 = time.perf_counter()
+    oracle.multishift_cg(dims, U, mass, shifts, b, tol=tol, max_iter=one_core_iters)
+    dt1 = (time.perf_counter() - t0) / one_core_iters
+    _omp_set_threads(cores)
+    return dict(value=round(dt, 3), unit="s", cores=cores, kind="oracle",
+                sample=f"the whole solve on {cores} threads ({info['iters']} iterations, 16 final true "
+                       f"residuals); one core: {dt1 * 1e3:.0f} ms per iteration (first {one_core_iters} "
+                       f"iterations, their true residuals included)",
+                iters=info["iters"], one_core_s_per_iter=round(dt1, 4))
+
+
+def config2_experiment(fmt):
+    """Time to solution of the 32^3x8 workload (m = 0.02, 12 shifts in
+    [1e-5, 2], FP64) on the GPU and with the FP64 oracle on the host cores,
+    with the largest true residual of each computed by the oracle's operator."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1010_5433_amd as stag
+    import stag_synth as syn
+
+    c = syn.config("c2_32x32x32x8_smooth")
+    dims, mass, tol = c["dims"], c["mass"], c["tol"]
+    shifts = syn.logspace_shifts(*c["shifts"])
+    U = syn.make_links(c["links"], dims)
+    b = syn.gaussian_source(dims, c["source_seed"])
+    lat = stag.Lattice(dims)
+    lat.set_links(torch.from_numpy(U).cuda(), fmt)
+    src = lat.pack(torch.from_numpy(b).cuda())
+    sols = [torch.empty_like(src) for _ in shifts]
+    lat.multishift_cg(mass, shifts, src, sols=sols, tol=tol)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rc, st = lat.multishift_cg(mass, shifts, src, sols=sols, tol=tol)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    if rc != 0:
+        raise RuntimeError(f"config-2 solve failed ({rc})")
+    xs = [lat.unpack(x).cpu().numpy() for x in sols]
+    cores = len(os.sched_getaffinity(0))
+    _omp_set_threads(cores)
+    t0 = time.perf_counter()
+    xo, rco, info = oracle.multishift_cg(dims, U, mass, shifts, b, tol=tol)
+    t_cpu = time.perf_counter() - t0
+    r_gpu = max(oracle.true_residual(dims, U, mass, s, b, x) for s, x in zip(shifts, xs))
+    diff = max(float(np.linalg.norm(x - y) / np.linalg.norm(y)) for x, y in zip(xs, xo))
+    log(f"config 2: GPU {t_gpu:.4f} s ({st['iters']} iterations), oracle {t_cpu:.2f} s on {cores} threads "
+        f"({info['iters']} iterations); GPU true residual by the oracle's operator {r_gpu:.2e}; "
+        f"largest solution difference {diff:.2e}")
+    lat.close()
+    return dict(lattice=list(dims), mass=mass, n_shifts=len(shifts), links=f"{fmt}-real", gpu_s=round(t_gpu, 4),
+                gpu_iters=st["iters"], oracle_s=round(t_cpu, 3), oracle_iters=info["iters"], oracle_cores=cores,
+                gpu_max_true_resid_by_oracle=r_gpu, max_rel_solution_diff=diff)
 
 
 def batched_experiment(args):
@@ -160,9 +239,24 @@ def batched_experiment(args):
                 raise RuntimeError(f"unbatched solve failed: rc={rc1}")
         torch.cuda.synchronize()
         t_u = time.perf_counter() - t0
+        # the same batch without graph replays, and with one Dslash launch per lattice
+        variants = {}
+        for name, kw in (("no_graph", dict(no_graph=True)), ("per_lattice", dict(per_lattice=True)),
+                         ("no_graph_per_lattice", dict(no_graph=True, per_lattice=True))):
+            stag.multishift_cg_batched(systems, tol=tol, prec=prec, **kw)   # warm-up (launch shape)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, rcv, stv = stag.multishift_cg_batched(systems, tol=tol, prec=prec, **kw)
+            torch.cuda.synchronize()
+            variants[name] = round(time.perf_counter() - t0, 4)
+            if rcv != 0 or max(max(s["resid_true"]) for s in stv) > tol:
+                raise RuntimeError(f"batched solve ({name}) failed: rc={rcv}")
         log(f"batched {prec}: {t_b:.4f} s in one call vs {t_u:.4f} s one system after another "
-            f"(first lattice's launch shape: block {block}, {rpt} right-hand sides per launch)")
+            f"(first lattice's launch shape: block {block}, {rpt} right-hand sides per launch); "
+            f"without graphs {variants['no_graph']:.4f} s, one launch per lattice {variants['per_lattice']:.4f} s, "
+            f"neither {variants['no_graph_per_lattice']:.4f} s")
         out[prec] = dict(batched_s=round(t_b, 4), sequential_s=round(t_u, 4), speedup=round(t_u / t_b, 3),
+                         variants_s=variants,
                          iters=[s["iters"] for s in st], refine_iters=[s["refine_iters"] for s in st],
                          max_resid_true=max(max(s["resid_true"]) for s in st),
                          launch_shape_first_lattice=dict(block=block, rhs_per_launch=rpt))
@@ -201,7 +295,8 @@ def force_experiment(lat, sols, nrow, reps=5):
     t_force = max(t - n * t_doe, 1e-9)
     b_force = force_bytes_per_site(nrow, n) * lat.V
     b_all = b_force + n * dslash_bytes_per_site(True, nrow) * lat.Vh
-    return dict(shifts=n, call_ms=round(t * 1e3, 3), call_GBs=round(b_all / t / 1e9, 1),
+    traffic = read_traffic("k_force<1>", "fermion_force_32x32x32x32.md") if nrow == 1 else None
+    return dict(shifts=n, call_ms=round(t * 1e3, 3), call_GBs=round(b_all / t / 1e9, 1), force_traffic=traffic,
                 d_oe_us=round(t_doe * 1e6, 2), force_kernels_us_est=round(t_force * 1e6, 1),
                 force_kernels_GBs_est=round(b_force / t_force / 1e9, 1),
                 force_algorithmic_bytes=b_force, call_algorithmic_bytes=b_all,
@@ -291,6 +386,94 @@ def rational_experiment(lat, mass, src, tol, n_poles):
     return out
 
 
+def rhmc_experiment(dims=(16, 16, 16, 16), n_md=8, n_g=4, n_therm=10, n_meas=3):
+    """RHMC trajectories of two staggered flavours on the GPU (the paper's
+    setting: single precision gauge update and force inversions, double
+    precision heatbath and Metropolis action): phi = M^(1/4) xi (Remez),
+    the action with M^(-1/2) (Zolotarev), the molecular dynamics force with
+    a coarser M^(-1/2).  The synthetic start field is far from equilibrium,
+    so n_therm trajectories with the Metropolis step come first (single
+    precision); then n_meas trajectories are timed in each precision from
+    the same field, and the reversibility of the molecular dynamics is
+    measured there: forward, momenta flipped, forward again."""
+    import numpy as np
+    import torch
+
+    import paper_1010_5433_amd as stag
+    import stag_synth as syn
+
+    beta, mass, tau = 5.6, 0.05, 1.0
+    lo, hi = mass * mass, mass * mass + 16.0
+    rat_act = stag.zolotarev(-1, lo, hi, 16)[:3]
+    rat_md = stag.zolotarev(-1, lo, hi, 8)[:3]
+    rat_hb = stag.rational_power(0.25, lo, hi, 16)[:3]
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(700)
+
+    def params(prec):
+        return stag.rhmc_params(beta, mass, tau, n_md, n_g, prec=prec, tol_md=1e-6 if prec == "f32" else 1e-10,
+                                tol_act=1e-10, rat_md=rat_md, rat_act=rat_act, rat_hb=rat_hb)
+
+    def draws():
+        p = torch.from_numpy(rng.standard_normal((4, V, 8))).cuda()
+        xi = torch.from_numpy((rng.standard_normal((V // 2, 3)) + 1j * rng.standard_normal((V // 2, 3)))
+                              * np.sqrt(0.5)).cuda()
+        return p, xi
+
+    out = dict(lattice=list(dims), beta=beta, mass=mass, tau=tau, n_md=n_md, n_g=n_g, pseudo_fermions=1,
+               rational=dict(heatbath="Remez M^(1/4), 16 poles", action="Zolotarev M^(-1/2), 16 poles",
+                             md="Zolotarev M^(-1/2), 8 poles"), thermalisation_trajectories=n_therm)
+    lat = stag.Lattice(dims)
+    lat.set_links(torch.from_numpy(syn.smooth_links(dims, 0.5, 700)).cuda(), "18p")
+    acc, dhs = 0, []
+    t0 = time.perf_counter()
+    for _ in range(n_therm):
+        p, xi = draws()
+        info = lat.rhmc_trajectory(params("f32"), p, [lat.pack(xi)], u=float(rng.uniform()))
+        acc += info["accepted"]
+        dhs.append(info["dH"])
+    out["thermalisation"] = dict(seconds=round(time.perf_counter() - t0, 3), accepted=acc,
+                                 dH=[float(f"{v:.3g}") for v in dhs])
+    log(f"rhmc: {n_therm} thermalisation trajectories in {out['thermalisation']['seconds']} s, {acc} accepted, "
+        f"dH {out['thermalisation']['dH']}")
+    U_eq = lat.links_get()
+    for prec in ("f32", "f64"):
+        lat.set_links(U_eq, "18p")
+        res = []
+        for _ in range(n_meas):
+            p, xi = draws()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = lat.rhmc_trajectory(params(prec), p, [lat.pack(xi)], u=-1.0)
+            res.append((time.perf_counter() - t0, info))
+        t = [r[0] for r in res]
+        info = res[-1][1]
+        log(f"rhmc {prec}: trajectories {min(t):.3f}-{max(t):.3f} s, dH {[round(r[1]['dH'], 4) for r in res]}, "
+            f"{info['fermion_forces']} fermion forces, {info['md_iters']} MD iterations, "
+            f"{info['action_iters']} heatbath/action iterations")
+        r = dict(trajectory_s=[round(v, 4) for v in t], dH=[r[1]["dH"] for r in res],
+                 fermion_forces=info["fermion_forces"], gauge_forces=info["gauge_forces"],
+                 md_iters=info["md_iters"], action_iters=info["action_iters"])
+        # reversibility of the molecular dynamics from the thermalised field
+        lat.set_links(U_eq, "18p")
+        U0 = lat.links_get()
+        p0, xi = draws()
+        phi = lat.rational_apply(mass, rat_hb[0], rat_hb[1], rat_hb[2], lat.pack(xi), tol=1e-10)[0]
+        mom = p0.clone()
+        lat.md_integrate(params(prec), mom, [phi])
+        mom.neg_()
+        lat.md_integrate(params(prec), mom, [phi])
+        mom.neg_()
+        dU = lat.links_get() - U0
+        n_dof = 2 * U0.numel() + p0.numel()
+        viol = float(torch.sqrt((torch.sum(torch.abs(dU) ** 2) + torch.sum((mom - p0) ** 2)) / n_dof))
+        r["reversibility_per_dof"] = viol
+        log(f"rhmc {prec}: reversibility {viol:.2e} per degree of freedom (paper, single precision update: ~5e-6)")
+        out[prec] = r
+    lat.close()
+    return out
+
+
 def learned_experiment(args, n_test_fields):
     """Train the gauge-equivariant preconditioner on 16^4 fields and test it
     in flexible CG on held-out 32^4 fields against plain FP64 CG."""
@@ -370,7 +553,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="f64", choices=["mixed", "f64", "f32"])
     ap.add_argument("--fmt", default="8", choices=["18", "12", "8", "18p", "12p"])
-    ap.add_argument("--cpu-sample-iters", type=int, default=40)
+    ap.add_argument("--cpu-one-core-iters", type=int, default=5)
+    ap.add_argument("--no-config2", action="store_true", help="skip the 32^3x8 GPU/oracle comparison")
+    ap.add_argument("--no-rhmc", action="store_true", help="skip the 16^4 RHMC trajectory")
+    ap.add_argument("--rhmc-only", action="store_true", help="run only the RHMC trajectory experiment")
+    ap.add_argument("--learned-test-fields", type=int, default=4,
+                    help="held-out 32^4 fields evaluated in the default run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64-reference", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
@@ -412,6 +600,10 @@ def main():
     if args.batched_only:
         torch.cuda.set_device(0)
         print(json.dumps({"batched": batched_experiment(args)}), flush=True)
+        return
+    if args.rhmc_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"rhmc": rhmc_experiment()}), flush=True)
         return
     if args.learned_only:
         torch.cuda.set_device(0)
@@ -531,7 +723,10 @@ def main():
             d = p == "f64"
             s = time_dslash(lat, p)
             gbs = dslash_bytes_per_site(d, FMT_NROW[fmt]) * lat.Vh / s / 1e9
+            link_mb = link_field_bytes(d, FMT_NROW[fmt], lat.Vh) / 1e6
             dsl[f"{p}_{fmt}"] = dict(us=round(s * 1e6, 2), GBs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4),
+                                     link_field_MB=round(link_mb, 1),
+                                     label=("effective (MALL-resident)" if link_mb < MALL_MB else "HBM"),
                                      traffic=read_traffic(f"k_dslash<{'double' if d else 'float'},{FMT_NROW[fmt]},PLAIN>"))
     lat.set_links(torch.from_numpy(U).cuda(), args.fmt)
     log(f"dslash: {dsl}")
@@ -544,12 +739,17 @@ def main():
     if not args.no_batched:
         extra["batched"] = batched_experiment(args)
     if not args.no_learned:
-        extra["learned"] = learned_experiment(args, 1)
+        extra["learned"] = learned_experiment(args, args.learned_test_fields)
+    if not args.no_config2:
+        extra["config2"] = config2_experiment(args.fmt)
+    if not args.no_rhmc:
+        extra["rhmc"] = rhmc_experiment()
 
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"cpu baseline: oracle, first {args.cpu_sample_iters} iterations")
-        cpu = cpu_baseline(dims, U, b, mass, shifts, st["iters"] + st["refine_iters"], args.cpu_sample_iters)
+        log("cpu baseline: the oracle's whole solve of the same workload, then one core")
+        cpu = cpu_baseline(dims, U, b, mass, shifts, tol, args.cpu_one_core_iters)
+        log(f"cpu baseline: {cpu}")
 
     out = {
         "metric": "multi-shift CG time-to-solution @1e-10 rel resid; Dslash HBM GB/s (% of peak)",
