@@ -97,9 +97,13 @@ def read_traffic(kernel: str, summary: str = "dslash_traffic_32x32x32x32.txt"):
     return float(vals[key]) if key in vals else None
 
 
-def time_dslash(lat, prec, n_warm=5, n_time=50):
-    """Average duration of one half-Dslash launch, HIP events on the stream
-    the library launches on (torch's current stream)."""
+def time_dslash(lat, prec, n_warm=5, n_time=100):
+    """Average duration of one half-Dslash launch: HIP events on the stream
+    the library launches on (torch's current stream) around n_time
+    back-to-back launches.  The average includes the dispatch gap between
+    two dependent launches (a few microseconds), which the kernel-trace
+    average of rocprofv3 does not; events around every single launch were
+    measured to add more than that gap (73 against 66 us at 32^4)."""
     import torch
     vh = lat.Vh
     dt = torch.float64 if prec == "f64" else torch.float32
@@ -386,16 +390,20 @@ def rational_experiment(lat, mass, src, tol, n_poles):
     return out
 
 
-def rhmc_experiment(dims=(16, 16, 16, 16), n_md=8, n_g=4, n_therm=10, n_meas=3):
+def rhmc_experiment(dims=(16, 16, 16, 16), n_md=16, n_g=4, n_forced=8, n_metro=4, n_meas=3):
     """RHMC trajectories of two staggered flavours on the GPU (the paper's
     setting: single precision gauge update and force inversions, double
     precision heatbath and Metropolis action): phi = M^(1/4) xi (Remez),
     the action with M^(-1/2) (Zolotarev), the molecular dynamics force with
-    a coarser M^(-1/2).  The synthetic start field is far from equilibrium,
-    so n_therm trajectories with the Metropolis step come first (single
-    precision); then n_meas trajectories are timed in each precision from
-    the same field, and the reversibility of the molecular dynamics is
-    measured there: forward, momenta flipped, forward again."""
+    a coarser M^(-1/2).  After the thermalisation below, n_meas
+    trajectories are timed in each precision from the same field, and the
+    reversibility of the molecular dynamics is measured there: forward,
+    momenta flipped, forward again.
+
+    The synthetic start field is far from equilibrium at this coupling:
+    n_forced trajectories with half the outer steps are accepted regardless
+    (the field relaxes; dH falls from about 30 to 1), then n_metro
+    trajectories with the Metropolis step."""
     import numpy as np
     import torch
 
@@ -410,8 +418,8 @@ def rhmc_experiment(dims=(16, 16, 16, 16), n_md=8, n_g=4, n_therm=10, n_meas=3):
     V = int(np.prod(dims))
     rng = np.random.default_rng(700)
 
-    def params(prec):
-        return stag.rhmc_params(beta, mass, tau, n_md, n_g, prec=prec, tol_md=1e-6 if prec == "f32" else 1e-10,
+    def params(prec, steps=n_md):
+        return stag.rhmc_params(beta, mass, tau, steps, n_g, prec=prec, tol_md=1e-6 if prec == "f32" else 1e-10,
                                 tol_act=1e-10, rat_md=rat_md, rat_act=rat_act, rat_hb=rat_hb)
 
     def draws():
@@ -422,20 +430,24 @@ def rhmc_experiment(dims=(16, 16, 16, 16), n_md=8, n_g=4, n_therm=10, n_meas=3):
 
     out = dict(lattice=list(dims), beta=beta, mass=mass, tau=tau, n_md=n_md, n_g=n_g, pseudo_fermions=1,
                rational=dict(heatbath="Remez M^(1/4), 16 poles", action="Zolotarev M^(-1/2), 16 poles",
-                             md="Zolotarev M^(-1/2), 8 poles"), thermalisation_trajectories=n_therm)
+                             md="Zolotarev M^(-1/2), 8 poles"))
     lat = stag.Lattice(dims)
     lat.set_links(torch.from_numpy(syn.smooth_links(dims, 0.5, 700)).cuda(), "18p")
-    acc, dhs = 0, []
     t0 = time.perf_counter()
-    for _ in range(n_therm):
+    forced = []
+    for _ in range(n_forced):
+        p, xi = draws()
+        forced.append(lat.rhmc_trajectory(params("f32", n_md // 2), p, [lat.pack(xi)], u=-1.0)["dH"])
+    acc, dhs = 0, []
+    for _ in range(n_metro):
         p, xi = draws()
         info = lat.rhmc_trajectory(params("f32"), p, [lat.pack(xi)], u=float(rng.uniform()))
         acc += info["accepted"]
         dhs.append(info["dH"])
-    out["thermalisation"] = dict(seconds=round(time.perf_counter() - t0, 3), accepted=acc,
-                                 dH=[float(f"{v:.3g}") for v in dhs])
-    log(f"rhmc: {n_therm} thermalisation trajectories in {out['thermalisation']['seconds']} s, {acc} accepted, "
-        f"dH {out['thermalisation']['dH']}")
+    out["thermalisation"] = dict(seconds=round(time.perf_counter() - t0, 3), forced_trajectories=n_forced,
+                                 forced_dH=[float(f"{v:.3g}") for v in forced], metropolis_trajectories=n_metro,
+                                 accepted=acc, dH=[float(f"{v:.3g}") for v in dhs])
+    log(f"rhmc: thermalisation {out['thermalisation']}")
     U_eq = lat.links_get()
     for prec in ("f32", "f64"):
         lat.set_links(U_eq, "18p")
@@ -524,6 +536,13 @@ def learned_experiment(args, n_test_fields):
         src = lat.pack(torch.from_numpy(b).cuda())
         learn.compare(lat, net, mass, src, tol=tol)          # warm-up
         res = learn.compare(lat, net, mass, src, tol=tol)
+        # the fixed two-hop polynomial P = (a + b) - M, a = m^2, b = 1.1 lambda_max,
+        # in the same folded bfloat16 kernels: the network's closed-form competitor
+        lmax = 1.1 * learn.lambda_max(lat, mass)
+        poly = stag.Net(learn.polynomial_theta(lmax, 1.0, scale=1.0 / lmax))
+        learn.compare(lat, poly, mass, src, tol=tol, modes=("folded_bf16",))
+        pres = learn.compare(lat, poly, mass, src, tol=tol, modes=("folded_bf16",))
+        res["polynomial_folded_bf16"] = pres["folded_bf16"]
         for name in res:
             if res[name]["status"] != 0 or res[name]["resid_true"] > tol:
                 raise RuntimeError(f"learned evaluation failed: {name} {res[name]}")
@@ -533,7 +552,7 @@ def learned_experiment(args, n_test_fields):
                                                for k2, v in res[n].items() if k2 != "status"}))
         del lat
     gains = {}
-    for mode in ("bf16", "folded", "folded_bf16"):
+    for mode in ("bf16", "folded", "folded_bf16", "polynomial_folded_bf16"):
         gains[mode] = dict(
             iteration_gain=round(float(np.mean([e["plain_iters"] / e[f"{mode}_iters"] for e in evals])), 3),
             tts_gain=round(float(np.mean([e["plain_seconds"] / e[f"{mode}_seconds"] for e in evals])), 3))

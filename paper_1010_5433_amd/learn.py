@@ -59,6 +59,40 @@ def solve_pairs(lat: Lattice, mass: float, n: int, seed: int, tol=1e-10):
     return B, X
 
 
+# offsets of the parameter blocks in the network's weight vector (include/stag.h)
+_W1S, _W1H, _W2, _WOUT = 0, 8, 72, 648
+
+
+def polynomial_theta(c_self: float, c_dd: float, scale: float = 1.0):
+    """Weights that make the network the fixed two-hop polynomial
+    P = scale (c_self + c_dd D_eo D_oe), through channel 0.  With
+    c_self = a + b - m^2 and c_dd = 1 it is P = scale (a + b - M): for a
+    spectrum in [a, b] the preconditioned operator's condition number drops
+    from b/a to (a + b)^2 / (4 a b)."""
+    import numpy as np
+    th = np.zeros(NET_NPARAM, np.complex128)
+    th[_W1S] = 1.0
+    for d in range(8):
+        th[_W1H + d] = 0.5 if d < 4 else -0.5
+        th[_W2 + 8 + 8 * d] = c_dd * (0.5 if d < 4 else -0.5)
+    th[_W2] = c_self
+    th[_WOUT] = scale
+    return th
+
+
+def lambda_max(lat: Lattice, mass: float, iters: int = 60, seed: int = 99) -> float:
+    """Largest eigenvalue of M by power iteration with the library's operator."""
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(int(seed))
+    x = _white((3, lat.Vh, 2), gen)
+    lam = 0.0
+    for _ in range(iters):
+        y = lat.normal_op(mass, 0.0, x)
+        lam = float((x * y).sum() / (x * x).sum())
+        x = y / torch.linalg.vector_norm(y)
+    return lam
+
+
 def init_theta(seed: int, scale: float = 0.1):
     import numpy as np
     rng = np.random.default_rng(seed)

@@ -50,14 +50,18 @@ def rand_theta(seed, scale=0.3):
 
 
 def poly_theta(c_self, c_dd, scale=1.0):
-    """P = scale * (c_self + c_dd D_eo D_oe) through channel 0."""
-    th = np.zeros(NP, np.complex128)
-    th[W1S] = 1.0
+    """P = scale * (c_self + c_dd D_eo D_oe) through channel 0 (the library
+    helper the benchmark uses; checked here against its definition)."""
+    from paper_1010_5433_amd.learn import polynomial_theta
+    th = polynomial_theta(c_self, c_dd, scale)
+    ref = np.zeros(NP, np.complex128)
+    ref[W1S] = 1.0
     for d in range(8):
-        th[W1H + d] = 0.5 if d < 4 else -0.5
-        th[W2 + 8 + 8 * d] = c_dd * (0.5 if d < 4 else -0.5)
-    th[W2] = c_self
-    th[WOUT] = scale
+        ref[W1H + d] = 0.5 if d < 4 else -0.5
+        ref[W2 + 8 + 8 * d] = c_dd * (0.5 if d < 4 else -0.5)
+    ref[W2] = c_self
+    ref[WOUT] = scale
+    assert np.array_equal(th, ref)
     return th
 
 
