@@ -39,7 +39,9 @@
  * streams (or host threads) at once.
  * Errors: no C++ exception crosses this boundary.  Every call returns a
  * stag_status; stag_last_error() gives a message for the calling thread.
- */
+ * Environment: STAG_LOG=1 prints one line per solve and trajectory on
+ * stderr ("[stag] ..."); STAG_AUTOTUNE_CACHE=<file> keeps the batched
+ * solver's timed launch shapes across processes (one line per layout). */
 #ifndef STAG_H
 #define STAG_H
 

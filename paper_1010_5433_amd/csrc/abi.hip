@@ -2,6 +2,7 @@
 // management, and dispatch to the kernels and solver drivers.  No C++
 // exception crosses this boundary.
 #include <algorithm>
+#include <cstdarg>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -32,6 +33,18 @@ bool outputs_disjoint(const ByteRange *outs, int n_out, const ByteRange *ins, in
         if (it != o.begin() && ranges_overlap(*(it - 1), ins[j])) return false;
     }
     return true;
+}
+
+void stag_log(int level, const char *fmt, ...) {
+    const char *env = std::getenv("STAG_LOG");
+    if (!env || std::atoi(env) < level) return;
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "[stag] %s\n", buf);
+    std::fflush(stderr);
 }
 
 static thread_local std::string g_last_error;

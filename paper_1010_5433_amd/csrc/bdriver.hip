@@ -90,8 +90,7 @@ stag_status rational_apply_multi(stag_lattice *lat, double mass, double alpha0, 
         spec[k].rat_w0 = alpha0;
         spec[k].rat_out = outs[k];
     }
-    BOptions opt;
-    std::memset(&opt, 0, sizeof(opt));
+    BOptions opt{};   // the defaults: graph replays, one launch for all lattices
     opt.tol = tol;
     opt.max_iter = max_iter;
     opt.dbl = true;

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <chrono>
 #include <cstring>
 #include <map>
@@ -239,6 +241,45 @@ static hipError_t bdm_launch(bool dbl, int nrow, int role, BDslashCfg cfg, const
 
 static std::mutex g_tune_mu;
 static std::map<std::string, BDslashCfg> g_tune;
+
+// Launch shapes persist across processes when the environment variable
+// STAG_AUTOTUNE_CACHE names a file: one line per layout,
+// "<layout key>\t<sites per block>\t<right-hand sides per launch>".  A layout
+// missing from the process cache is looked up there before it is timed; a
+// newly timed one is appended.  Lines that do not parse, or name a shape the
+// kernels do not have, are ignored.  (Callers hold g_tune_mu.)
+static bool shape_ok(BDslashCfg c) {
+    return (c.block == 64 || c.block == 128 || c.block == 256) && (c.rpt == 1 || c.rpt == 2 || c.rpt == 4 || c.rpt == 8);
+}
+static bool tune_file_lookup(const std::string &key, BDslashCfg *out) {
+    const char *path = std::getenv("STAG_AUTOTUNE_CACHE");
+    if (!path || !*path) return false;
+    std::FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        char *t1 = std::strchr(line, '\t');
+        if (!t1) continue;
+        *t1 = 0;
+        if (key != line) continue;
+        BDslashCfg c = {0, 0};
+        if (std::sscanf(t1 + 1, "%d\t%d", &c.block, &c.rpt) == 2 && shape_ok(c)) {
+            *out = c;   // the last matching line wins
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+static void tune_file_append(const std::string &key, BDslashCfg c) {
+    const char *path = std::getenv("STAG_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    std::FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s\t%d\t%d\n", key.c_str(), c.block, c.rpt);
+    std::fclose(f);
+}
 static thread_local BDslashCfg g_last_cfg = {0, 0};
 
 BDslashCfg last_batch_cfg() { return g_last_cfg; }
@@ -483,6 +524,7 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tune.find(key.str());
             if (it != g_tune.end()) c = it->second;
+            else if (tune_file_lookup(key.str(), &c)) g_tune[key.str()] = c;
         }
         if (!c.block) {
             hipEvent_t e0, e1;
@@ -513,6 +555,9 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
             (void)hipEventDestroy(e1);
             std::lock_guard<std::mutex> lk(g_tune_mu);
             g_tune[key.str()] = c;
+            tune_file_append(key.str(), c);
+            stag_log(1, "batched: launch shape of %s timed: %d sites per block, %d right-hand sides", key.str().c_str(),
+                     c.block, c.rpt);
         }
         cfg[l] = c;
     }
@@ -564,6 +609,7 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tune.find(key.str());
             if (it != g_tune.end()) mcfg = it->second;
+            else if (tune_file_lookup(key.str(), &mcfg)) g_tune[key.str()] = mcfg;
         }
         if (opt.force_block) mcfg.block = opt.force_block;
         if (!mcfg.block) {
@@ -591,6 +637,8 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
             (void)hipEventDestroy(e1);
             std::lock_guard<std::mutex> lk(g_tune_mu);
             g_tune[key.str()] = mcfg;
+            tune_file_append(key.str(), mcfg);
+            stag_log(1, "batched: launch shape of %s timed: %d sites per block", key.str().c_str(), mcfg.block);
         }
         layout(mcfg.block);
     }

@@ -30,6 +30,11 @@ const char *last_error();
         if (s_ != STAG_OK) return s_;                                                        \
     } while (0)
 
+// Diagnostic messages on stderr, "[stag] ..." plus a newline, when the
+// environment variable STAG_LOG is set to a level >= `level` (1: one line
+// per solve or trajectory, 2: also per phase).  Read at every call.
+void stag_log(int level, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
 inline stag_status invalid(const std::string &msg) {
     set_error(msg);
     return STAG_EINVAL;

@@ -745,6 +745,9 @@ stag_status rhmc_trajectory(stag_lattice *lat, const stag_rhmc_params *prm, doub
     if (!info->accepted) STAG_HIP(hipMemcpyAsync(lat->links64, bak, lb, hipMemcpyDeviceToDevice, s));
     STAG_HIP(hipStreamSynchronize(s));
     info->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stag_log(1, "rhmc_trajectory: dH %.6g (K %.6g, S_g %.6g, S_f %.6g -> %.6g, %.6g, %.6g), %s, %d fermion forces, "
+             "%d MD iterations, %.4f s", info->dH, k0, sg0, sf0, k1, sg1, sf1, info->accepted ? "accepted" : "rejected",
+             info->fermion_forces, info->md_iters, info->seconds);
     return STAG_OK;
 }
 

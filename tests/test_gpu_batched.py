@@ -139,6 +139,71 @@ def test_repeated_calls_bit_identical(prec):
     assert [s["iters"] for s in sa] == [s["iters"] for s in sb]
 
 
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_merged_launch_equals_per_lattice_launches(prec):
+    """Three lattices of different sizes (one with three systems): the one
+    multi-RHS launch per phase for all lattices, each group on its own range
+    of workgroups, gives results bit-identical to one launch per lattice and
+    group (same launch shape forced on both), with and without graphs."""
+    import torch
+    import paper_1010_5433_amd as stag
+    log(f"merged vs per-lattice launches prec={prec}")
+    lats, systems, host = _setup(SMALL_BATCH)
+    runs = {}
+    for name, kw in (("merged", {}), ("per_lattice", dict(per_lattice=True)),
+                     ("merged_no_graph", dict(no_graph=True))):
+        sols, rc, st = stag.multishift_cg_batched(systems, prec=prec, rpt=4, block=64, **kw)
+        torch.cuda.synchronize()
+        assert rc == 0, name
+        runs[name] = ([[x.clone() for x in s] for s in sols], [t["iters"] for t in st])
+    ref_sols, ref_its = runs["per_lattice"]
+    for name, (sols, its) in runs.items():
+        assert its == ref_its, name
+        for a, b in zip(sols, ref_sols):
+            for x, y in zip(a, b):
+                assert torch.equal(x, y), name
+
+
+def test_autotune_cache_file(tmp_path, monkeypatch):
+    """STAG_AUTOTUNE_CACHE: a layout found in the file is used without
+    timing; a layout timed in this process is appended to the file."""
+    import torch
+    import paper_1010_5433_amd as stag
+    path = tmp_path / "shapes.txt"
+    seeded = "f64 nrow3 6x6x6x6:2"
+    path.write_text(f"garbage line\n{seeded}\t128\t2\n")
+    monkeypatch.setenv("STAG_AUTOTUNE_CACHE", str(path))
+    specs_seeded = [((6, 6, 6, 6), 44, 0.1, [0.0, 0.5], [7, 8])]
+    _, systems, _ = _setup(specs_seeded)
+    _, rc, _ = stag.multishift_cg_batched(systems, prec="f64")
+    torch.cuda.synchronize()
+    assert rc == 0 and stag.batch_last_config() == (128, 2)
+    specs_new = [((6, 6, 4, 4), 45, 0.1, [0.0, 0.5], [9, 10, 11])]
+    _, systems, _ = _setup(specs_new)
+    _, rc, _ = stag.multishift_cg_batched(systems, prec="f64")
+    torch.cuda.synchronize()
+    assert rc == 0
+    block, rpt = stag.batch_last_config()
+    assert f"f64 nrow3 6x6x4x4:3\t{block}\t{rpt}" in path.read_text().splitlines()
+
+
+def test_log_lines(capfd, monkeypatch):
+    """STAG_LOG=1 prints one line per solve on stderr; unset, nothing."""
+    import torch
+    import paper_1010_5433_amd as stag
+    _, systems, _ = _setup([((4, 4, 4, 4), 46, 0.1, [0.0, 0.3], [12])])
+    y = systems[0]
+    monkeypatch.setenv("STAG_LOG", "1")
+    y["lat"].multishift_cg(y["mass"], y["shifts"], y["src"])
+    torch.cuda.synchronize()
+    err = capfd.readouterr().err
+    assert "[stag] multishift_cg: 2 shifts, f64" in err
+    monkeypatch.delenv("STAG_LOG")
+    y["lat"].multishift_cg(y["mass"], y["shifts"], y["src"])
+    torch.cuda.synchronize()
+    assert "[stag]" not in capfd.readouterr().err
+
+
 def test_batched_config4_full_size(orc):
     """8 pseudo-fermions x 16 shifts on 24^3x6 (m = 0.02) plus 8^4, 12^4 and
     16^3x8 (m = 0.05, 8 shifts each), FP32 with FP64 reliable updates and
