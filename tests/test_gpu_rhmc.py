@@ -196,6 +196,38 @@ def test_md_with_fermions_vs_oracle(orc, dims):
     lat.close()
 
 
+def test_md_single_precision_and_12_real_pairs_vs_oracle(orc):
+    """The paper's setting (single precision momenta, gauge update and force
+    solves at tol 1e-6) stays close to the double precision oracle over
+    tau = 0.5; the 12-real float-pair field in double precision matches it
+    to rounding."""
+    dims = (4, 4, 2, 4)
+    U0 = syn.smooth_links(dims, 0.5, 30)
+    p = _momenta(dims, 31)
+    phis = [syn.gaussian_source(dims, 32), syn.gaussian_source(dims, 33)]
+    # double precision, 12-real pairs
+    lat = lattice_with_links(dims, U0, "12p")
+    U = _host(lat.links_get())
+    mom = to_dev(p.copy())
+    lat.md_integrate(_params("f64"), mom, [pack(lat, f) for f in phis])
+    Ur, pr, _ = rhmc.md_integrate(orc, dims, U, p, phis, _oracle_prm())
+    assert np.abs(_host(lat.links_get()) - Ur).max() <= 1e-9
+    assert np.abs(_host(mom) - pr).max() <= 1e-8 * max(1.0, np.abs(pr).max())
+    lat.close()
+    # single precision, 18-real pairs
+    lat = lattice_with_links(dims, U0, "18p")
+    U = _host(lat.links_get())
+    mom = to_dev(p.copy())
+    info = lat.md_integrate(_params("f32", tol_md=1e-6), mom, [pack(lat, f) for f in phis])
+    Ur, pr, _ = rhmc.md_integrate(orc, dims, U, p, phis, _oracle_prm())
+    du = np.abs(_host(lat.links_get()) - Ur).max()
+    dp = np.abs(_host(mom) - pr).max()
+    log(f"single precision molecular dynamics against the double precision oracle: links {du:.2e}, momenta {dp:.2e}")
+    assert du <= 1e-4 and dp <= 1e-3 * max(1.0, np.abs(pr).max())
+    assert info["fermion_forces"] == 2 * 4 + 1
+    lat.close()
+
+
 def test_trajectory_vs_oracle(orc):
     dims = (4, 4, 2, 4)
     U0 = syn.smooth_links(dims, 0.5, 30)
