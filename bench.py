@@ -97,13 +97,15 @@ def read_traffic(kernel: str, summary: str = "dslash_traffic_32x32x32x32.txt"):
     return float(vals[key]) if key in vals else None
 
 
-def time_dslash(lat, prec, n_warm=5, n_time=100):
+def time_dslash(lat, prec, n_warm=5, n_time=100, n_rep=3):
     """Average duration of one half-Dslash launch: HIP events on the stream
     the library launches on (torch's current stream) around n_time
-    back-to-back launches.  The average includes the dispatch gap between
-    two dependent launches (a few microseconds), which the kernel-trace
-    average of rocprofv3 does not; events around every single launch were
-    measured to add more than that gap (73 against 66 us at 32^4)."""
+    back-to-back launches, the median over n_rep such loops.  A rocprofv3
+    kernel trace of such loops shows the launches back to back (under 0.1 us
+    between one kernel's end and the next one's start on average), so the
+    figure is the kernel's own duration.  Events around single launches
+    were measured to add several microseconds each, inside the solver as
+    well as here, so the bench does not time launches one by one."""
     import torch
     vh = lat.Vh
     dt = torch.float64 if prec == "f64" else torch.float32
@@ -113,16 +115,19 @@ def time_dslash(lat, prec, n_warm=5, n_time=100):
         lat.dslash_eo(0, x, y)
         lat.dslash_eo(1, y, x)
     s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for k in range(n_time):
-        if k & 1:
-            lat.dslash_eo(1, y, x)
-        else:
-            lat.dslash_eo(0, x, y)
-    e1.record(s)
-    e1.synchronize()
-    return e0.elapsed_time(e1) / n_time * 1e-3
+    loops = []
+    for _ in range(n_rep):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for k in range(n_time):
+            if k & 1:
+                lat.dslash_eo(1, y, x)
+            else:
+                lat.dslash_eo(0, x, y)
+        e1.record(s)
+        e1.synchronize()
+        loops.append(e0.elapsed_time(e1) / n_time * 1e-3)
+    return sorted(loops)[len(loops) // 2]
 
 
 def _omp_set_threads(n: int):
@@ -646,7 +651,8 @@ def main():
     if args.only_dslash or args.only_force:
         if args.only_dslash:
             log(f"profiling aid: {args.only_dslash} half-Dslash launches ({it_prec}, {args.fmt}-real)")
-            time_dslash(lat, it_prec, n_warm=2, n_time=args.only_dslash)
+            sec = time_dslash(lat, it_prec, n_warm=2, n_time=args.only_dslash, n_rep=1)
+            log(f"half-Dslash by HIP events: {sec * 1e6:.2f} us per launch over {args.only_dslash} launches")
         if args.only_force:
             log(f"profiling aid: {args.only_force} fermion-force calls, 16 random solutions ({args.fmt}-real)")
             xs = [torch.randn(3, lat.Vh, 2, dtype=torch.float64, device="cuda") for _ in range(16)]

@@ -50,7 +50,8 @@ def _compile(src: str, extra) -> str:
 
 
 def _kernel_hashes(src: str, extra) -> dict:
-    """Demangled kernel name -> hash of its instructions (comments dropped)."""
+    """Demangled kernel name -> hash of its instructions (comments dropped,
+    block labels numbered within the function only)."""
     asm = os.path.join(BUILD, os.path.basename(src) + ".s")
     cmd = [HIPCC, "--cuda-device-only", "-S", src, "-o", asm] + CFLAGS + list(extra)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -70,7 +71,8 @@ def _kernel_hashes(src: str, extra) -> dict:
             continue
         text = line.split(";", 1)[0].strip()
         if text:
-            body.append(text + "\n")
+            # block labels carry the function's position in the file: drop it
+            body.append(re.sub(r"\.LBB\d+_", ".LBB_", text) + "\n")
     if not out:
         return {}
     dem = subprocess.run(["c++filt"], input="\n".join(out), capture_output=True, text=True, check=True)

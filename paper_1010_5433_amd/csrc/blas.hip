@@ -38,6 +38,18 @@ __device__ __forceinline__ double sum_partials(const double *part, int nparts) {
 
 template <typename R> using T2 = typename vtype<R>::t2;
 
+// Vector access of the solver's per-iteration kernels: with NT the loads and
+// stores are nontemporal, so that the streamed vectors do not push the link
+// blocks that the Dslash keeps in the Infinity Cache out of it.
+template <bool NT, typename V> __device__ __forceinline__ V ldv(const V *p) {
+    if constexpr (NT) return ld_nt(p);
+    else return *p;
+}
+template <bool NT, typename V> __device__ __forceinline__ void stv(V *p, V v) {
+    if constexpr (NT) st_nt(p, v);
+    else *p = v;
+}
+
 template <typename R> __device__ __forceinline__ double abs2(T2<R> v) {
     return double(v.x) * double(v.x) + double(v.y) * double(v.y);
 }
@@ -135,7 +147,7 @@ __global__ void __launch_bounds__(kBlasBlock) k_shift_update(const MsState *st, 
 // Fused forms (see solver.h).  Every block reduces the partials in the order
 // of k_reduce_tail (threads stride kBlasBlock, then block_sum), so alpha and
 // beta equal the tail kernel's bit for bit.
-template <typename R>
+template <typename R, bool NT>
 __global__ void __launch_bounds__(kBlasBlock) k_r_update_fused(MsState *st, const double *pq_part, int npq,
                                                             const T2<R> *rin, T2<R> *r, const T2<R> *ap, int64_t n,
                                                             double *partial) {
@@ -153,18 +165,18 @@ __global__ void __launch_bounds__(kBlasBlock) k_r_update_fused(MsState *st, cons
     const R alpha = R(st->rho / pap);   // rho is not written by this kernel
     double part = 0.0;
     for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
-        T2<R> rv = rin[j];
-        const T2<R> q = ap[j];
+        T2<R> rv = ldv<NT>(&rin[j]);
+        const T2<R> q = ldv<NT>(&ap[j]);
         rv.x -= alpha * q.x;
         rv.y -= alpha * q.y;
-        r[j] = rv;
+        stv<NT>(&r[j], rv);
         part += abs2<R>(rv);
     }
     const double s = block_sum(part, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-template <typename R>
+template <typename R, bool NT>
 __global__ void __launch_bounds__(kBlasBlock) k_dir_update_fused(MsState *st, const double *r_part, int nr,
                                                               const T2<R> *r, T2<R> *pd, int64_t n) {
     if (st->done) return;
@@ -175,11 +187,11 @@ __global__ void __launch_bounds__(kBlasBlock) k_dir_update_fused(MsState *st, co
     const R beta = R(rho_new / st->rho_snap);   // block 0 rewrites rho below, not rho_snap
     if (blockIdx.x == 0) ms_beta_step(st, rho_new);
     for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
-        const T2<R> rv = r[j];
-        T2<R> pv = pd[j];
+        const T2<R> rv = ldv<NT>(&r[j]);
+        T2<R> pv = ldv<NT>(&pd[j]);
         pv.x = rv.x + beta * pv.x;
         pv.y = rv.y + beta * pv.y;
-        pd[j] = pv;
+        stv<NT>(&pd[j], pv);
     }
 }
 
@@ -192,7 +204,7 @@ __global__ void __launch_bounds__(kWave) k_defer_coef(MsState *st, DeferHist *h)
 // x_i += cx0 p_i + sum_m cx_m r_m and p_i = cp0 p_i + sum_m cp_m r_m,
 // the block's residuals read once for all shifts.  RAT: the (weighted)
 // increments of all shifts go into one output vector instead.
-template <typename R, bool RAT>
+template <typename R, bool RAT, bool NT>
 __global__ void __launch_bounds__(kBlasBlock) k_defer_apply(const MsState *st, const DeferHist *h, const T2<R> *ring,
                                                          int64_t slot, ShiftPtrs ptrs, int n_shift, int64_t n,
                                                          T2<R> *out) {
@@ -203,29 +215,29 @@ __global__ void __launch_bounds__(kBlasBlock) k_defer_apply(const MsState *st, c
 #pragma unroll
         for (int m = 0; m < kDefer; ++m) {
             if (m < nv) {
-                rr[m] = ring[m * slot + j];
+                rr[m] = ldv<NT>(&ring[m * slot + j]);
             } else {
                 rr[m].x = R(0);
                 rr[m].y = R(0);
             }
         }
         T2<R> acc;
-        if (RAT) acc = out[j];
+        if (RAT) acc = ldv<NT>(&out[j]);
         for (int i = 0; i < n_shift; ++i) {
             if (!h->act[i]) continue;
             T2<R> *pi = static_cast<T2<R> *>(ptrs.p[i]);
-            T2<R> pv = pi[j];
+            T2<R> pv = ldv<NT>(&pi[j]);
             if (RAT) {
                 defer_combine<T2<R>, R>(h, i, rr, acc, pv);
             } else {
                 T2<R> *xi = static_cast<T2<R> *>(ptrs.x[i]);
-                T2<R> xv = xi[j];
+                T2<R> xv = ldv<NT>(&xi[j]);
                 defer_combine<T2<R>, R>(h, i, rr, xv, pv);
-                xi[j] = xv;
+                stv<NT>(&xi[j], xv);
             }
-            pi[j] = pv;
+            stv<NT>(&pi[j], pv);
         }
-        if (RAT) out[j] = acc;
+        if (RAT) stv<NT>(&out[j], acc);
     }
 }
 
@@ -363,31 +375,44 @@ hipError_t launch_r_update(bool dbl, MsState *st, const void *rin, void *r, cons
     return hipGetLastError();
 }
 
+template <bool RAT, bool NT>
+static void defer_apply64(const MsState *st, const DeferHist *h, const void *ring, int64_t slot_elems, ShiftPtrs ptrs,
+                          int n_shift, int64_t n, int grid, hipStream_t s, void *out) {
+    hipLaunchKernelGGL((k_defer_apply<double, RAT, NT>), dim3(grid), dim3(kBlasBlock), 0, s, st, h,
+                       static_cast<const double2 *>(ring), slot_elems, ptrs, n_shift, n, static_cast<double2 *>(out));
+}
+
 hipError_t launch_defer_pass(bool dbl, MsState *st, DeferHist *h, const void *ring, int64_t slot_elems, ShiftPtrs ptrs,
-                             int n_shift, int64_t n, int grid, hipStream_t s, void *out) {
+                             int n_shift, int64_t n, int grid, hipStream_t s, void *out, bool nt) {
     hipLaunchKernelGGL(k_defer_coef, dim3(1), dim3(kWave), 0, s, st, h);
-    if (out) {
-        if (!dbl) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_defer_apply<double, true>), dim3(grid), dim3(kBlasBlock), 0, s, (const MsState *)st, (const DeferHist *)h, static_cast<const double2 *>(ring), slot_elems, ptrs, n_shift, n, static_cast<double2 *>(out));
-    } else if (dbl) {
-        hipLaunchKernelGGL((k_defer_apply<double, false>), dim3(grid), dim3(kBlasBlock), 0, s, (const MsState *)st, (const DeferHist *)h, static_cast<const double2 *>(ring), slot_elems, ptrs, n_shift, n, (double2 *)nullptr);
+    if (out && !dbl) return hipErrorInvalidValue;
+    if (dbl) {
+        if (out) {
+            if (nt) defer_apply64<true, true>(st, h, ring, slot_elems, ptrs, n_shift, n, grid, s, out);
+            else defer_apply64<true, false>(st, h, ring, slot_elems, ptrs, n_shift, n, grid, s, out);
+        } else {
+            if (nt) defer_apply64<false, true>(st, h, ring, slot_elems, ptrs, n_shift, n, grid, s, nullptr);
+            else defer_apply64<false, false>(st, h, ring, slot_elems, ptrs, n_shift, n, grid, s, nullptr);
+        }
     } else {
-        hipLaunchKernelGGL((k_defer_apply<float, false>), dim3(grid), dim3(kBlasBlock), 0, s, (const MsState *)st, (const DeferHist *)h, static_cast<const float2 *>(ring), slot_elems, ptrs, n_shift, n, (float2 *)nullptr);
+        hipLaunchKernelGGL((k_defer_apply<float, false, false>), dim3(grid), dim3(kBlasBlock), 0, s, (const MsState *)st, (const DeferHist *)h, static_cast<const float2 *>(ring), slot_elems, ptrs, n_shift, n, (float2 *)nullptr);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_r_update_fused(bool dbl, MsState *st, const double *pq_part, int npq, const void *rin, void *r,
-                                 const void *ap, int64_t n, double *partial, int grid, hipStream_t s) {
-    if (dbl) hipLaunchKernelGGL(k_r_update_fused<double>, dim3(grid), dim3(kBlasBlock), 0, s, st, pq_part, npq, static_cast<const double2 *>(rin), static_cast<double2 *>(r), static_cast<const double2 *>(ap), n, partial);
-    else hipLaunchKernelGGL(k_r_update_fused<float>, dim3(grid), dim3(kBlasBlock), 0, s, st, pq_part, npq, static_cast<const float2 *>(rin), static_cast<float2 *>(r), static_cast<const float2 *>(ap), n, partial);
+                                 const void *ap, int64_t n, double *partial, int grid, hipStream_t s, bool nt) {
+    if (dbl && nt) hipLaunchKernelGGL((k_r_update_fused<double, true>), dim3(grid), dim3(kBlasBlock), 0, s, st, pq_part, npq, static_cast<const double2 *>(rin), static_cast<double2 *>(r), static_cast<const double2 *>(ap), n, partial);
+    else if (dbl) hipLaunchKernelGGL((k_r_update_fused<double, false>), dim3(grid), dim3(kBlasBlock), 0, s, st, pq_part, npq, static_cast<const double2 *>(rin), static_cast<double2 *>(r), static_cast<const double2 *>(ap), n, partial);
+    else hipLaunchKernelGGL((k_r_update_fused<float, false>), dim3(grid), dim3(kBlasBlock), 0, s, st, pq_part, npq, static_cast<const float2 *>(rin), static_cast<float2 *>(r), static_cast<const float2 *>(ap), n, partial);
     return hipGetLastError();
 }
 
 hipError_t launch_dir_update_fused(bool dbl, MsState *st, const double *r_part, int nr, const void *r, void *pd,
-                                   int64_t n, int grid, hipStream_t s) {
-    if (dbl) hipLaunchKernelGGL(k_dir_update_fused<double>, dim3(grid), dim3(kBlasBlock), 0, s, st, r_part, nr, static_cast<const double2 *>(r), static_cast<double2 *>(pd), n);
-    else hipLaunchKernelGGL(k_dir_update_fused<float>, dim3(grid), dim3(kBlasBlock), 0, s, st, r_part, nr, static_cast<const float2 *>(r), static_cast<float2 *>(pd), n);
+                                   int64_t n, int grid, hipStream_t s, bool nt) {
+    if (dbl && nt) hipLaunchKernelGGL((k_dir_update_fused<double, true>), dim3(grid), dim3(kBlasBlock), 0, s, st, r_part, nr, static_cast<const double2 *>(r), static_cast<double2 *>(pd), n);
+    else if (dbl) hipLaunchKernelGGL((k_dir_update_fused<double, false>), dim3(grid), dim3(kBlasBlock), 0, s, st, r_part, nr, static_cast<const double2 *>(r), static_cast<double2 *>(pd), n);
+    else hipLaunchKernelGGL((k_dir_update_fused<float, false>), dim3(grid), dim3(kBlasBlock), 0, s, st, r_part, nr, static_cast<const float2 *>(r), static_cast<float2 *>(pd), n);
     return hipGetLastError();
 }
 

@@ -149,6 +149,8 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
     DslashArgs a;
     std::memset(&a, 0, sizeof(a));
     a.g = lat->g;
+    a.link_cache = lat->link_cache;
+    const bool nt = dbl && lat->vec_stream;
 
     // r = b - A x in double precision (into rout if non-null), partials of
     // |r|^2 in `partial` (ds_grid of them)
@@ -209,10 +211,11 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
         STAG_HIP(launch_dslash(dbl, lat->nrow, DS_NORMAL_DOT, d, s));
         if (defer) {
             // the scalar steps ride in the two vector kernels (no tail launches)
-            STAG_HIP(launch_r_update_fused(dbl, st, part0, ds_grid, rslot(k - 1), rslot(k), AP, ne, part1, bl_grid, s));
-            STAG_HIP(launch_dir_update_fused(dbl, st, part1, bl_grid, rslot(k), pbase, ne, bl_grid, s));
+            STAG_HIP(launch_r_update_fused(dbl, st, part0, ds_grid, rslot(k - 1), rslot(k), AP, ne, part1, bl_grid, s,
+                                           nt));
+            STAG_HIP(launch_dir_update_fused(dbl, st, part1, bl_grid, rslot(k), pbase, ne, bl_grid, s, nt));
             if ((k + 1) % dlen == 0)
-                STAG_HIP(launch_defer_pass(dbl, st, hist, R, ne, it_ptrs, n, ne, bl_grid, s, sp.rat_out));
+                STAG_HIP(launch_defer_pass(dbl, st, hist, R, ne, it_ptrs, n, ne, bl_grid, s, sp.rat_out, nt));
         } else {
             STAG_HIP(launch_reduce_tail(st, part0, ds_grid, TAIL_ALPHA, 0, s));
             STAG_HIP(launch_r_update(dbl, st, rslot(k - 1), rslot(k), AP, ne, part1, bl_grid, s));
@@ -265,7 +268,7 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
 
     // ---------------------------------------------------------------- finish
     // the last block may end between passes (a no-op when it does not)
-    if (defer) STAG_HIP(launch_defer_pass(dbl, st, hist, R, ne, it_ptrs, n, ne, bl_grid, s, sp.rat_out));
+    if (defer) STAG_HIP(launch_defer_pass(dbl, st, hist, R, ne, it_ptrs, n, ne, bl_grid, s, sp.rat_out, nt));
     if (!dbl) STAG_HIP(launch_x_flush(st, hi_ptrs, lo_ptrs, n, ne, false, s));
     if (rat) {
         // no solutions are kept: report Re <src, out> instead of true residuals

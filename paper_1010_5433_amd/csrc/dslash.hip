@@ -50,11 +50,12 @@ __global__ void __launch_bounds__(kDslashBlock) k_dslash(DslashArgs a) {
             auto fetch = [&](int h) {
                 const int mu = h >> 1;
                 if (h & 1) {
-                    const int jb = site_nbr(a.g, i, x, mu, -1);
-                    rw = L8::load_raw(a.links, vh, (1 - p) * 4 + mu, jb);
+                    const int jb = site_nbr(a.g, i, x, mu, -1), bb = (1 - p) * 4 + mu;
+                    rw = L8::load_raw(a.links, vh, bb, jb, (a.link_cache >> bb) & 1);
                     vw = load_vec<R>(a.in, vh, jb);
                 } else {
-                    rw = L8::load_raw(a.links, vh, p * 4 + mu, i);
+                    const int bf = p * 4 + mu;
+                    rw = L8::load_raw(a.links, vh, bf, i, (a.link_cache >> bf) & 1);
                     vw = load_vec<R>(a.in, vh, site_nbr(a.g, i, x, mu, +1));
                 }
             };

@@ -72,6 +72,7 @@ struct DslashArgs {
     double c;            // m^2 + shift
     double *partial;     // per-block partial sums (dot modes)
     const int *skip;     // if non-null and *skip != 0 the launch does nothing
+    unsigned link_cache; // 8-real double precision links: bit b set = link block b read with ordinary loads
 };
 
 constexpr int kDslashBlock = 256;
@@ -128,6 +129,8 @@ struct stag_lattice {
     void *links64;
     void *links32;
     void *links16;       // bfloat16 12-real copy for the learned preconditioner (packed on first use)
+    unsigned link_cache; // link blocks the solver's double precision Dslash reads cached (link_cache_mask)
+    bool vec_stream;     // the solver's double precision vector kernels stream (nontemporal access)
     void *ws[WS_NSLOTS];
     size_t ws_bytes[WS_NSLOTS];
     int *host_flags;     // pinned host mirror of solver flags
@@ -139,5 +142,16 @@ namespace stag {
 stag_status ws_get(stag_lattice *lat, int slot, size_t bytes, void **out);
 
 inline int64_t vec_bytes(const stag_lattice *lat, bool dbl) { return (dbl ? 48 : 24) * lat->Vh; }
+
+// Infinity Cache residency of a double precision link field of `nrow` rows
+// (only the 8-real form, nrow = 1, gets any): the set of
+// its 8 link blocks (parity * 4 + mu) that the solver's Dslash reads with
+// ordinary loads, so that they stay in the 256 MB Infinity Cache from one
+// launch to the next.  A field within the budget is cached whole; a larger
+// one caches whole blocks in the order 0, 4, 1, 5, 2, 6, 3, 7 while they
+// fit, and streams the rest.  *stream tells whether the solver's vector
+// kernels should then stream too (a partly cached field), so that they do
+// not push those blocks out.
+unsigned link_cache_mask(int nrow, int64_t vh, bool *stream);
 
 }  // namespace stag

@@ -20,12 +20,16 @@
 // Staggered phases and boundary signs are never folded into the links: a
 // sign flip would leave det = -1 and break the third-row rebuild.
 //
-// Double precision links are read with nontemporal loads: a 32^4 field
-// (403-604 MB) cannot stay in the 256 MB Infinity Cache anyway, and keeping
-// the streamed links out of the L2 leaves room for the neighbour vectors
-// (measured 122 -> 115 us per 18-real half-Dslash at 32^4).  Single
-// precision fields (201-302 MB) partly live in the Infinity Cache, and
-// nontemporal loads measured slower there, so they use ordinary loads.
+// Double precision links are read with nontemporal loads by default: a 32^4
+// field (268-604 MB) cannot stay whole in the 256 MB Infinity Cache, and
+// keeping the streamed links out of the L2 leaves room for the neighbour
+// vectors (measured 122 -> 115 us per 18-real half-Dslash at 32^4).  For the
+// 8-real form the Dslash reads a chosen set of link blocks with ordinary
+// loads instead (`cached`): that part of the field, sized to fit the cache
+// next to the vectors, is then served from the Infinity Cache from one
+// launch to the next (see link_cache_mask).  Single precision fields
+// (201-302 MB) partly live in the Infinity Cache, and nontemporal loads
+// measured slower there, so they use ordinary loads.
 #pragma once
 
 #include "common.h"
@@ -203,8 +207,11 @@ template <> struct LinkLayout<double, 1> {
     // the stored words of one link; load_raw issues the loads, build rebuilds
     // (split so that a kernel can issue the next link's loads first)
     struct Raw { double2 a, d, c, t; };
-    __device__ static __forceinline__ Raw load_raw(const void *base, int64_t vh, int blk, int64_t i) {
+    __device__ static __forceinline__ Raw load_raw(const void *base, int64_t vh, int blk, int64_t i,
+                                                   bool cached = false) {
         const double2 *b = static_cast<const double2 *>(base) + (int64_t)blk * 4 * vh;
+        // `cached` is uniform over a launch: a branch, not a select of two loads
+        if (cached) return {b[0 * vh + i], b[1 * vh + i], b[2 * vh + i], b[3 * vh + i]};
         return {ld_nt(&b[0 * vh + i]), ld_nt(&b[1 * vh + i]), ld_nt(&b[2 * vh + i]), ld_nt(&b[3 * vh + i])};
     }
     __device__ static __forceinline__ su3<double> build(const Raw &w) {
@@ -214,8 +221,9 @@ template <> struct LinkLayout<double, 1> {
         rebuild8(u, cplx<double>{w.c.x, w.c.y}, w.t.x, w.t.y);
         return u;
     }
-    __device__ static __forceinline__ su3<double> load(const void *base, int64_t vh, int blk, int64_t i) {
-        return build(load_raw(base, vh, blk, i));
+    __device__ static __forceinline__ su3<double> load(const void *base, int64_t vh, int blk, int64_t i,
+                                                      bool cached = false) {
+        return build(load_raw(base, vh, blk, i, cached));
     }
     __device__ static __forceinline__ void store(void *base, int64_t vh, int blk, int64_t i, const su3<double> &u) {
         double2 *b = static_cast<double2 *>(base) + (int64_t)blk * 4 * vh;

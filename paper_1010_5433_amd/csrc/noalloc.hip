@@ -78,6 +78,7 @@ stag_status stag_normal_op_noalloc(stag_lattice *lat, double mass, double shift,
     std::memset(&a, 0, sizeof(a));
     a.g = lat->g;
     a.links = dbl ? lat->links64 : lat->links32;
+    a.link_cache = lat->link_cache;
     a.out_parity = 1;
     a.in = in;
     a.out = t;

@@ -92,18 +92,20 @@ hipError_t launch_r_update(bool dbl, MsState *st, const void *rin, void *r, cons
 // tail kernel) and block 0 also advances the recursion.
 //   r update: <p, A p> from pq_part (npq) -> alpha, zeta_i; r = rin - alpha A p; |r|^2 partials
 //   direction: |r|^2 from r_part (nr) -> beta, shift coefficients, freeze tests; pd = r + beta pd
+// nt (double precision): nontemporal vector loads and stores, for a lattice
+// whose Dslash keeps part of the link field in the Infinity Cache.
 hipError_t launch_r_update_fused(bool dbl, MsState *st, const double *pq_part, int npq, const void *rin, void *r,
-                                 const void *ap, int64_t n, double *partial, int grid, hipStream_t s);
+                                 const void *ap, int64_t n, double *partial, int grid, hipStream_t s, bool nt = false);
 hipError_t launch_dir_update_fused(bool dbl, MsState *st, const double *r_part, int nr, const void *r, void *pd,
-                                   int64_t n, int grid, hipStream_t s);
+                                   int64_t n, int grid, hipStream_t s, bool nt = false);
 // At the end of a block of deferred iterations: the coefficients and the
 // pass over every shift changed in it.  ring: one residual vector per
 // iteration of the block, slot m holding r^{k0+1+m}.
 // out == nullptr: x_i += ... for every shift; otherwise (rational
 // application, double precision) out += sum_i wgt_i (x_i increment) and no
-// x_i is kept.
+// x_i is kept.  nt as above.
 hipError_t launch_defer_pass(bool dbl, MsState *st, DeferHist *h, const void *ring, int64_t slot_elems, ShiftPtrs ptrs,
-                             int n_shift, int64_t n, int grid, hipStream_t s, void *out = nullptr);
+                             int n_shift, int64_t n, int grid, hipStream_t s, void *out = nullptr, bool nt = false);
 // out = c * b (double precision)
 hipError_t launch_scale(const double2 *b, double c, double2 *out, int64_t n, hipStream_t s);
 // partials of Re <a, b> (double precision), one per block of `grid`
