@@ -38,7 +38,7 @@ struct BDArgs {
     Geom g;
     const void *links;
     int nrhs;
-    int pad;
+    unsigned link_cache;         // 8-real double precision links: blocks read with ordinary loads
     const void *in[kMaxRpt];     // OE: p_base; EO: t
     void *out[kMaxRpt];          // OE: t; EO: ap
     const void *aux[kMaxRpt];    // EO: p_base; RESID: x
@@ -52,6 +52,17 @@ struct BDArgs {
 // OE: t = D_oe p; EO: q = c p - D_eo t with <p, q> partials; RESID: r = b - (c x - D_eo t)
 // with |r|^2 partials (double precision; r stored only where out is non-null)
 enum BDRole { BD_OE = 0, BD_EO = 1, BD_RESID = 2 };
+
+// Link `blk` of site i: the 8-real double precision field honours the
+// lattice's Infinity Cache blocks (link_cache_mask), the other layouts stream
+// or cache as their loads do.
+template <typename R, int NROW>
+__device__ __forceinline__ su3<R> bd_link(const BDArgs &a, int vh, int blk, int i) {
+    if constexpr (NROW == 1 && sizeof(R) == sizeof(double))
+        return LinkLayout<double, 1>::load(a.links, vh, blk, i, (a.link_cache >> blk) & 1);
+    else
+        return LinkLayout<R, NROW>::load(a.links, vh, blk, i);
+}
 
 // The multi-RHS half-Dslash of one workgroup: `tile` numbers the group of
 // blockDim.x consecutive output sites it covers.
@@ -82,12 +93,12 @@ __device__ __forceinline__ void bd_tile(const BDArgs &a, int tile) {
         auto hop = [&](int mu) {
             const int jf = site_nbr(a.g, i, x, mu, +1);
             const int jb = site_nbr(a.g, i, x, mu, -1);
-            const su3<R> uf = LinkLayout<R, NROW>::load(a.links, vh, p * 4 + mu, i);
+            const su3<R> uf = bd_link<R, NROW>(a, vh, p * 4 + mu, i);
             const R sf = R(fwd_sign(a.g, x, mu));
 #pragma unroll
             for (int r = 0; r < RPT; ++r)
                 if (live[r]) acc_mul(acc[r], sf, uf, load_vec<R>(a.in[r], vh, jf));
-            const su3<R> ub = LinkLayout<R, NROW>::load(a.links, vh, (1 - p) * 4 + mu, jb);
+            const su3<R> ub = bd_link<R, NROW>(a, vh, (1 - p) * 4 + mu, jb);
             const R sb = R(-bwd_sign(a.g, x, mu));
 #pragma unroll
             for (int r = 0; r < RPT; ++r)
@@ -446,6 +457,7 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
         std::memset(&d, 0, sizeof(d));
         d.g = lat->g;
         d.links = lat->links64;
+        d.link_cache = lat->link_cache;
         d.skip = skip;
         d.out_parity = 1;
         d.in = h_sys[k].xhi[i];
@@ -482,6 +494,7 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
         std::memset(&a, 0, sizeof(a));
         a.g = lats[l]->g;
         a.links = h_lat[l].links;
+        a.link_cache = dbl ? lats[l]->link_cache : 0u;
         a.nrhs = (int)grp.size();
         for (size_t r = 0; r < grp.size(); ++r) {
             const int k = grp[r];
@@ -793,6 +806,7 @@ stag_status run_batched(const BSpec *spec, int nsys, const BOptions &opt, BOut *
                 std::memset(&oe, 0, sizeof(oe));
                 oe.g = lats[l]->g;
                 oe.links = h_lat[l].links64;
+                oe.link_cache = lats[l]->link_cache;
                 oe.nrhs = (int)std::min<size_t>(8, in_round.size() - k0);
                 eo = oe;
                 for (int r = 0; r < oe.nrhs; ++r) {
