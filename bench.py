@@ -523,13 +523,14 @@ def learned_experiment(args, n_test_fields):
     t0 = time.perf_counter()
     losses = []
     lr = args.lr
-    for phase in range(3):   # step size lr, lr/3, lr/10
+    plateau = (args.plateau_window, args.plateau_rtol) if args.plateau_window > 0 else None
+    for phase in range(3):   # step size lr, lr/3, lr/10; each phase ends early at a plateau
         n = args.train_steps // 3 if phase < 2 else args.train_steps - 2 * (args.train_steps // 3)
-        losses += learn.train(net, data, n, args.batch, lr, seed=phase, log=log)
+        losses += learn.train(net, data, n, args.batch, lr, seed=phase, log=log, plateau=plateau)
         lr = args.lr / (3.0 if phase == 0 else 10.0)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    log(f"learned: {args.train_steps} Adam steps of {args.batch} pairs in {t_train:.1f} s, "
+    log(f"learned: {len(losses)} Adam steps (at most {args.train_steps}) of {args.batch} pairs in {t_train:.1f} s, "
         f"loss {losses[0]:.4f} -> {np.mean(losses[-20:]):.4f}")
     del data
     evals = []
@@ -562,7 +563,8 @@ def learned_experiment(args, n_test_fields):
             iteration_gain=round(float(np.mean([e["plain_iters"] / e[f"{mode}_iters"] for e in evals])), 3),
             tts_gain=round(float(np.mean([e["plain_seconds"] / e[f"{mode}_seconds"] for e in evals])), 3))
     return dict(train=dict(dims=list(c["train_dims"]), fields=nf, pairs_per_field=npairs, pairs=args.pairs,
-                           steps=args.train_steps, batch=args.batch, lr=args.lr, mode="bf16",
+                           steps=len(losses), max_steps=args.train_steps,
+                           plateau=list(plateau) if plateau else None, batch=args.batch, lr=args.lr, mode="bf16",
                            seconds=round(t_train, 2), data_seconds=round(t_data, 2),
                            loss_first=round(losses[0], 5), loss_last=round(float(np.mean(losses[-20:])), 5)),
                 test=dict(dims=list(c["test_dims"]), mass=mass, shift=0.0, tol=tol, links=f"{fmt}-real",
@@ -596,6 +598,10 @@ def main():
     ap.add_argument("--learned-only", action="store_true",
                     help="run only the learned-preconditioner experiment (all held-out fields)")
     ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--plateau-window", type=int, default=50,
+                    help="end a training phase once the mean loss of this many steps stops falling (0: never)")
+    ap.add_argument("--plateau-rtol", type=float, default=0.005,
+                    help="relative fall of the window mean below which a phase ends")
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-2)
     ap.add_argument("--init-scale", type=float, default=0.1)

@@ -273,11 +273,12 @@ class Lattice:
                                int(max_iter), _PREC[prec], ctypes.byref(st), _stream()), "stag_cg")
         return x, rc, st.to_dict(1)
 
-    def fcg_solve(self, mass, shift, src: torch.Tensor, x: torch.Tensor, net=None, mode="bf16", tol=1e-10,
+    def fcg_solve(self, mass, shift, src: torch.Tensor, x: torch.Tensor, net=None, mode="folded_bf16", tol=1e-10,
                   max_iter=100000):
         """Flexible CG for (M + shift) x = src preconditioned by `net` (a Net, or
-        None for plain double precision CG) evaluated in `mode` ("bf16",
-        "fp32", "folded" or "folded_bf16"), from the given x (overwritten)."""
+        None for plain double precision CG) evaluated in `mode` ("folded_bf16",
+        the fastest; "folded"; or the layered forms "bf16" and "fp32"), from
+        the given x (overwritten)."""
         st = CgStats()
         rc = _check(_L.stag_fcg_solve(self._h, float(mass), float(shift), _ptr(src), _ptr(x),
                                       net._h if net is not None else None, _MIX.get(mode, mode), float(tol),

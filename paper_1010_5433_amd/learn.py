@@ -99,10 +99,13 @@ def init_theta(seed: int, scale: float = 0.1):
     return scale * (rng.standard_normal(NET_NPARAM) + 1j * rng.standard_normal(NET_NPARAM))
 
 
-def train(net: Net, data, steps: int, batch: int, lr: float, mode="bf16", seed: int = 0, log=None):
+def train(net: Net, data, steps: int, batch: int, lr: float, mode="bf16", seed: int = 0, log=None,
+          plateau=None):
     """Adam on minibatches.  data: list of (Lattice, B, X); step k uses field
-    k mod len(data) and a minibatch drawn from its pairs.  Returns the loss
-    history (one value per step)."""
+    k mod len(data) and a minibatch drawn from its pairs.  plateau =
+    (window, rtol): stop early once the mean loss of the last `window` steps
+    is less than rtol (relative) below the mean of the window before it.
+    Returns the loss history (one value per step taken)."""
     gen = torch.Generator()
     gen.manual_seed(int(seed))
     losses = []
@@ -118,6 +121,13 @@ def train(net: Net, data, steps: int, batch: int, lr: float, mode="bf16", seed: 
         losses.append(net.train_step(lat, b, x, lr, mode))
         if log and (k + 1) % max(1, steps // 10) == 0:
             log(f"step {k + 1}/{steps} loss {losses[-1]:.5f} ({time.perf_counter() - t0:.1f} s)")
+        if plateau and (k + 1) % plateau[0] == 0 and k + 1 >= 2 * plateau[0]:
+            w = plateau[0]
+            cur, prev = sum(losses[-w:]) / w, sum(losses[-2 * w:-w]) / w
+            if prev - cur < plateau[1] * prev:
+                if log:
+                    log(f"plateau after {k + 1} steps: window mean {cur:.5f} against {prev:.5f}")
+                break
     return losses
 
 

@@ -370,10 +370,12 @@ def test_fcg_fallback_on_indefinite_preconditioner(orc):
     net = stag.Net(poly_theta(-1.0, 0.0))
     b = syn.gaussian_source(dims, 33)
     src = pack(lat, b)
-    x = torch.zeros_like(src)
-    _, rc, st = lat.fcg_solve(m, 0.0, src, x, net=net, tol=1e-10)
-    assert rc == 0 and st["fallback_used"] == 1
-    assert orc.true_residual(dims, U, m, 0.0, b, unpack(lat, x)) <= 1e-10
+    for mode in ("bf16", "folded_bf16", None):   # None: the binding's default mode
+        x = torch.zeros_like(src)
+        kw = {} if mode is None else dict(mode=mode)
+        _, rc, st = lat.fcg_solve(m, 0.0, src, x, net=net, tol=1e-10, **kw)
+        assert rc == 0 and st["fallback_used"] == 1, mode
+        assert orc.true_residual(dims, U, m, 0.0, b, unpack(lat, x)) <= 1e-10, mode
 
 
 def test_trained_network_gains_over_plain_cg(orc):
