@@ -747,9 +747,11 @@ def main():
                 kernel=kname, bytes_per_launch=algo, avg_launch_us=round(sec * 1e6, 2))
     # every precision and link format, for the record (same field, repacked)
     dsl = {}
+    loaded = args.fmt
     for fmt in ("8", "12", "18", "12p", "18p"):
-        if fmt != args.fmt:
+        if fmt != loaded:
             lat.set_links(torch.from_numpy(U).cuda(), fmt)
+            loaded = fmt
         for p in ("f64", "f32"):
             d = p == "f64"
             s = time_dslash(lat, p)
@@ -759,7 +761,8 @@ def main():
                                      link_field_MB=round(link_mb, 1),
                                      label=("effective (MALL-resident)" if link_mb < MALL_MB else "HBM"),
                                      traffic=read_traffic(f"k_dslash<{'double' if d else 'float'},{FMT_NROW[fmt]},PLAIN>"))
-    lat.set_links(torch.from_numpy(U).cuda(), args.fmt)
+    if loaded != args.fmt:
+        lat.set_links(torch.from_numpy(U).cuda(), args.fmt)
     log(f"dslash: {dsl}")
 
     if args.prec == "f64" and not args.no_force:
