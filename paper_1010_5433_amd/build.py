@@ -38,6 +38,9 @@ CFLAGS = [
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
     f"-I{os.path.join(ROOT, 'include')}",
 ]
+# roctx, for the named ranges of the solver phases in rocprofv3's marker trace
+ROCM_LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(HIPCC))), "lib")
+LDFLAGS = [f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}"]
 
 
 def _compile(src: str, extra) -> str:
@@ -91,7 +94,7 @@ def build(verbose: bool = False, extra=()) -> str:
         for h in hashes:
             kernels.update(h)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + LDFLAGS
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

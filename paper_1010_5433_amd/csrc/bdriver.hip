@@ -25,6 +25,7 @@ static stag_status status_of_ms(int ms) {
 // (systems on one lattice share link loads), repeated for the few that a
 // pass leaves above tol.
 stag_status refine_batched(const BSpec *spec, int nsys, const BOptions &opt, stag_cg_stats *stats, hipStream_t s) {
+    TraceRange tr("batched refinement");
     struct Item {
         int k, i;
     };
@@ -76,6 +77,7 @@ stag_status refine_batched(const BSpec *spec, int nsys, const BOptions &opt, sta
 stag_status rational_apply_multi(stag_lattice *lat, double mass, double alpha0, const double *alphas,
                                  const double *shifts, int n, const void *const *srcs, void *const *outs, int n_rhs,
                                  double tol, int max_iter, double *dots, stag_cg_stats *stats, hipStream_t s) {
+    TraceRange tr("rational function of M, several fields");
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<BSpec> spec(n_rhs);
     for (int k = 0; k < n_rhs; ++k) {
@@ -118,6 +120,7 @@ stag_status rational_apply_multi(stag_lattice *lat, double mass, double alpha0, 
 
 stag_status batched_solve(const BSpec *spec, int nsys, const BOptions &opt0, bool mixed, stag_cg_stats *stats,
                           hipStream_t s) {
+    TraceRange tr("batched multi-shift CG");
     const auto t0 = std::chrono::steady_clock::now();
     BOptions opt = opt0;
     std::vector<BOut> out(nsys);

@@ -68,6 +68,7 @@ static constexpr double kReliableDelta = 0.1;   // reliable update after |r| fel
 static constexpr int kReliableCheck = kDefer;   // iterations between reliable-update checks
 
 stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult *res, hipStream_t s) {
+    TraceRange tr(sp.dbl_iter ? "shifted CG, FP64 iterations" : "shifted CG, FP32 iterations");
     const int n = sp.n;
     const bool dbl = sp.dbl_iter;
     const int64_t ne = 3 * lat->Vh;  // complex entries per vector
@@ -345,6 +346,7 @@ static stag_status cg_refine(stag_lattice *lat, double mass, double shift, const
 stag_status multishift_cg(stag_lattice *lat, double mass, const double *shifts, int n, const void *src,
                           void *const *sols, double tol, int max_iter, stag_prec prec, stag_cg_stats *stats,
                           hipStream_t s) {
+    TraceRange tr("multi-shift CG");
     const auto t0 = std::chrono::steady_clock::now();
     ShiftedSolve sp;
     sp.mass = mass;
@@ -397,6 +399,7 @@ stag_status multishift_cg(stag_lattice *lat, double mass, const double *shifts, 
 stag_status rational_apply(stag_lattice *lat, double mass, double alpha0, const double *alphas, const double *shifts,
                            int n, const void *src, void *out, double tol, int max_iter, double *dot,
                            stag_cg_stats *stats, hipStream_t s) {
+    TraceRange tr("rational function of M");
     const auto t0 = std::chrono::steady_clock::now();
     ShiftedSolve sp;
     sp.mass = mass;

@@ -240,6 +240,7 @@ static constexpr int kFcgChunk = 8;   // iterations enqueued between reads of th
 
 stag_status fcg_solve(stag_lattice *lat, double mass, double shift, const void *src, void *sol, stag_net *net,
                       int mode, double tol, int max_iter, stag_cg_stats *stats, hipStream_t s) {
+    TraceRange tr("flexible CG");
     const auto t0 = std::chrono::steady_clock::now();
     stag_cg_stats st;
     std::memset(&st, 0, sizeof(st));

@@ -140,6 +140,7 @@ static hipError_t launch_force(int nrow, const ForceArgs &a, hipStream_t s) {
 // Z_i = D_oe X_i for every shift into a work buffer, then the force launch.  The caller has validated the arguments.
 stag_status fermion_force(stag_lattice *lat, int n, const double *alphas, const void *const *x, void *force,
                           hipStream_t s) {
+    TraceRange tr("pseudo-fermion force");
     void *z = nullptr;
     const int64_t vb = vec_bytes(lat, true);
     STAG_TRY(ws_get(lat, WS_FORCE, (size_t)(n > 0 ? n : 1) * vb, &z));

@@ -6,10 +6,22 @@
 
 #include <string>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "stag.h"
 #include "geom.h"
 
 namespace stag {
+
+// A named range of rocprofv3's marker trace (`--marker-trace`) over a scope:
+// the solver phases show up as ranges beside their kernels.  Without a tool
+// attached a push or pop is a call that returns at once.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string &msg);

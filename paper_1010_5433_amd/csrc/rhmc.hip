@@ -675,6 +675,7 @@ stag_status check_md_params(const stag_lattice *lat, const stag_rhmc_params *prm
 
 stag_status md_integrate(stag_lattice *lat, const stag_rhmc_params *prm, double *mom_canon, int n_pf,
                          const void *const *phis, stag_rhmc_info *info, hipStream_t s) {
+    TraceRange tr("molecular dynamics");
     const auto t0 = std::chrono::steady_clock::now();
     const bool dbl = prm->md_prec == STAG_F64;
     void *mom = nullptr;
@@ -689,6 +690,7 @@ stag_status md_integrate(stag_lattice *lat, const stag_rhmc_params *prm, double 
 
 stag_status rhmc_trajectory(stag_lattice *lat, const stag_rhmc_params *prm, double *mom_canon, int n_pf,
                             const void *const *xis, double u, stag_rhmc_info *info, hipStream_t s) {
+    TraceRange tr("RHMC trajectory");
     const auto t0 = std::chrono::steady_clock::now();
     const bool dbl = prm->md_prec == STAG_F64;
     const int64_t vb = vec_bytes(lat, true);
@@ -702,6 +704,7 @@ stag_status rhmc_trajectory(stag_lattice *lat, const stag_rhmc_params *prm, doub
     std::vector<const void *> phis(n_pf > 0 ? n_pf : 1);
     double sf0 = 0.0;
     for (int k = 0; k < n_pf; ++k) {
+        TraceRange trk("heatbath");
         void *phi = static_cast<char *>(phi_buf) + k * vb;
         phis[k] = phi;
         double dot = 0.0;
@@ -718,13 +721,17 @@ stag_status rhmc_trajectory(stag_lattice *lat, const stag_rhmc_params *prm, doub
     double k0 = 0.0, sg0 = 0.0;
     STAG_TRY(kinetic_energy(lat, dbl, mom, &k0, s));
     STAG_TRY(gauge_action(lat, prm->beta, &sg0, s));
-    STAG_TRY(md_run(lat, prm, mom, dbl, n_pf, phis.data(), info, s));
+    {
+        TraceRange trm("molecular dynamics");
+        STAG_TRY(md_run(lat, prm, mom, dbl, n_pf, phis.data(), info, s));
+    }
     double k1 = 0.0, sg1 = 0.0, sf1 = 0.0;
     STAG_TRY(kinetic_energy(lat, dbl, mom, &k1, s));
     STAG_TRY(gauge_action(lat, prm->beta, &sg1, s));
     void *scratch_out = nullptr;
     if (n_pf > 0) STAG_TRY(ws_get(lat, WS_MD_OUT, (size_t)vb, &scratch_out));
     for (int k = 0; k < n_pf; ++k) {
+        TraceRange trk("Metropolis action");
         double dot = 0.0;
         stag_cg_stats st;
         std::memset(&st, 0, sizeof(st));

@@ -135,6 +135,6 @@ def test_library_host_code_under_asan_and_ubsan(tmp_path):
     with cf.ThreadPoolExecutor(min(8, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(comp, srcs))
     lib = str(tmp_path / "libstag_san.so")
-    subprocess.run([B.HIPCC, "-shared", "-fPIC", f"--offload-arch={B.ARCH}", "-o", lib] + objs + HOST_SAN,
+    subprocess.run([B.HIPCC, "-shared", "-fPIC", f"--offload-arch={B.ARCH}", "-o", lib] + objs + HOST_SAN + B.LDFLAGS,
                    check=True, capture_output=True)
     _run_child(LIBRARY_CHILD, lib, rt[-1], tmp_path)
