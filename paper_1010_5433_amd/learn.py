@@ -93,6 +93,20 @@ def lambda_max(lat: Lattice, mass: float, iters: int = 60, seed: int = 99) -> fl
     return lam
 
 
+def save_params(path: str, net: Net, **meta):
+    """The network's parameters (and any scalar metadata, e.g. the training
+    loss) to an .npz file; read back with load_params (no pickled objects)."""
+    import numpy as np
+    np.savez(path, theta=net.get_params(), **{k: np.asarray(v) for k, v in meta.items()})
+
+
+def load_params(path: str) -> Net:
+    """A network with the parameters saved by save_params."""
+    import numpy as np
+    with np.load(path, allow_pickle=False) as f:
+        return Net(f["theta"])
+
+
 def init_theta(seed: int, scale: float = 0.1):
     import numpy as np
     rng = np.random.default_rng(seed)

@@ -402,3 +402,25 @@ def test_trained_network_gains_over_plain_cg(orc):
         assert res[mode]["resid_true"] <= 1e-10
         assert res[mode]["iters"] <= 0.8 * res["plain"]["iters"]
     assert losses[-1] < losses[0]
+
+
+def test_params_save_and_load(tmp_path):
+    """Checkpoint of trained weights: .npz round trip, the same parameters and
+    the same application."""
+    import numpy as np
+    import torch
+    import paper_1010_5433_amd as stag
+    from paper_1010_5433_amd import learn
+    dims = (4, 4, 4, 4)
+    U, lat = _setup(dims, "smooth", "18")
+    net = stag.Net(learn.init_theta(3))
+    path = str(tmp_path / "net.npz")
+    learn.save_params(path, net, loss=0.25)
+    back = learn.load_params(path)
+    assert np.array_equal(back.get_params(), net.get_params())
+    with np.load(path, allow_pickle=False) as f:
+        assert float(f["loss"]) == 0.25
+    r = torch.randn((3, lat.Vh, 2), dtype=torch.float32, device="cuda")
+    a, b = net.apply(lat, r, mode="fp32"), back.apply(lat, r, mode="fp32")
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
