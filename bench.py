@@ -163,6 +163,45 @@ def cpu_baseline(dims, U, b, mass, shifts, tol, one_core_iters=5):
                 iters=info["iters"], one_core_s_per_iter=round(dt1, 4))
 
 
+# The paper's Table 2: its single precision Dirac kernel on a Tesla C1060
+# (102 GB/s), 12-real links, on three lattices (N_t x N_s^3).
+PAPER_TAB2 = {(16, 16, 16, 4): 56.84, (32, 32, 32, 32): 64.091, (48, 48, 48, 4): 69.94}
+C1060_GBS = 102.0
+
+
+def tab2_experiment():
+    """The half-Dslash on the paper's three Table 2 lattices (4 x 16^3,
+    32 x 32^3, 4 x 48^3): single precision with 12-real links, the paper's
+    setting, and double precision with 8-real links, the solver's.  Bytes
+    are the algorithmic ones (all links once, the input and output vectors
+    once); the paper's GB/s and fraction of its GPU's peak stand beside,
+    as context."""
+    import torch
+
+    import paper_1010_5433_amd as stag
+    import stag_synth as syn
+
+    out = {}
+    for dims, paper_gbs in PAPER_TAB2.items():
+        U = torch.from_numpy(syn.smooth_links(dims, 0.5, 11)).cuda()
+        lat = stag.Lattice(dims)
+        row = {}
+        for fmt, prec in (("12", "f32"), ("8", "f64")):
+            lat.set_links(U, fmt)
+            s = time_dslash(lat, prec)
+            dbl = prec == "f64"
+            gbs = dslash_bytes_per_site(dbl, FMT_NROW[fmt]) * lat.Vh / s / 1e9
+            link_mb = link_field_bytes(dbl, FMT_NROW[fmt], lat.Vh) / 1e6
+            row[f"{prec}_{fmt}"] = dict(us=round(s * 1e6, 2), GBs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4),
+                                        link_field_MB=round(link_mb, 1),
+                                        label=("effective (MALL-resident)" if link_mb < MALL_MB else "HBM"))
+        row["paper_f32_12"] = dict(GBs=paper_gbs, frac=round(paper_gbs / C1060_GBS, 4), gpu="Tesla C1060")
+        out["x".join(str(d) for d in dims)] = row
+        del lat, U
+    log(f"paper Table 2 lattices: {out}")
+    return out
+
+
 def config2_experiment(fmt):
     """Time to solution of the 32^3x8 workload (m = 0.02, 12 shifts in
     [1e-5, 2], FP64) on the GPU and with the FP64 oracle on the host cores,
@@ -581,6 +620,8 @@ def main():
     ap.add_argument("--fmt", default="8", choices=["18", "12", "8", "18p", "12p"])
     ap.add_argument("--cpu-one-core-iters", type=int, default=5)
     ap.add_argument("--no-config2", action="store_true", help="skip the 32^3x8 GPU/oracle comparison")
+    ap.add_argument("--no-tab2", action="store_true", help="skip the half-Dslash on the paper's Table 2 lattices")
+    ap.add_argument("--tab2-only", action="store_true", help="run only the paper's Table 2 lattices")
     ap.add_argument("--no-rhmc", action="store_true", help="skip the 16^4 RHMC trajectory")
     ap.add_argument("--rhmc-only", action="store_true", help="run only the RHMC trajectory experiment")
     ap.add_argument("--learned-test-fields", type=int, default=4,
@@ -634,6 +675,10 @@ def main():
     if args.rhmc_only:
         torch.cuda.set_device(0)
         print(json.dumps({"rhmc": rhmc_experiment()}), flush=True)
+        return
+    if args.tab2_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"tab2": tab2_experiment()}), flush=True)
         return
     if args.learned_only:
         torch.cuda.set_device(0)
@@ -776,6 +821,8 @@ def main():
         extra["learned"] = learned_experiment(args, args.learned_test_fields)
     if not args.no_config2:
         extra["config2"] = config2_experiment(args.fmt)
+    if not args.no_tab2:
+        extra["tab2"] = tab2_experiment()
     if not args.no_rhmc:
         extra["rhmc"] = rhmc_experiment()
 
