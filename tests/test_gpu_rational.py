@@ -30,7 +30,10 @@ def _bound(b, mass, alphas, shifts, tol):
 
 CASES = [((4, 4, 4, 4), "haar", "18", 0.1, 11), ((4, 4, 2, 6), "smooth", "12", 0.05, 12),
          ((8, 8, 8, 8), "smooth", "8", 0.02, 13), ((6, 4, 2, 8), "haar", "18", 0.2, 14),
-         ((4, 4, 2, 6), "smooth", "12p", 0.05, 15)]
+         ((4, 4, 2, 6), "smooth", "12p", 0.05, 15),
+         # 32^4 with 8-real links: part of the field kept in the Infinity Cache and the
+         # vector kernels (the weighted sums of the deferred passes) streaming
+         ((32, 32, 32, 32), "smooth", "8", 0.05, 16)]
 
 
 @pytest.mark.parametrize("dims,kind,fmt,mass,seed", CASES)
