@@ -137,22 +137,20 @@ static hipError_t launch_force(int nrow, const ForceArgs &a, hipStream_t s) {
     }
 }
 
-// Z_i = D_oe X_i for every shift into a work buffer, then the force launch.  The caller has validated the arguments.
+// Workgroup size of the multi-right-hand-side D_oe that makes the Z_i.
+constexpr int kZBlock = 128;
+
+// Z_i = D_oe X_i for every shift into a work buffer (eight vectors per
+// launch), then the force launch.  The caller has validated the arguments.
 stag_status fermion_force(stag_lattice *lat, int n, const double *alphas, const void *const *x, void *force,
                           hipStream_t s) {
     TraceRange tr("pseudo-fermion force");
     void *z = nullptr;
     const int64_t vb = vec_bytes(lat, true);
     STAG_TRY(ws_get(lat, WS_FORCE, (size_t)(n > 0 ? n : 1) * vb, &z));
-    for (int i = 0; i < n; ++i) {
-        DslashArgs d{};
-        d.g = lat->g;
-        d.out_parity = 1;
-        d.links = lat->links64;
-        d.in = x[i];
-        d.out = static_cast<char *>(z) + i * vb;
-        STAG_HIP(launch_dslash(true, lat->nrow, DS_PLAIN, d, s));
-    }
+    void *zs[kMaxShifts];
+    for (int i = 0; i < n; ++i) zs[i] = static_cast<char *>(z) + i * vb;
+    STAG_HIP(launch_dslash_oe_multi(lat, n, x, zs, kZBlock, s));
     ForceArgs a{};
     a.g = lat->g;
     a.n = n;

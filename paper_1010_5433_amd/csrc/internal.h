@@ -90,6 +90,11 @@ struct DslashArgs {
 constexpr int kDslashBlock = 256;
 int dslash_grid(const Geom &g, int block);
 hipError_t launch_dslash(bool dbl, int nrow, int mode, const DslashArgs &a, hipStream_t s);
+// D_oe in double precision of n even-site vectors of `lat`, up to 8 per
+// launch of the multi-right-hand-side half-Dslash (the links read once for
+// all of them); block: 64, 128 or 256 sites per workgroup.
+hipError_t launch_dslash_oe_multi(const stag_lattice *lat, int n, const void *const *in, void *const *out, int block,
+                                  hipStream_t s);
 
 hipError_t launch_pack_links(const Geom &g, const void *canon, void *dst, bool dbl, int nrow, hipStream_t s);
 // bfloat16 12-real copy from a packed single precision field of any format
