@@ -270,6 +270,35 @@ hipError_t launch_dslash_oe_multi(const stag_lattice *lat, int n, const void *co
     return hipSuccess;
 }
 
+hipError_t launch_true_resid_multi(const stag_lattice *lat, int n, const void *const *x, const double *c,
+                                   const void *b, void *const *t, double *const *part, int block, hipStream_t s) {
+    const int nchunk = (int)((lat->Vh + kWave - 1) / kWave);
+    for (int k0 = 0; k0 < n; k0 += kMaxRpt) {
+        BDArgs oe;
+        std::memset(&oe, 0, sizeof(oe));
+        oe.g = lat->g;
+        oe.links = lat->links64;
+        oe.link_cache = lat->link_cache;
+        oe.nrhs = n - k0 < kMaxRpt ? n - k0 : kMaxRpt;
+        BDArgs rs = oe;
+        for (int r = 0; r < oe.nrhs; ++r) {
+            oe.in[r] = x[k0 + r];
+            oe.out[r] = t[r];
+            rs.in[r] = t[r];
+            rs.aux[r] = x[k0 + r];
+            rs.rhs[r] = b;
+            rs.c[r] = c[k0 + r];
+            rs.part[r] = part[k0 + r];
+            rs.nchunk[r] = nchunk;
+        }
+        const BDslashCfg cfg = {block, oe.nrhs > 4 ? 8 : oe.nrhs > 2 ? 4 : oe.nrhs > 1 ? 2 : 1};
+        hipError_t e = bd_launch(true, lat->nrow, BD_OE, cfg, oe, s);
+        if (e == hipSuccess) e = bd_launch(true, lat->nrow, BD_RESID, cfg, rs, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // ---------------------------------------------------------------- launch-shape cache
 
 static std::mutex g_tune_mu;

@@ -64,6 +64,7 @@ struct ShiftedResult {
 };
 
 static constexpr int kChunk = 8;   // iterations enqueued between flag reads
+static constexpr int kTresBlock = 128;   // sites per workgroup of the final true-residual launches
 static constexpr double kReliableDelta = 0.1;   // reliable update after |r| fell 10x
 static constexpr int kReliableCheck = kDefer;   // iterations between reliable-update checks
 
@@ -276,11 +277,26 @@ stag_status run_shifted(stag_lattice *lat, const ShiftedSolve &sp, ShiftedResult
         STAG_HIP(launch_dot_re(static_cast<const double2 *>(sp.src), static_cast<const double2 *>(sp.rat_out), ne,
                                part0, bl_grid, s));
         STAG_HIP(launch_reduce_tail(st, part0, bl_grid, TAIL_SCRATCH, 0, s));
-    } else {
+    } else if (n > 1) {
+        // every shift's true residual, eight per multi-right-hand-side launch pair
+        const int nchunk = (int)((lat->Vh + kWave - 1) / kWave);
+        const int ng = n < kMaxRpt ? n : kMaxRpt;
+        void *tres = nullptr;
+        STAG_TRY(ws_get(lat, WS_TRES, vb64 * ng + sizeof(double) * (size_t)nchunk * n, &tres));
+        void *tb[kMaxRpt];
+        double *pp[kMaxShifts];
+        double cc[kMaxShifts];
+        for (int r = 0; r < ng; ++r) tb[r] = static_cast<char *>(tres) + vb64 * r;
         for (int i = 0; i < n; ++i) {
-            STAG_HIP(true_residual(sp.x_hi[i], sp.shifts[i], nullptr, part0, nullptr));
-            STAG_HIP(launch_reduce_tail(st, part0, ds_grid, TAIL_TRUE_RESID, i, s));
+            pp[i] = reinterpret_cast<double *>(static_cast<char *>(tres) + vb64 * ng) + (size_t)nchunk * i;
+            cc[i] = m2 + sp.shifts[i];
         }
+        STAG_HIP(launch_true_resid_multi(lat, n, reinterpret_cast<const void *const *>(sp.x_hi), cc, sp.src, tb, pp,
+                                         kTresBlock, s));
+        for (int i = 0; i < n; ++i) STAG_HIP(launch_reduce_tail(st, pp[i], nchunk, TAIL_TRUE_RESID, i, s));
+    } else {
+        STAG_HIP(true_residual(sp.x_hi[0], sp.shifts[0], nullptr, part0, nullptr));
+        STAG_HIP(launch_reduce_tail(st, part0, ds_grid, TAIL_TRUE_RESID, 0, s));
     }
     STAG_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
     STAG_HIP(hipStreamSynchronize(s));

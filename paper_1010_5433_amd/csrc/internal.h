@@ -95,6 +95,13 @@ hipError_t launch_dslash(bool dbl, int nrow, int mode, const DslashArgs &a, hipS
 // all of them); block: 64, 128 or 256 sites per workgroup.
 hipError_t launch_dslash_oe_multi(const stag_lattice *lat, int n, const void *const *in, void *const *out, int block,
                                   hipStream_t s);
+// The double precision true residuals r_i = b - (M + shift_i) x_i of n
+// solutions, eight per launch pair: t_r = D_oe x_r into t[r] (8 odd-site
+// vectors), then r_i = b - (c[i] x_i - D_eo t_r) with c[i] = m^2 + shift_i
+// and one partial of |r_i|^2 per 64 consecutive sites into part[i]
+// (ceil(V/2 / 64) of them); r_i itself is not stored.
+hipError_t launch_true_resid_multi(const stag_lattice *lat, int n, const void *const *x, const double *c,
+                                   const void *b, void *const *t, double *const *part, int block, hipStream_t s);
 
 hipError_t launch_pack_links(const Geom &g, const void *canon, void *dst, bool dbl, int nrow, hipStream_t s);
 // bfloat16 12-real copy from a packed single precision field of any format
@@ -126,6 +133,7 @@ enum WsSlot {
     WS_STATE,      // solver scalar state
     WS_BATCH,      // arena of the batched solver
     WS_FORCE,      // odd-site vectors D_oe X_i of the fermion force
+    WS_TRES,       // odd-site temporaries and partials of the final true residuals
     WS_MD_MOM,     // momenta of the molecular dynamics (library layout)
     WS_MD_SOLS,    // multi-shift solutions of the molecular-dynamics force
     WS_MD_FORCE,   // pseudo-fermion force (4, V, 3, 3)
