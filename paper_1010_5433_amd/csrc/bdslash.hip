@@ -248,17 +248,18 @@ static hipError_t bdm_launch(bool dbl, int nrow, int role, BDslashCfg cfg, const
                      : bdm_launch_nrow<float, 3>(role, cfg, groups, m, s);
 }
 
-// D_oe of n double precision even-site vectors of one lattice, up to 8 per
-// launch (the links read once for all of them).
+// D_oe of n double precision even-site vectors of one lattice, rpt (1, 2,
+// 4 or 8) per launch (the links read once for all of them).
 hipError_t launch_dslash_oe_multi(const stag_lattice *lat, int n, const void *const *in, void *const *out, int block,
-                                  hipStream_t s) {
-    for (int k0 = 0; k0 < n; k0 += kMaxRpt) {
+                                  int rpt, hipStream_t s) {
+    if (rpt != 1 && rpt != 2 && rpt != 4 && rpt != 8) return hipErrorInvalidValue;
+    for (int k0 = 0; k0 < n; k0 += rpt) {
         BDArgs a;
         std::memset(&a, 0, sizeof(a));
         a.g = lat->g;
         a.links = lat->links64;
         a.link_cache = lat->link_cache;
-        a.nrhs = n - k0 < kMaxRpt ? n - k0 : kMaxRpt;
+        a.nrhs = n - k0 < rpt ? n - k0 : rpt;
         for (int r = 0; r < a.nrhs; ++r) {
             a.in[r] = in[k0 + r];
             a.out[r] = out[k0 + r];

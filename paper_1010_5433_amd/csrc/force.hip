@@ -137,8 +137,9 @@ static hipError_t launch_force(int nrow, const ForceArgs &a, hipStream_t s) {
     }
 }
 
-// Workgroup size of the multi-right-hand-side D_oe that makes the Z_i.
+// Launch shape of the multi-right-hand-side D_oe that makes the Z_i.
 constexpr int kZBlock = 128;
+constexpr int kZRpt = 8;
 
 // Z_i = D_oe X_i for every shift into a work buffer (eight vectors per
 // launch), then the force launch.  The caller has validated the arguments.
@@ -150,7 +151,7 @@ stag_status fermion_force(stag_lattice *lat, int n, const double *alphas, const 
     STAG_TRY(ws_get(lat, WS_FORCE, (size_t)(n > 0 ? n : 1) * vb, &z));
     void *zs[kMaxShifts];
     for (int i = 0; i < n; ++i) zs[i] = static_cast<char *>(z) + i * vb;
-    STAG_HIP(launch_dslash_oe_multi(lat, n, x, zs, kZBlock, s));
+    STAG_HIP(launch_dslash_oe_multi(lat, n, x, zs, kZBlock, kZRpt, s));
     ForceArgs a{};
     a.g = lat->g;
     a.n = n;

@@ -90,11 +90,11 @@ struct DslashArgs {
 constexpr int kDslashBlock = 256;
 int dslash_grid(const Geom &g, int block);
 hipError_t launch_dslash(bool dbl, int nrow, int mode, const DslashArgs &a, hipStream_t s);
-// D_oe in double precision of n even-site vectors of `lat`, up to 8 per
-// launch of the multi-right-hand-side half-Dslash (the links read once for
-// all of them); block: 64, 128 or 256 sites per workgroup.
+// D_oe in double precision of n even-site vectors of `lat`, rpt (1, 2, 4
+// or 8) per launch of the multi-right-hand-side half-Dslash (the links read
+// once for all of them); block: 64, 128 or 256 sites per workgroup.
 hipError_t launch_dslash_oe_multi(const stag_lattice *lat, int n, const void *const *in, void *const *out, int block,
-                                  hipStream_t s);
+                                  int rpt, hipStream_t s);
 // The double precision true residuals r_i = b - (M + shift_i) x_i of n
 // solutions, eight per launch pair: t_r = D_oe x_r into t[r] (8 odd-site
 // vectors), then r_i = b - (c[i] x_i - D_eo t_r) with c[i] = m^2 + shift_i
