@@ -38,6 +38,7 @@
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "internal.h"
 #include "links.h"
 #include "solver.h"
@@ -580,17 +581,41 @@ static stag_status md_run(stag_lattice *lat, const stag_rhmc_params *prm, void *
                           const void *const *phis, stag_rhmc_info *info, hipStream_t s) {
     const int nr = prm->rat_md.n;
     const int64_t vb = vec_bytes(lat, true);
+    // several pseudo-fermion fields: their solves in one batched call and one
+    // force over all their solutions (the force is linear in them), while
+    // the solutions fit the force's limit of shifts
+    const bool batch = n_pf > 1 && n_pf * nr <= kMaxShifts;
+    const int nsol = batch ? n_pf * nr : nr;
     void *sols_buf = nullptr, *force = nullptr;
     if (n_pf > 0) {
-        STAG_TRY(ws_get(lat, WS_MD_SOLS, (size_t)nr * vb, &sols_buf));
+        STAG_TRY(ws_get(lat, WS_MD_SOLS, (size_t)(nsol > 0 ? nsol : 1) * vb, &sols_buf));
         STAG_TRY(ws_get(lat, WS_MD_FORCE, (size_t)576 * lat->V, &force));
     }
-    std::vector<void *> sols(nr > 0 ? nr : 1);
-    for (int k = 0; k < nr; ++k) sols[k] = static_cast<char *>(sols_buf) + k * vb;
+    std::vector<void *> sols(nsol > 0 ? nsol : 1);
+    for (int k = 0; k < nsol; ++k) sols[k] = static_cast<char *>(sols_buf) + k * vb;
+    std::vector<double> alphas_all;
+    for (int k = 0; batch && k < n_pf; ++k)
+        alphas_all.insert(alphas_all.end(), prm->rat_md.alpha, prm->rat_md.alpha + nr);
     const stag_prec solve_prec = dbl ? STAG_F64 : STAG_F32;
     double pend_g = 0.0, pend_f = 0.0;
     auto flush = [&]() -> stag_status {
-        if (pend_f != 0.0 && n_pf > 0) {
+        if (pend_f != 0.0 && batch) {
+            std::vector<BSpec> spec(n_pf);
+            for (int k = 0; k < n_pf; ++k)
+                spec[k] = {lat, prm->mass, nr, prm->rat_md.shift, phis[k], sols.data() + k * nr, false};
+            BOptions opt{};
+            opt.tol = prm->tol_md;
+            opt.max_iter = prm->max_iter;
+            opt.dbl = dbl;
+            opt.reliable_every = 0;
+            std::vector<stag_cg_stats> st(n_pf);
+            const stag_status rc = batched_solve(spec.data(), n_pf, opt, false, st.data(), s);
+            for (int k = 0; k < n_pf; ++k) info->md_iters += st[k].iters;
+            if (rc != STAG_OK) return rc;
+            STAG_TRY(fermion_force(lat, nsol, alphas_all.data(), sols.data(), force, s));
+            STAG_HIP(launch_force_kick(lat, dbl, force, pend_f, mom, s));
+            info->fermion_forces += 1;
+        } else if (pend_f != 0.0 && n_pf > 0) {
             for (int k = 0; k < n_pf; ++k) {
                 stag_cg_stats st;
                 std::memset(&st, 0, sizeof(st));
