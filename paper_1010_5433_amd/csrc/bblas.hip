@@ -89,9 +89,7 @@ __global__ void __launch_bounds__(kBBlock) kb_vec(BView v, int op, int it) {
         R alpha;
         if (op == BV_R_UPDATE_FUSED) {
             __shared__ double red[kBBlock / kWave];
-            double t = 0.0;
-            for (int k = threadIdx.x; k < s.nchunk_ds; k += kBBlock) t += s.part_ds[k];
-            const double pap = block_sum(t, red);
+            const double pap = block_sum(part_sum<kBBlock>(s.part_ds, s.nchunk_ds), red);
             if (blockIdx.x == 0) {
                 if (threadIdx.x == 0) st->rho_snap = st->rho;
                 ms_alpha_step(st, pap);
@@ -123,9 +121,7 @@ __global__ void __launch_bounds__(kBBlock) kb_vec(BView v, int op, int it) {
         R beta;
         if (op == BV_DIR_FUSED) {
             __shared__ double red[kBBlock / kWave];
-            double t = 0.0;
-            for (int k = threadIdx.x; k < s.nchunk_bl; k += kBBlock) t += s.part_bl[k];
-            const double rho_new = block_sum(t, red);
+            const double rho_new = block_sum(part_sum<kBBlock>(s.part_bl, s.nchunk_bl), red);
             beta = R(rho_new / st->rho_snap);   // block 0 rewrites rho below, not rho_snap
             if (blockIdx.x == 0) ms_beta_step(st, rho_new);
         } else {
@@ -255,9 +251,7 @@ __global__ void __launch_bounds__(kBTailBlock) kb_tail(BView v, int kind, int id
     MsState *st = s.st;
     if (kind == BT_TRUE_RESID) {
         if (s.rat || idx >= s.n) return;
-        double t = 0.0;
-        for (int k = threadIdx.x; k < s.nchunk_ds; k += kBTailBlock) t += s.part_ds[k];
-        const double total = block_sum(t, red);
+        const double total = block_sum(part_sum<kBTailBlock>(s.part_ds, s.nchunk_ds), red);
         if (threadIdx.x == 0) st->resid_true[idx] = st->bnorm2 > 0.0 ? sqrt(total / st->bnorm2) : sqrt(total);
         return;
     }
@@ -269,9 +263,7 @@ __global__ void __launch_bounds__(kBTailBlock) kb_tail(BView v, int kind, int id
     const bool use_ds = kind == BT_ALPHA;
     const double *part = use_ds ? s.part_ds : s.part_bl;
     const int np = use_ds ? s.nchunk_ds : s.nchunk_bl;
-    double t = 0.0;
-    for (int k = threadIdx.x; k < np; k += kBTailBlock) t += part[k];
-    const double total = block_sum(t, red);
+    const double total = block_sum(part_sum<kBTailBlock>(part, np), red);
     if (kind == BT_INIT) ms_init_step(st, total, total);   // zero start: r = b
     else if (kind == BT_ALPHA) ms_alpha_step(st, total);
     else ms_beta_step(st, total);

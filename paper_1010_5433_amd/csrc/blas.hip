@@ -31,9 +31,7 @@ int blas_grid(int64_t n) {
 
 // Sum of nparts partials by one wave (blockDim.x == 64), fixed order.
 __device__ __forceinline__ double sum_partials(const double *part, int nparts) {
-    double s = 0.0;
-    for (int k = threadIdx.x; k < nparts; k += kWave) s += part[k];
-    return wave_sum(s);
+    return wave_sum(part_sum<kWave>(part, nparts));
 }
 
 template <typename R> using T2 = typename vtype<R>::t2;
@@ -146,15 +144,32 @@ __global__ void __launch_bounds__(kBlasBlock) k_shift_update(const MsState *st, 
 
 // Fused forms (see solver.h).  Every block reduces the partials in the order
 // of k_reduce_tail (threads stride kBlasBlock, then block_sum), so alpha and
-// beta equal the tail kernel's bit for bit.
+// beta equal the tail kernel's bit for bit.  A thread loads its first group
+// of partials, then the vectors of its first kPrefetch grid-stride trips,
+// before it adds anything, so that all those memory latencies overlap.
+constexpr int kPrefetch = 4;
+
 template <typename R, bool NT>
 __global__ void __launch_bounds__(kBlasBlock) k_r_update_fused(MsState *st, const double *pq_part, int npq,
                                                             const T2<R> *rin, T2<R> *r, const T2<R> *ap, int64_t n,
                                                             double *partial) {
     if (st->done) return;
     __shared__ double red[kBlasBlock / kWave];
-    double t = 0.0;
-    for (int k = threadIdx.x; k < npq; k += kBlasBlock) t += pq_part[k];
+    double pre[kPartGroup];
+    part_load_group<kBlasBlock>(pq_part, npq, threadIdx.x, pre);
+    const int64_t j0 = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kBlasBlock;
+    T2<R> rv[kPrefetch], q[kPrefetch];
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+        const int64_t j = j0 + u * stride;
+        if (j < n) {
+            rv[u] = ldv<NT>(&rin[j]);
+            q[u] = ldv<NT>(&ap[j]);
+        }
+    }
+    double t = part_add_group<kBlasBlock>(0.0, npq, threadIdx.x, pre);
+    t = part_sum_from<kBlasBlock>(t, pq_part, npq, threadIdx.x + kPartGroup * kBlasBlock);
     const double pap = block_sum(t, red);
     const bool bad = !(pap > 0.0) || !isfinite(pap);
     if (blockIdx.x == 0) {
@@ -164,13 +179,23 @@ __global__ void __launch_bounds__(kBlasBlock) k_r_update_fused(MsState *st, cons
     if (bad) return;
     const R alpha = R(st->rho / pap);   // rho is not written by this kernel
     double part = 0.0;
-    for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
-        T2<R> rv = ldv<NT>(&rin[j]);
-        const T2<R> q = ldv<NT>(&ap[j]);
-        rv.x -= alpha * q.x;
-        rv.y -= alpha * q.y;
-        stv<NT>(&r[j], rv);
-        part += abs2<R>(rv);
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+        const int64_t j = j0 + u * stride;
+        if (j < n) {
+            rv[u].x -= alpha * q[u].x;
+            rv[u].y -= alpha * q[u].y;
+            stv<NT>(&r[j], rv[u]);
+            part += abs2<R>(rv[u]);
+        }
+    }
+    for (int64_t j = j0 + kPrefetch * stride; j < n; j += stride) {
+        T2<R> v = ldv<NT>(&rin[j]);
+        const T2<R> w = ldv<NT>(&ap[j]);
+        v.x -= alpha * w.x;
+        v.y -= alpha * w.y;
+        stv<NT>(&r[j], v);
+        part += abs2<R>(v);
     }
     const double s = block_sum(part, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -181,17 +206,39 @@ __global__ void __launch_bounds__(kBlasBlock) k_dir_update_fused(MsState *st, co
                                                               const T2<R> *r, T2<R> *pd, int64_t n) {
     if (st->done) return;
     __shared__ double red[kBlasBlock / kWave];
-    double t = 0.0;
-    for (int k = threadIdx.x; k < nr; k += kBlasBlock) t += r_part[k];
+    double pre[kPartGroup];
+    part_load_group<kBlasBlock>(r_part, nr, threadIdx.x, pre);
+    const int64_t j0 = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kBlasBlock;
+    T2<R> rv[kPrefetch], pv[kPrefetch];
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+        const int64_t j = j0 + u * stride;
+        if (j < n) {
+            rv[u] = ldv<NT>(&r[j]);
+            pv[u] = ldv<NT>(&pd[j]);
+        }
+    }
+    double t = part_add_group<kBlasBlock>(0.0, nr, threadIdx.x, pre);
+    t = part_sum_from<kBlasBlock>(t, r_part, nr, threadIdx.x + kPartGroup * kBlasBlock);
     const double rho_new = block_sum(t, red);
     const R beta = R(rho_new / st->rho_snap);   // block 0 rewrites rho below, not rho_snap
     if (blockIdx.x == 0) ms_beta_step(st, rho_new);
-    for (int64_t j = (int64_t)blockIdx.x * kBlasBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlasBlock) {
-        const T2<R> rv = ldv<NT>(&r[j]);
-        T2<R> pv = ldv<NT>(&pd[j]);
-        pv.x = rv.x + beta * pv.x;
-        pv.y = rv.y + beta * pv.y;
-        stv<NT>(&pd[j], pv);
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+        const int64_t j = j0 + u * stride;
+        if (j < n) {
+            pv[u].x = rv[u].x + beta * pv[u].x;
+            pv[u].y = rv[u].y + beta * pv[u].y;
+            stv<NT>(&pd[j], pv[u]);
+        }
+    }
+    for (int64_t j = j0 + kPrefetch * stride; j < n; j += stride) {
+        const T2<R> v = ldv<NT>(&r[j]);
+        T2<R> w = ldv<NT>(&pd[j]);
+        w.x = v.x + beta * w.x;
+        w.y = v.y + beta * w.y;
+        stv<NT>(&pd[j], w);
     }
 }
 
@@ -320,9 +367,7 @@ __global__ void __launch_bounds__(kTailBlock) k_reduce_tail(MsState *st, const d
     }
     if (kind == TAIL_BETA && st->done) return;
     if (kind == TAIL_RELIABLE && st->rel_skip) return;
-    double t = 0.0;
-    for (int k = threadIdx.x; k < nparts; k += kTailBlock) t += partial[k];
-    const double total = block_sum(t, red);
+    const double total = block_sum(part_sum<kTailBlock>(partial, nparts), red);
     if (kind == TAIL_ALPHA) {
         if (threadIdx.x == 0) st->upd_valid = 0;
         ms_alpha_step(st, total);

@@ -168,4 +168,42 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
     return s;
 }
 
+// Per-thread part of a fixed-order sum of reduction partials: t = part[k]
+// for k = threadIdx.x, threadIdx.x + B, ... < n, added in that order (B =
+// the threads that share the sum).  The loads go out in groups of
+// kPartGroup, all of a group before its first addition: a loop that adds
+// each partial as it arrives waits for the loads one after another.  The
+// index is clamped instead of branched on, so that no branch ties an
+// addition to its load.
+constexpr int kPartGroup = 8;
+
+template <int B>
+__device__ __forceinline__ void part_load_group(const double *part, int n, int k0, double (&v)[kPartGroup]) {
+    if (n < 1) return;
+#pragma unroll
+    for (int u = 0; u < kPartGroup; ++u) {
+        const int k = k0 + u * B;
+        v[u] = part[k < n ? k : n - 1];
+    }
+}
+template <int B>
+__device__ __forceinline__ double part_add_group(double t, int n, int k0, const double (&v)[kPartGroup]) {
+#pragma unroll
+    for (int u = 0; u < kPartGroup; ++u)
+        if (k0 + u * B < n) t += v[u];
+    return t;
+}
+// the sum from k0 on, its earlier terms already in t
+template <int B> __device__ __forceinline__ double part_sum_from(double t, const double *part, int n, int k0) {
+    for (; k0 < n; k0 += kPartGroup * B) {
+        double v[kPartGroup];
+        part_load_group<B>(part, n, k0, v);
+        t = part_add_group<B>(t, n, k0, v);
+    }
+    return t;
+}
+template <int B> __device__ __forceinline__ double part_sum(const double *part, int n) {
+    return part_sum_from<B>(0.0, part, n, threadIdx.x);
+}
+
 }  // namespace stag

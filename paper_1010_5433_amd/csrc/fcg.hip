@@ -54,9 +54,7 @@ constexpr int kFcgBlock = 256;
 constexpr int kFcgStall = 50;
 
 __device__ __forceinline__ double fixed_sum(const double *part, int n, double *red) {
-    double t = 0.0;
-    for (int k = threadIdx.x; k < n; k += kFcgBlock) t += part[k];
-    return block_sum(t, red);
+    return block_sum(part_sum<kFcgBlock>(part, n), red);
 }
 
 // |b|^2 and the stopping threshold
