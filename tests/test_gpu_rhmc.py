@@ -196,6 +196,40 @@ def test_md_with_fermions_vs_oracle(orc, dims):
     lat.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_md_two_fields_batched_equal_one_field_doubled(prec):
+    """Several pseudo-fermion fields have their solves in one batched call
+    and one force over all their solutions; a single field goes through the
+    multi-shift solver and the force on its own.  Two copies of one field
+    must then move links and momenta as that field alone with the force's
+    rational weights doubled, since the force is linear in them."""
+    dims = (6, 4, 4, 4)
+    log(f"md: two copies of a field against one with doubled weights, {prec}")
+    U0 = syn.smooth_links(dims, 0.5, 40)
+    p = _momenta(dims, 41)
+    phi = syn.gaussian_source(dims, 42)
+    a0, al, sh = _rational()
+    kw = dict(tol_md=1e-6) if prec == "f32" else {}
+    res = []
+    for copies, alphas in ((2, al), (1, 2.0 * al)):
+        lat = lattice_with_links(dims, U0, "18p")
+        mom = to_dev(p.copy())
+        f = pack(lat, phi)
+        info = lat.md_integrate(_params(prec, rat_md=(a0, alphas, sh), **kw), mom, [f] * copies)
+        res.append((_host(lat.links_get()), _host(mom), info))
+        lat.close()
+    (U2, p2, i2), (U1, p1, i1) = res
+    du, dp = np.abs(U2 - U1).max(), np.abs(p2 - p1).max() / max(1.0, np.abs(p1).max())
+    log(f"  links {du:.2e}, momenta {dp:.2e}; MD iterations {i2['md_iters']} against 2 x {i1['md_iters']}")
+    if prec == "f64":
+        assert du <= 1e-11 and dp <= 1e-10
+    else:
+        assert du <= 1e-4 and dp <= 1e-3
+    assert i2["fermion_forces"] == i1["fermion_forces"] == 2 * 4 + 1
+    # the same systems under the same stopping rule: one iteration apart at most per solve
+    assert abs(i2["md_iters"] - 2 * i1["md_iters"]) <= 2 * i1["fermion_forces"]
+
+
 def test_md_single_precision_and_12_real_pairs_vs_oracle(orc):
     """The paper's setting (single precision momenta, gauge update and force
     solves at tol 1e-6) stays close to the double precision oracle over
