@@ -726,18 +726,29 @@ stag_status rhmc_trajectory(stag_lattice *lat, const stag_rhmc_params *prm, doub
     if (n_pf > 0) STAG_TRY(ws_get(lat, WS_MD_PHI, (size_t)n_pf * vb, &phi_buf));
     STAG_HIP(hipMemcpyAsync(bak, lat->links64, lb, hipMemcpyDeviceToDevice, s));
     // heatbath: phi_k = r_hb(M) xi_k; the fermion action at the start is |xi_k|^2
+    // (several fields: one batched application of the rational function to
+    // all of them, every link read once per up to eight fields)
     std::vector<const void *> phis(n_pf > 0 ? n_pf : 1);
+    std::vector<void *> phi_out(n_pf > 0 ? n_pf : 1);
+    for (int k = 0; k < n_pf; ++k) phis[k] = phi_out[k] = static_cast<char *>(phi_buf) + k * vb;
+    std::vector<stag_cg_stats> rst(n_pf > 0 ? n_pf : 1);
     double sf0 = 0.0;
-    for (int k = 0; k < n_pf; ++k) {
+    if (n_pf > 1) {
         TraceRange trk("heatbath");
-        void *phi = static_cast<char *>(phi_buf) + k * vb;
-        phis[k] = phi;
-        double dot = 0.0;
-        stag_cg_stats st;
-        std::memset(&st, 0, sizeof(st));
-        STAG_TRY(rational_apply(lat, prm->mass, prm->rat_hb.alpha0, prm->rat_hb.alpha, prm->rat_hb.shift,
-                                prm->rat_hb.n, xis[k], phi, prm->tol_act, prm->max_iter, &dot, &st, s));
-        info->action_iters += st.iters;
+        STAG_TRY(rational_apply_multi(lat, prm->mass, prm->rat_hb.alpha0, prm->rat_hb.alpha, prm->rat_hb.shift,
+                                      prm->rat_hb.n, xis, phi_out.data(), n_pf, prm->tol_act, prm->max_iter, nullptr,
+                                      rst.data(), s));
+        for (int k = 0; k < n_pf; ++k) info->action_iters += rst[k].iters;
+    }
+    for (int k = 0; k < n_pf; ++k) {
+        if (n_pf == 1) {
+            TraceRange trk("heatbath");
+            double dot = 0.0;
+            std::memset(&rst[0], 0, sizeof(rst[0]));
+            STAG_TRY(rational_apply(lat, prm->mass, prm->rat_hb.alpha0, prm->rat_hb.alpha, prm->rat_hb.shift,
+                                    prm->rat_hb.n, xis[k], phi_out[k], prm->tol_act, prm->max_iter, &dot, &rst[0], s));
+            info->action_iters += rst[0].iters;
+        }
         double x2 = 0.0;
         STAG_TRY(vec_norm2(lat, xis[k], &x2, s));
         sf0 += x2;
@@ -754,15 +765,26 @@ stag_status rhmc_trajectory(stag_lattice *lat, const stag_rhmc_params *prm, doub
     STAG_TRY(kinetic_energy(lat, dbl, mom, &k1, s));
     STAG_TRY(gauge_action(lat, prm->beta, &sg1, s));
     void *scratch_out = nullptr;
-    if (n_pf > 0) STAG_TRY(ws_get(lat, WS_MD_OUT, (size_t)vb, &scratch_out));
-    for (int k = 0; k < n_pf; ++k) {
+    if (n_pf > 0) STAG_TRY(ws_get(lat, WS_MD_OUT, (size_t)n_pf * vb, &scratch_out));
+    if (n_pf > 1) {
+        TraceRange trk("Metropolis action");
+        std::vector<void *> outs(n_pf);
+        for (int k = 0; k < n_pf; ++k) outs[k] = static_cast<char *>(scratch_out) + k * vb;
+        std::vector<double> dots(n_pf, 0.0);
+        STAG_TRY(rational_apply_multi(lat, prm->mass, prm->rat_act.alpha0, prm->rat_act.alpha, prm->rat_act.shift,
+                                      prm->rat_act.n, phis.data(), outs.data(), n_pf, prm->tol_act, prm->max_iter,
+                                      dots.data(), rst.data(), s));
+        for (int k = 0; k < n_pf; ++k) {
+            info->action_iters += rst[k].iters;
+            sf1 += dots[k];
+        }
+    } else if (n_pf == 1) {
         TraceRange trk("Metropolis action");
         double dot = 0.0;
-        stag_cg_stats st;
-        std::memset(&st, 0, sizeof(st));
+        std::memset(&rst[0], 0, sizeof(rst[0]));
         STAG_TRY(rational_apply(lat, prm->mass, prm->rat_act.alpha0, prm->rat_act.alpha, prm->rat_act.shift,
-                                prm->rat_act.n, phis[k], scratch_out, prm->tol_act, prm->max_iter, &dot, &st, s));
-        info->action_iters += st.iters;
+                                prm->rat_act.n, phis[0], scratch_out, prm->tol_act, prm->max_iter, &dot, &rst[0], s));
+        info->action_iters += rst[0].iters;
         sf1 += dot;
     }
     STAG_HIP(launch_mom_unpack(lat, dbl, mom, mom_canon, s));
