@@ -230,6 +230,35 @@ def test_md_two_fields_batched_equal_one_field_doubled(prec):
     assert abs(i2["md_iters"] - 2 * i1["md_iters"]) <= 2 * i1["fermion_forces"]
 
 
+def test_md_two_fields_beyond_the_batch_limit():
+    """Two fields with a 33-pole force rational have 66 solutions, more than
+    one force call takes: the molecular dynamics then solves and applies the
+    force field by field.  Two copies of a field must still move links and
+    momenta as that field alone with the force weights doubled."""
+    dims = (4, 4, 2, 4)
+    log("md: two fields with 33 poles each (field by field)")
+    U0 = syn.smooth_links(dims, 0.5, 50)
+    p = _momenta(dims, 51)
+    phi = syn.gaussian_source(dims, 52)
+    sh = np.geomspace(1e-3, 5.0, 33)
+    al = 0.02 * np.sqrt(sh)
+    res = []
+    for copies, alphas in ((2, al), (1, 2.0 * al)):
+        lat = lattice_with_links(dims, U0, "18p")
+        mom = to_dev(p.copy())
+        f = pack(lat, phi)
+        info = lat.md_integrate(_params("f64", rat_md=(0.1, alphas, sh)), mom, [f] * copies)
+        res.append((_host(lat.links_get()), _host(mom), info))
+        lat.close()
+    (U2, p2, i2), (U1, p1, i1) = res
+    du, dp = np.abs(U2 - U1).max(), np.abs(p2 - p1).max() / max(1.0, np.abs(p1).max())
+    log(f"  links {du:.2e}, momenta {dp:.2e}; MD iterations {i2['md_iters']} against 2 x {i1['md_iters']}")
+    assert du <= 1e-11 and dp <= 1e-10
+    # the same solver on the same systems: the same iterations
+    assert i2["md_iters"] == 2 * i1["md_iters"]
+    assert i2["fermion_forces"] == i1["fermion_forces"] == 2 * 4 + 1
+
+
 def test_md_single_precision_and_12_real_pairs_vs_oracle(orc):
     """The paper's setting (single precision momenta, gauge update and force
     solves at tol 1e-6) stays close to the double precision oracle over
