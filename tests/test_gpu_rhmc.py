@@ -291,11 +291,14 @@ def test_md_single_precision_and_12_real_pairs_vs_oracle(orc):
     lat.close()
 
 
-def test_trajectory_vs_oracle(orc):
+@pytest.mark.parametrize("n_fields", [1, 2])
+def test_trajectory_vs_oracle(orc, n_fields):
+    """One field: heatbath and action by the single-field rational
+    function; two fields: both fields in one batched application."""
     dims = (4, 4, 2, 4)
     U0 = syn.smooth_links(dims, 0.5, 30)
     p = _momenta(dims, 31)
-    xis = [syn.gaussian_source(dims, 40), syn.gaussian_source(dims, 41)]
+    xis = [syn.gaussian_source(dims, 40), syn.gaussian_source(dims, 41)][:n_fields]
     lat = lattice_with_links(dims, U0, "18p")
     U = _host(lat.links_get())
     mom = to_dev(p.copy())
