@@ -726,8 +726,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU decomposition is a design, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library drives a single "
+              "GPU, with no collectives between GPUs", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
