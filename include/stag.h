@@ -430,7 +430,11 @@ stag_status stag_link_update(stag_lattice *lat, const double *mom, double h, sta
  * momenta mom (both updated in place) with the n_pf pseudo-fermion fields
  * phis (HOST array of DEVICE double precision library vectors, fixed during
  * the integration), in prm->md_prec.  info (HOST, may be NULL) receives the
- * force and iteration counts.  Synchronous.  STAG_EINVAL on invalid
+ * force and iteration counts.  Several fields (the paper's multiple
+ * pseudo-fermions, Section 2) whose solutions number at most 64 in all
+ * (n_pf * prm->rat_md.n) have their solves run as one batched solve and
+ * their force as one force call per kick; otherwise field by field.  The
+ * result is the same up to rounding.  Synchronous.  STAG_EINVAL on invalid
  * parameters or links not stored as float pairs. */
 stag_status stag_md_integrate(stag_lattice *lat, const stag_rhmc_params *prm, double *mom, int n_pf,
                               const void *const *phis, stag_rhmc_info *info, void *stream);
@@ -442,7 +446,9 @@ stag_status stag_md_integrate(stag_lattice *lat, const stag_rhmc_params *prm, do
  * rejection the links return to their initial values.  mom (DEVICE (4, V,
  * 8) float64) holds the momenta drawn by the caller on entry and the final
  * momenta on exit; xis: HOST array of n_pf DEVICE double precision
- * Gaussian library vectors.  Synchronous. */
+ * Gaussian library vectors.  With several fields the heatbath and the
+ * action apply their rational function to all fields in one batched call.
+ * Synchronous. */
 stag_status stag_rhmc_trajectory(stag_lattice *lat, const stag_rhmc_params *prm, double *mom, int n_pf,
                                  const void *const *xis, double u, stag_rhmc_info *info, void *stream);
 
